@@ -1,0 +1,357 @@
+"""Fast directional matrix-vector multiplication (Sect. 2.6, Alg. 4).  Oracle.
+
+``build`` assembles what Alg. 4 takes as input: the two box cluster trees
+(Alg. 1), the block tree (Alg. 2), the direction sets (Alg. 3) and the active
+and inherited directions ``D(t), D^(t), D(s), D^(s)`` (Sect. 2.6).  ``matvec``
+then runs Alg. 4 in the paper's order, in FP64 / complex128:
+
+1. ``g = 0``;
+2. S2M: ``v~_{s,c} = L_{s,c}^* v|_s`` for leaves ``s``, ``c in D(s) u D^(s)``;
+3. M2M, levels ``p-1 .. 0``: ``v~_{s,c} = sum_{s'} E_{s',c}^* v~_{s',c'}``,
+   ``c' = dir_(l+1)(c)``;
+4. M2L: ``g~_{t,c} += A_{c,t x s} v~_{s,c}`` over admissible leaves;
+5. L2L, levels ``0 .. p-1``: ``g~_{t',c'} += E_{t',c} g~_{t,c}``;
+6. L2T: ``g|_t += L_{t,c} g~_{t,c}`` for leaves ``t``;
+7. near field: ``g|_t += A|_{t x s} v|_s`` over inadmissible leaves.
+
+Steps use the paper's absolute plane-wave factors ``exp(i kappa <x, c>)``
+(eq. of ``L_{t,c,nu}``) and the transfer matrices of Sect. 2.5.  Blocks of
+step 4 that share a level and an offset are applied as one matrix product
+(Sect. 2.7 stores their coupling matrix once); this only changes the order
+of the sums.
+
+``sample_rows`` runs the same algorithm for a few target rows: the block tree
+is restricted to the ancestors of those rows' leaves (so only the moments they
+need are formed), and L2T / near field are evaluated at those rows only.
+"""
+from __future__ import annotations
+
+import time
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from .tree import BoxTree, build_box_tree
+from .partition import ETA2, BlockTree, block_tree
+from .directions import DirectionSets, active_directions, high_frequency_level
+from .interpolation import (coupling_matrix, directional_part, helmholtz,
+                            interpolation_rows, transfer_reference)
+
+
+@dataclass
+class Plan:
+    TT: BoxTree
+    TS: BoxTree
+    BT: BlockTree
+    dirs: DirectionSets
+    kappa: float
+    m: int
+    l_hf: int
+    eta2: float
+    DT: list
+    DhT: list
+    DS: list
+    DhS: list
+    cdir: list
+    rows: np.ndarray | None = None  # sampled target rows (user indices)
+    timings: dict = field(default_factory=dict)
+    debug: dict = field(default_factory=dict)
+
+    @property
+    def levels(self) -> int:
+        return self.TT.levels
+
+    @property
+    def K(self) -> int:
+        return (self.m + 1) ** 3
+
+    def side(self, level: int) -> np.ndarray:
+        return self.TT.side(level)
+
+
+def _validate(box, kappa, levels, m):
+    lo = np.asarray(box[:3], dtype=np.float64)
+    hi = np.asarray(box[3:], dtype=np.float64)
+    if not (np.all(np.isfinite(lo)) and np.all(np.isfinite(hi)) and
+            np.all(hi > lo)):
+        raise ValueError("invalid root box")
+    side = hi - lo
+    if not (side[0] == side[1] == side[2]):
+        raise ValueError("root box must be a cube")
+    if not (np.isfinite(kappa) and kappa >= 0):
+        raise ValueError("kappa must be finite and >= 0")
+    if not (0 <= levels <= 10):
+        raise ValueError("levels must be in [0, 10]")
+    if not (1 <= m <= 8):
+        raise ValueError("m must be in [1, 8]")
+    return float(side[0])
+
+
+def build(points_T, points_S, kappa, box, levels, m, l_hf=None,
+          eta2=ETA2, rows=None) -> Plan:
+    side = _validate(box, kappa, levels, m)
+    TT = build_box_tree(points_T, box, levels)
+    TS = build_box_tree(points_S, box, levels)
+    if l_hf is None:
+        l_hf = high_frequency_level(kappa, side, levels)
+    dirs = DirectionSets(l_hf, levels)
+    filt = None
+    if rows is not None:
+        rows = np.asarray(rows, dtype=np.int64)
+        inv = np.empty(TT.n, dtype=np.int64)
+        inv[TT.perm] = np.arange(TT.n)
+        leaf = TT.leaf_of_slot()[inv[rows]]
+        filt = [None] * (levels + 1)
+        box_idx = leaf
+        for level in range(levels, -1, -1):
+            mask = np.zeros(TT.keys[level].shape[0], dtype=bool)
+            mask[box_idx] = True
+            filt[level] = mask
+            if level > 0:
+                box_idx = TT.parent[level][box_idx]
+    BT = block_tree(TT, TS, kappa, eta2, filt)
+    DT, DhT, DS, DhS, cdir = active_directions(TT, TS, BT, dirs, side)
+    return Plan(TT, TS, BT, dirs, float(kappa), m, l_hf, eta2,
+                DT, DhT, DS, DhS, cdir, rows)
+
+
+def _segments(start, count):
+    """Tree slots of boxes given their ranges, plus each slot's box."""
+    total = int(count.sum())
+    box = np.repeat(np.arange(start.shape[0]), count)
+    first = np.concatenate(([0], np.cumsum(count)[:-1]))
+    slots = np.repeat(start, count) + (np.arange(total) - np.repeat(first, count))
+    return slots, box
+
+
+def _chunks(counts, limit):
+    """Split consecutive boxes into chunks of at most ~limit points."""
+    out, acc, begin = [], 0, 0
+    for i, c in enumerate(counts):
+        if acc + c > limit and i > begin:
+            out.append((begin, i))
+            begin, acc = i, 0
+        acc += int(c)
+    if begin < len(counts):
+        out.append((begin, len(counts)))
+    return out
+
+
+def matvec(plan: Plan, v, chunk_points: int = 65536, keep: bool = False) -> np.ndarray:
+    """Alg. 4: ``g ~= A v`` in the user's target order (complex128)."""
+    t0 = time.perf_counter()
+    TT, TS, BT, dirs = plan.TT, plan.TS, plan.BT, plan.dirs
+    p, m, K, kappa = plan.levels, plan.m, plan.K, plan.kappa
+    v = np.asarray(v, dtype=np.complex128).reshape(-1)
+    if v.shape[0] != TS.n:
+        raise ValueError("v has the wrong length")
+    g_tree = np.zeros(TT.n, dtype=np.complex128)
+    if TT.n == 0 or TS.n == 0:
+        return np.zeros(TT.n, dtype=np.complex128) if plan.rows is None \
+            else np.zeros(plan.rows.shape[0], dtype=np.complex128)
+    vt = v[TS.perm]
+    Eref = transfer_reference(m)
+
+    # --- S2M (leaves of T_S) ----------------------------------------------
+    mom = [None] * (p + 1)
+    need = plan.DS[p] | plan.DhS[p]
+    mom[p] = np.zeros(need.shape + (K,), dtype=np.complex128)
+    cvec = dirs.vectors(p)
+    for c in range(need.shape[1]):
+        leaves = np.flatnonzero(need[:, c])
+        for a, b in _chunks(TS.count[p][leaves], chunk_points):
+            lv = leaves[a:b]
+            slots, owner = _segments(TS.start[p][lv], TS.count[p][lv])
+            y = TS.points[slots]
+            L = interpolation_rows(y, TS.lo[p][lv][owner], TS.hi[p][lv][owner], m)
+            # conj(L_{s,c}) rows times v: L_{s,nu}(y) exp(-i kappa <y,c>) v
+            w = np.exp(-1j * kappa * (y @ cvec[c])) * vt[slots]
+            contrib = L * w[:, None]
+            seg = np.concatenate(([0], np.cumsum(TS.count[p][lv])[:-1]))
+            mom[p][lv, c] = np.add.reduceat(contrib, seg, axis=0)
+    plan.timings["s2m"] = time.perf_counter() - t0
+
+    # --- M2M (levels p-1 .. 0) ---------------------------------------------
+    t1 = time.perf_counter()
+    for level in range(p - 1, -1, -1):
+        need = plan.DS[level] | plan.DhS[level]
+        mom[level] = np.zeros(need.shape + (K,), dtype=np.complex128)
+        if not need.any():
+            continue
+        par_dir = dirs.parent_index(level)
+        cv, cv1 = dirs.vectors(level), dirs.vectors(level + 1)
+        for c in range(need.shape[1]):
+            parents = np.flatnonzero(need[:, c])
+            if parents.size == 0:
+                continue
+            ch, owner = _segments(TS.child_start[level][parents],
+                                  TS.child_count[level][parents])
+            cp = par_dir[c]
+            Ed = directional_part(TS.lo[level + 1][ch], TS.hi[level + 1][ch],
+                                  m, kappa, cv[c], cv1[cp])
+            w = np.conj(Ed) * mom[level + 1][ch, cp]  # (E^d)^* v~_{s',c'}
+            octant = TS.keys[level + 1][ch] & 7
+            contrib = np.empty_like(w)
+            for q in range(8):
+                sel = octant == q
+                if sel.any():
+                    contrib[sel] = w[sel] @ Eref[q]  # rows of E_{s'}^T w
+            seg = np.concatenate(([0], np.cumsum(TS.child_count[level][parents])[:-1]))
+            mom[level][parents, c] = np.add.reduceat(contrib, seg, axis=0)
+    plan.timings["m2m"] = time.perf_counter() - t1
+
+    # --- M2L ----------------------------------------------------------------
+    t2 = time.perf_counter()
+    loc = [np.zeros((plan.DT[l] | plan.DhT[l]).shape + (K,), dtype=np.complex128)
+           for l in range(p + 1)]
+    for level in range(p + 1):
+        t, s = BT.adm_t[level], BT.adm_s[level]
+        if t.size == 0:
+            continue
+        o = TT.coords[level][t] - TS.coords[level][s]
+        c = plan.cdir[level]
+        cv = dirs.vectors(level)
+        h = plan.side(level)
+        uo, inv = np.unique(o, axis=0, return_inverse=True)
+        inv = inv.reshape(-1)
+        order = np.argsort(inv, kind="stable")
+        bounds = np.concatenate(([0], np.cumsum(np.bincount(inv, minlength=uo.shape[0]))))
+        for gi in range(uo.shape[0]):
+            idx = order[bounds[gi]:bounds[gi + 1]]
+            cg = c[idx[0]]
+            A = coupling_matrix(m, h, uo[gi], kappa, cv[cg])
+            loc[level][t[idx], cg] += mom[level][s[idx], cg] @ A.T
+    plan.timings["m2l"] = time.perf_counter() - t2
+
+    # --- L2L (levels 0 .. p-1) ---------------------------------------------
+    t3 = time.perf_counter()
+    for level in range(p):
+        need = plan.DT[level] | plan.DhT[level]
+        if not need.any():
+            continue
+        par_dir = dirs.parent_index(level)
+        cv, cv1 = dirs.vectors(level), dirs.vectors(level + 1)
+        for c in range(need.shape[1]):
+            parents = np.flatnonzero(need[:, c])
+            if parents.size == 0:
+                continue
+            ch, owner = _segments(TT.child_start[level][parents],
+                                  TT.child_count[level][parents])
+            cp = par_dir[c]
+            gpar = loc[level][parents[owner], c]
+            octant = TT.keys[level + 1][ch] & 7
+            Eg = np.empty_like(gpar)
+            for q in range(8):
+                sel = octant == q
+                if sel.any():
+                    Eg[sel] = gpar[sel] @ Eref[q].T  # rows of E_{t'} g
+            Ed = directional_part(TT.lo[level + 1][ch], TT.hi[level + 1][ch],
+                                  m, kappa, cv[c], cv1[cp])
+            loc[level + 1][ch, cp] += Ed * Eg
+    plan.timings["l2l"] = time.perf_counter() - t3
+
+    # --- L2T (leaves of T_T) -----------------------------------------------
+    t4 = time.perf_counter()
+    if plan.rows is not None:
+        inv = np.empty(TT.n, dtype=np.int64)
+        inv[TT.perm] = np.arange(TT.n)
+        want = np.zeros(TT.n, dtype=bool)
+        want[inv[plan.rows]] = True
+    need = plan.DT[p] | plan.DhT[p]
+    cvec = dirs.vectors(p)
+    for c in range(need.shape[1]):
+        leaves = np.flatnonzero(need[:, c])
+        for a, b in _chunks(TT.count[p][leaves], chunk_points):
+            lv = leaves[a:b]
+            slots, owner = _segments(TT.start[p][lv], TT.count[p][lv])
+            if plan.rows is not None:
+                sel = want[slots]
+                slots, owner = slots[sel], owner[sel]
+            x = TT.points[slots]
+            L = interpolation_rows(x, TT.lo[p][lv][owner], TT.hi[p][lv][owner], m)
+            ph = np.exp(1j * kappa * (x @ cvec[c]))
+            g_tree[slots] += ph * np.einsum("nk,nk->n", L, loc[p][lv[owner], c])
+    plan.timings["l2t"] = time.perf_counter() - t4
+
+    # --- near field -----------------------------------------------------------
+    t5 = time.perf_counter()
+    nt, ns = BT.near_t[p], BT.near_s[p]
+    if nt.size:
+        tslots, towner = _segments(TT.start[p][nt], TT.count[p][nt])
+        if plan.rows is not None:
+            sel = want[tslots]
+            tslots, towner = tslots[sel], towner[sel]
+        # every target slot meets every source slot of its pair's source box
+        srcs = ns[towner]
+        cnt = TS.count[p][srcs]
+        for a, b in _chunks(cnt, 4 * chunk_points):
+            ts = tslots[a:b]
+            sl, own = _segments(TS.start[p][srcs[a:b]], cnt[a:b])
+            tj = ts[own]
+            d = TT.points[tj] - TS.points[sl]
+            # f(x, y) = 0 exactly when the two points coincide (diagonal)
+            same = np.all(TT.points[tj] == TS.points[sl], axis=1)
+            r = np.sqrt(np.sum(d * d, axis=1))
+            r[same] = 0.0
+            np.add.at(g_tree, tj, helmholtz(r, kappa) * vt[sl])
+    plan.timings["near"] = time.perf_counter() - t5
+    plan.timings["total"] = time.perf_counter() - t0
+    if keep:  # intermediate moments and locals (absolute phase form)
+        plan.debug = {"mom": mom, "loc": loc}
+
+    g = np.zeros(TT.n, dtype=np.complex128)
+    g[TT.perm] = g_tree
+    if plan.rows is not None:
+        return g[plan.rows]
+    return g
+
+
+def sample_rows(points_T, points_S, v, kappa, box, levels, m, rows,
+                l_hf=None, eta2=ETA2) -> np.ndarray:
+    """Alg. 4 evaluated at the given target rows only (user indices)."""
+    plan = build(points_T, points_S, kappa, box, levels, m, l_hf, eta2, rows)
+    return matvec(plan, v)
+
+
+def structure(plan: Plan) -> dict:
+    """Canonical integer description of the plan, for structure parity.
+
+    Keys: ``perm_T``/``perm_S``; per level ``keys_T{l}``, ``start_T{l}``,
+    ``count_T{l}`` (and ``_S``); ``l_hf``; per level the number of admissible
+    blocks ``nc{l}``, the distinct offsets they use ``off{l}`` (sorted, (n,3))
+    with their direction index ``offdir{l}`` and use count ``offcnt{l}``;
+    ``near_pairs`` and ``near_entries`` (sum of ``#t * #s`` over inadmissible
+    leaves); per level the active / inherited direction sets as sorted
+    ``box * ndir + dir`` codes ``D_T{l}``, ``Dh_T{l}``, ``D_S{l}``, ``Dh_S{l}``.
+    """
+    out = {"perm_T": plan.TT.perm, "perm_S": plan.TS.perm,
+           "l_hf": np.array([plan.l_hf])}
+    p = plan.levels
+    for tag, T in (("T", plan.TT), ("S", plan.TS)):
+        for l in range(p + 1):
+            out[f"keys_{tag}{l}"] = T.keys[l]
+            out[f"start_{tag}{l}"] = T.start[l]
+            out[f"count_{tag}{l}"] = T.count[l]
+    for l in range(p + 1):
+        t, s = plan.BT.adm_t[l], plan.BT.adm_s[l]
+        out[f"nc{l}"] = np.array([t.shape[0]])
+        if t.size:
+            o = plan.TT.coords[l][t] - plan.TS.coords[l][s]
+            uo, first, cnt = np.unique(o, axis=0, return_index=True,
+                                       return_counts=True)
+            out[f"off{l}"] = uo
+            out[f"offdir{l}"] = plan.cdir[l][first]
+            out[f"offcnt{l}"] = cnt
+        else:
+            out[f"off{l}"] = np.zeros((0, 3), dtype=np.int64)
+            out[f"offdir{l}"] = np.zeros(0, dtype=np.int64)
+            out[f"offcnt{l}"] = np.zeros(0, dtype=np.int64)
+        for tag, D in (("D_T", plan.DT), ("Dh_T", plan.DhT), ("D_S", plan.DS),
+                       ("Dh_S", plan.DhS)):
+            b, c = np.nonzero(D[l])
+            out[f"{tag}{l}"] = np.sort(b * D[l].shape[1] + c)
+    nt, ns = plan.BT.near_t[p], plan.BT.near_s[p]
+    out["near_pairs"] = np.array([nt.shape[0]])
+    out["near_entries"] = np.array([int(np.sum(plan.TT.count[p][nt] *
+                                               plan.TS.count[p][ns]))])
+    return out
