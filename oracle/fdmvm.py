@@ -31,6 +31,7 @@ from dataclasses import dataclass, field
 
 import numpy as np
 
+from . import emulate
 from .tree import BoxTree, build_box_tree
 from .partition import ETA2, BlockTree, block_tree
 from .directions import DirectionSets, active_directions, high_frequency_level
@@ -137,8 +138,13 @@ def _chunks(counts, limit):
     return out
 
 
-def matvec(plan: Plan, v, chunk_points: int = 65536, keep: bool = False) -> np.ndarray:
-    """Alg. 4: ``g ~= A v`` in the user's target order (complex128)."""
+def matvec(plan: Plan, v, chunk_points: int = 65536, keep: bool = False,
+           m2l: str = "fp64") -> np.ndarray:
+    """Alg. 4: ``g ~= A v`` in the user's target order (complex128).
+
+    ``m2l`` other than ``"fp64"`` emulates a reduced-precision coupling step
+    (see ``oracle.emulate``); the default is the plain FP64 algorithm.
+    """
     t0 = time.perf_counter()
     TT, TS, BT, dirs = plan.TT, plan.TS, plan.BT, plan.dirs
     p, m, K, kappa = plan.levels, plan.m, plan.K, plan.kappa
@@ -202,7 +208,8 @@ def matvec(plan: Plan, v, chunk_points: int = 65536, keep: bool = False) -> np.n
 
     # --- M2L ----------------------------------------------------------------
     t2 = time.perf_counter()
-    loc = [np.zeros((plan.DT[l] | plan.DhT[l]).shape + (K,), dtype=np.complex128)
+    acc_dtype = emulate.accumulate_dtype(m2l)
+    loc = [np.zeros((plan.DT[l] | plan.DhT[l]).shape + (K,), dtype=acc_dtype)
            for l in range(p + 1)]
     for level in range(p + 1):
         t, s = BT.adm_t[level], BT.adm_s[level]
@@ -220,7 +227,8 @@ def matvec(plan: Plan, v, chunk_points: int = 65536, keep: bool = False) -> np.n
             idx = order[bounds[gi]:bounds[gi + 1]]
             cg = c[idx[0]]
             A = coupling_matrix(m, h, uo[gi], kappa, cv[cg])
-            loc[level][t[idx], cg] += mom[level][s[idx], cg] @ A.T
+            loc[level][t[idx], cg] += emulate.product(A, mom[level][s[idx], cg], m2l)
+    loc = [x.astype(np.complex128) for x in loc]
     plan.timings["m2l"] = time.perf_counter() - t2
 
     # --- L2L (levels 0 .. p-1) ---------------------------------------------

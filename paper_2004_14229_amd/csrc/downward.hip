@@ -1,0 +1,200 @@
+// Backward transformation of Alg. 4 (Sect. 2.6) in the centre-relative
+// phase form:
+//
+//   L2L  g~_{t',c'} = G_{t',c'} + sum_{c : dir_(l+1)(c) = c'} E~d_{t',c} .* (E_{t'} g~_{t,c})
+//   L2T  y_j = sum_c sum_nu L_{t,nu}(x_j) exp(i kappa <x_j - m_t, c>) g~_{t,c}[nu]
+//
+// with G the coupling (M2L) result of the box and E~d as in the forward
+// transformation.  One workgroup owns one (box, direction) local, so every
+// local is written exactly once per level, with a fixed order of the sums.
+#include "plan.hpp"
+#include "device_math.hpp"
+
+namespace fdm {
+
+namespace {
+
+template <class GT>
+__device__ __forceinline__ double2 load_c(const GT* p, int64_t i);
+template <>
+__device__ __forceinline__ double2 load_c<double2>(const double2* p, int64_t i) {
+  return p[i];
+}
+template <>
+__device__ __forceinline__ double2 load_c<float2>(const float2* p, int64_t i) {
+  float2 v = p[i];
+  return make_double2(v.x, v.y);
+}
+
+// One workgroup (64 threads) per (child box t' on level l+1, direction c').
+template <class GT>
+__global__ void __launch_bounds__(64) k_l2l(
+    const double2* __restrict__ ploc, int nd, const int32_t* __restrict__ pgrid,
+    const uint32_t* __restrict__ key1, int64_t nb1, int level, double h1,
+    const double* __restrict__ dirvec, const double* __restrict__ dirvec1, int nd1,
+    int l_hf, double kappa, Interp ip, const GT* g_m2l,
+    double2* loc1) {  // g_m2l may alias loc1 (read before write, same thread)
+  __shared__ double2 buf[2][kMaxK];
+  __shared__ double2 ph[3][kMaxM1];
+  const int lane = threadIdx.x;
+  const int cp = blockIdx.y;  // c' on level l+1
+  const int m1 = ip.m1, K = ip.K, Kp = ip.Kp;
+  // parent directions c with dir_(l+1)(c) = c'
+  const bool hf_child = level + 1 <= l_hf;
+  const int c_begin = hf_child ? 4 * cp : 0;
+  const int c_end = hf_child ? 4 * cp + 4 : nd;
+  const double cv1[3] = {dirvec1[3 * cp], dirvec1[3 * cp + 1], dirvec1[3 * cp + 2]};
+  for (int64_t b = blockIdx.x; b < nb1; b += gridDim.x) {
+    const uint32_t k1 = key1[b];
+    const int32_t par = pgrid[k1 >> 3];
+    const int q = k1 & 7;
+    const int bq[3] = {(q >> 2) & 1, (q >> 1) & 1, q & 1};
+    double2 acc[kPerLane];
+    const int64_t obase = (b * nd1 + cp) * int64_t(Kp);
+#pragma unroll
+    for (int i = 0; i < kPerLane; ++i) {
+      const int k = lane + 64 * i;
+      acc[i] = k < K ? load_c(g_m2l, obase + k) : make_double2(0.0, 0.0);
+    }
+    for (int c = c_begin; c < c_end; ++c) {
+      const double cv[3] = {dirvec[3 * c], dirvec[3 * c + 1], dirvec[3 * c + 2]};
+      __syncthreads();
+      if (lane < 3 * m1) {
+        const int d = lane / m1, nu = lane % m1;
+        const double r = 0.5 * h1 * ip.node[nu];  // xi - m_{t'}
+        const double off = (bq[d] - 0.5) * h1;    // m_{t'} - m_t
+        double sn, cs;
+        phase_sincos(kappa * ((r + off) * cv[d] - r * cv1[d]), sn, cs);
+        ph[d][nu] = make_double2(cs, sn);
+      }
+      const double2* src = ploc + (int64_t(par) * nd + c) * Kp;
+      for (int k = lane; k < K; k += 64) buf[0][k] = src[k];
+      __syncthreads();
+      apply_transfer(buf, ip, bq, false, lane, 64);  // buf[1] = E_{t'} g
+#pragma unroll
+      for (int i = 0; i < kPerLane; ++i) {
+        const int k = lane + 64 * i;
+        if (k < K) {
+          const int n3 = k % m1, n2 = (k / m1) % m1, n1 = k / (m1 * m1);
+          const double2 f = cmul(cmul(ph[0][n1], ph[1][n2]), ph[2][n3]);
+          const double2 v = cmul(f, buf[1][k]);
+          acc[i].x += v.x;
+          acc[i].y += v.y;
+        }
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < kPerLane + 1; ++i) {
+      const int k = lane + 64 * i;
+      if (k < Kp) loc1[obase + k] = (k < K && i < kPerLane) ? acc[i < kPerLane ? i : 0]
+                                                           : make_double2(0.0, 0.0);
+    }
+  }
+}
+
+// One wave per leaf box: every point of the box, every direction.
+__global__ void __launch_bounds__(64) k_l2t(
+    const double* __restrict__ x, const double* __restrict__ y,
+    const double* __restrict__ z, const uint32_t* __restrict__ key,
+    const int32_t* __restrict__ start, const int32_t* __restrict__ count, int64_t nb,
+    int level, double lo0, double lo1, double lo2, double h,
+    const double* __restrict__ dirvec, int nd, double kappa, Interp ip,
+    const double2* __restrict__ loc, double2* __restrict__ y_tree) {
+  __shared__ double lag[3][kMaxM1];
+  const int lane = threadIdx.x;
+  const int m1 = ip.m1, K = ip.K, Kp = ip.Kp;
+  for (int64_t b = blockIdx.x; b < nb; b += gridDim.x) {
+    int ix, iy, iz;
+    demorton3(key[b], level, ix, iy, iz);
+    const double mx = lo0 + (ix + 0.5) * h, my = lo1 + (iy + 0.5) * h,
+                 mz = lo2 + (iz + 0.5) * h;
+    const double inv_half = 2.0 / h;
+    const int p0 = start[b], pn = count[b];
+    for (int pi = 0; pi < pn; ++pi) {
+      const int64_t j = p0 + pi;
+      const double dx = x[j] - mx, dy = y[j] - my, dz = z[j] - mz;
+      __syncthreads();
+      if (lane < 3 * m1) {
+        const int d = lane / m1, nu = lane % m1;
+        const double u = (d == 0 ? dx : d == 1 ? dy : dz) * inv_half;
+        lag[d][nu] = lagrange1d(ip, nu, u);
+      }
+      __syncthreads();
+      double yr = 0.0, yi = 0.0;
+      for (int c = 0; c < nd; ++c) {
+        const double2* g = loc + (b * nd + c) * int64_t(Kp);
+        double sr = 0.0, si = 0.0;
+#pragma unroll
+        for (int i = 0; i < kPerLane; ++i) {
+          const int k = lane + 64 * i;
+          if (k < K) {
+            const int n3 = k % m1, n2 = (k / m1) % m1, n1 = k / (m1 * m1);
+            const double L = lag[0][n1] * lag[1][n2] * lag[2][n3];
+            const double2 gv = g[k];
+            sr += L * gv.x;
+            si += L * gv.y;
+          }
+        }
+        for (int off = 32; off > 0; off >>= 1) {
+          sr += __shfl_xor(sr, off, 64);
+          si += __shfl_xor(si, off, 64);
+        }
+        const double cx = dirvec[3 * c], cy = dirvec[3 * c + 1], cz = dirvec[3 * c + 2];
+        double sn, cs;
+        phase_sincos(kappa * (dx * cx + dy * cy + dz * cz), sn, cs);
+        yr += cs * sr - sn * si;
+        yi += cs * si + sn * sr;
+      }
+      if (lane == 0) y_tree[j] = make_double2(yr, yi);
+    }
+  }
+}
+
+__global__ void k_zero_c128(double2* p, int64_t n) {
+  for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < n;
+       i += int64_t(gridDim.x) * blockDim.x)
+    p[i] = make_double2(0.0, 0.0);
+}
+
+}  // namespace
+
+void launch_zero_c128(double* p, int64_t n, hipStream_t s) {
+  if (n == 0) return;
+  k_zero_c128<<<grid_for(n, 256), 256, 0, s>>>(reinterpret_cast<double2*>(p), n);
+  FDM_LAUNCH("k_zero_c128");
+}
+
+void launch_l2l(Plan& P, int level, hipStream_t s) {
+  LevelData& Lc = P.L[level];
+  LevelData& L1 = P.L[level + 1];
+  const int64_t nb1 = P.T.nb[level + 1];
+  if (nb1 == 0) return;
+  dim3 grid(static_cast<unsigned>(std::min<int64_t>(nb1, 1 << 20)), L1.nd);
+  k_l2l<double2><<<grid, 64, 0, s>>>(
+      reinterpret_cast<const double2*>(Lc.loc64.get()), Lc.nd, P.T.grid[level].get(),
+      P.T.key[level + 1].get(), nb1, level, L1.h, Lc.dirvec.get(), L1.dirvec.get(),
+      L1.nd, P.l_hf, P.kappa, P.ip, reinterpret_cast<const double2*>(L1.loc64.get()),
+      reinterpret_cast<double2*>(L1.loc64.get()));
+  FDM_LAUNCH("k_l2l");
+}
+
+void launch_l2t(Plan& P, hipStream_t s) {
+  const int p = P.levels;
+  const int64_t nb = P.T.nb[p];
+  if (P.nT == 0) return;
+  if (P.l_min > p || nb == 0) {  // no coupling anywhere: the far field is zero
+    k_zero_c128<<<grid_for(P.nT, 256), 256, 0, s>>>(
+        reinterpret_cast<double2*>(P.y_tree.get()), P.nT);
+    FDM_LAUNCH("k_zero_c128");
+    return;
+  }
+  LevelData& Lp = P.L[p];
+  k_l2t<<<static_cast<unsigned>(std::min<int64_t>(nb, 1 << 20)), 64, 0, s>>>(
+      P.T.x.get(), P.T.y.get(), P.T.z.get(), P.T.key[p].get(), P.T.start[p].get(),
+      P.T.count[p].get(), nb, p, P.lo[0], P.lo[1], P.lo[2], Lp.h, Lp.dirvec.get(), Lp.nd,
+      P.kappa, P.ip, reinterpret_cast<const double2*>(Lp.loc64.get()),
+      reinterpret_cast<double2*>(P.y_tree.get()));
+  FDM_LAUNCH("k_l2t");
+}
+
+}  // namespace fdm

@@ -1,0 +1,525 @@
+// Coupling step of Alg. 4 (Sect. 2.6, M2L): g~_{t,c} = sum_s A~_{c,t x s} v~_{s,c}
+// over the admissible blocks, on the matrix cores.
+//
+// Bank (Sect. 2.7): the coupling matrix of a block depends only on its level
+// and offset o = i_t - i_s, so one K x K complex matrix is stored per
+// admissible (level, offset):
+//   A~[j,k] = f(xi_{t,j}, xi_{s,k}) exp(-i kappa <(xi_{t,j}-m_t) - (xi_{s,k}-m_s), c>)
+// (the paper's f_c with the plane-wave factors of the box centres moved into
+// the moments and locals), evaluated in FP64 and stored as split re/im
+// planes, transposed (k-major) so that a wave's rows of one k are contiguous.
+//
+// Product: one workgroup owns a block of up to 64 target boxes of one level,
+// one octant (so they share the list of admissible offsets) and one
+// direction c.  It loops over that list's offsets that hit at least one
+// non-empty source box, gathers the 64 source moment columns t - o (zero for
+// missing boxes) through LDS and accumulates A~_o * M on the MFMA units in
+// registers; the result of each (target, c) is written once.  Complex
+// products use four real products: Re += Ar Br - Ai Bi, Im += Ar Bi + Ai Br.
+// Wave w owns rows 32w .. 32w+31 of the (padded) K rows.
+#include <algorithm>
+#include <numeric>
+
+#include "plan.hpp"
+#include "device_math.hpp"
+
+namespace fdm {
+
+namespace {
+
+typedef float f16v __attribute__((ext_vector_type(16)));
+typedef double d4v __attribute__((ext_vector_type(4)));
+
+struct BankLevel {
+  double h;
+  int level;
+  int nd;
+  const double* dirvec;
+};
+
+// Coupling matrices in the layout of the plan precision.
+template <class T>
+__global__ void k_bank(const int32_t* __restrict__ info,  // per matrix: level, ox, oy, oz, c
+                       int64_t n_mat, const BankLevel* __restrict__ lv, double kappa,
+                       Interp ip, T* __restrict__ bank) {
+  const int Kp = ip.Kp, K = ip.K, m1 = ip.m1;
+  const int64_t per = int64_t(Kp) * Kp;
+  const int64_t total = n_mat * per;
+  for (int64_t e = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; e < total;
+       e += int64_t(gridDim.x) * blockDim.x) {
+    const int64_t id = e / per;
+    const int64_t r = e % per;
+    const int kk = static_cast<int>(r / Kp);   // source node (column of A)
+    const int row = static_cast<int>(r % Kp);  // target node (row of A)
+    double re = 0.0, im = 0.0;
+    if (row < K && kk < K) {
+      const int32_t* in = info + 5 * id;
+      const BankLevel L = lv[in[0]];
+      const int o[3] = {in[1], in[2], in[3]};
+      const int c = in[4];
+      const int a[3] = {row / (m1 * m1), (row / m1) % m1, row % m1};
+      const int b[3] = {kk / (m1 * m1), (kk / m1) % m1, kk % m1};
+      double d[3], rel[3];
+      for (int q = 0; q < 3; ++q) {
+        rel[q] = 0.5 * L.h * (ip.node[a[q]] - ip.node[b[q]]);
+        d[q] = L.h * o[q] + rel[q];
+      }
+      const double rr = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+      const double* cv = L.dirvec + 3 * c;
+      const double arg = kappa * rr - kappa * (rel[0] * cv[0] + rel[1] * cv[1] + rel[2] * cv[2]);
+      double sn, cs;
+      phase_sincos(arg, sn, cs);
+      const double w = 1.0 / (4.0 * M_PI * rr);
+      re = cs * w;
+      im = sn * w;
+    }
+    T* base = bank + id * 2 * per;
+    base[int64_t(kk) * Kp + row] = static_cast<T>(re);
+    base[per + int64_t(kk) * Kp + row] = static_cast<T>(im);
+  }
+}
+
+// Shared prologue: the block's target boxes and their integer positions.
+struct TargetTile {
+  int32_t t[kNB];
+  int32_t x[kNB], y[kNB], z[kNB];
+  int64_t col[kNB];  // first moment element of the source column, or -1
+};
+
+__device__ __forceinline__ void load_targets(TargetTile& S, const M2LItem& it,
+                                             const M2LLevel& L,
+                                             const int32_t* __restrict__ tgt_list) {
+  for (int j = threadIdx.x; j < kNB; j += blockDim.x) {
+    int32_t t = j < it.ntgt ? tgt_list[it.tgt_begin + j] : -1;
+    S.t[j] = t;
+    int ix = 0, iy = 0, iz = 0;
+    if (t >= 0) demorton3(L.keyT[t], L.level, ix, iy, iz);
+    S.x[j] = ix;
+    S.y[j] = iy;
+    S.z[j] = iz;
+  }
+}
+
+__device__ __forceinline__ void source_columns(TargetTile& S, const M2LLevel& L,
+                                               int4 od, int c, int Kp) {
+  const int lim = 1 << L.level;
+  for (int j = threadIdx.x; j < kNB; j += blockDim.x) {
+    int64_t col = -1;
+    if (S.t[j] >= 0) {
+      const int sx = S.x[j] - od.x, sy = S.y[j] - od.y, sz = S.z[j] - od.z;
+      if (sx >= 0 && sy >= 0 && sz >= 0 && sx < lim && sy < lim && sz < lim) {
+        const int32_t sb = L.gridS[morton3(sx, sy, sz, L.level)];
+        if (sb >= 0) col = (int64_t(sb) * L.nd + c) * Kp;
+      }
+    }
+    S.col[j] = col;
+  }
+}
+
+// ---------------------------------------------------------------- FP32 --
+// Each offset's product is summed in its own MFMA accumulator (rounding
+// relative to that product), added to an FP32 total, and every kFlush
+// offsets the total is added to the FP64 result in memory, which this
+// workgroup alone owns.
+constexpr int kKS32 = 16;  // k slab
+constexpr int kFlush = 16;
+
+template <int NCS>
+__device__ __forceinline__ void flush_f32(const f16v (&totr)[NCS], const f16v (&toti)[NCS],
+                                          const TargetTile& S, double2* out, int nd, int c,
+                                          int Kp, int wave, int lane, bool first) {
+#pragma unroll
+  for (int cs = 0; cs < NCS; ++cs) {
+    const int32_t t = S.t[32 * cs + (lane % 32)];
+    if (t < 0) continue;
+    double2* dst = out + (int64_t(t) * nd + c) * Kp;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      const int r = 32 * wave + 8 * (i / 4) + 4 * (lane / 32) + (i % 4);
+      double2 v = make_double2(totr[cs][i], toti[cs][i]);
+      if (!first) {
+        const double2 o = dst[r];
+        v.x += o.x;
+        v.y += o.y;
+      }
+      dst[r] = v;
+    }
+  }
+}
+
+__global__ void __launch_bounds__(kM2LMaxThreads) k_m2l_f32(
+    const M2LItem* __restrict__ items, const M2LLevel* __restrict__ lv,
+    const int32_t* __restrict__ tgt_list, const int32_t* __restrict__ valid_off,
+    const int4* __restrict__ offtab, const float* __restrict__ bank, int Kp) {
+  constexpr int NCS = kNB / 32;
+  __shared__ TargetTile S;
+  __shared__ float Bs[2][kKS32][kNB + 1];
+  const M2LItem it = items[blockIdx.x];
+  const M2LLevel L = lv[it.level];
+  const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+  const int nthr = blockDim.x;
+  load_targets(S, it, L, tgt_list);
+  __syncthreads();
+  const float* mom = static_cast<const float*>(L.mom);
+  double2* out = static_cast<double2*>(L.out);
+  const int64_t per = int64_t(Kp) * Kp;
+  f16v accr[NCS], acci[NCS], totr[NCS], toti[NCS];
+  for (int cs = 0; cs < NCS; ++cs)
+    for (int i = 0; i < 16; ++i) totr[cs][i] = toti[cs][i] = 0.0f;
+  const int row = 32 * wave + (lane % 32);
+  const int kl = lane / 32;
+  bool first = true;
+  for (int v = 0; v < it.vo_count; ++v) {
+    const int4 od = offtab[valid_off[it.vo_begin + v]];
+    __syncthreads();
+    source_columns(S, L, od, it.c, Kp);
+    const float* Ar = bank + int64_t(od.w) * 2 * per;
+    const float* Ai = Ar + per;
+    for (int cs = 0; cs < NCS; ++cs)
+      for (int i = 0; i < 16; ++i) accr[cs][i] = acci[cs][i] = 0.0f;
+    for (int k0 = 0; k0 < Kp; k0 += kKS32) {
+      __syncthreads();
+      for (int e = threadIdx.x; e < kNB * (kKS32 / 2); e += nthr) {
+        const int j = e / (kKS32 / 2), q = e % (kKS32 / 2);
+        const int64_t col = S.col[j];
+        float4 val = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (col >= 0) val = *reinterpret_cast<const float4*>(mom + 2 * (col + k0 + 2 * q));
+        Bs[0][2 * q][j] = val.x;
+        Bs[1][2 * q][j] = val.y;
+        Bs[0][2 * q + 1][j] = val.z;
+        Bs[1][2 * q + 1][j] = val.w;
+      }
+      __syncthreads();
+#pragma unroll
+      for (int kk = 0; kk < kKS32; kk += 2) {
+        const int64_t ka = int64_t(k0 + kk + kl) * Kp + row;
+        const float ar = Ar[ka], ai = Ai[ka];
+#pragma unroll
+        for (int cs = 0; cs < NCS; ++cs) {
+          const float br = Bs[0][kk + kl][32 * cs + (lane % 32)];
+          const float bi = Bs[1][kk + kl][32 * cs + (lane % 32)];
+          accr[cs] = __builtin_amdgcn_mfma_f32_32x32x2f32(ar, br, accr[cs], 0, 0, 0);
+          accr[cs] = __builtin_amdgcn_mfma_f32_32x32x2f32(-ai, bi, accr[cs], 0, 0, 0);
+          acci[cs] = __builtin_amdgcn_mfma_f32_32x32x2f32(ar, bi, acci[cs], 0, 0, 0);
+          acci[cs] = __builtin_amdgcn_mfma_f32_32x32x2f32(ai, br, acci[cs], 0, 0, 0);
+        }
+      }
+    }
+    for (int cs = 0; cs < NCS; ++cs) {
+      totr[cs] += accr[cs];
+      toti[cs] += acci[cs];
+    }
+    if ((v + 1) % kFlush == 0 || v + 1 == it.vo_count) {
+      flush_f32(totr, toti, S, out, L.nd, it.c, Kp, wave, lane, first);
+      first = false;
+      for (int cs = 0; cs < NCS; ++cs)
+        for (int i = 0; i < 16; ++i) totr[cs][i] = toti[cs][i] = 0.0f;
+    }
+  }
+  if (first) flush_f32(totr, toti, S, out, L.nd, it.c, Kp, wave, lane, true);  // no offsets: zeros
+}
+
+// ---------------------------------------------------------------- FP64 --
+constexpr int kKS64 = 16;
+__global__ void __launch_bounds__(kM2LMaxThreads) k_m2l_f64(
+    const M2LItem* __restrict__ items, const M2LLevel* __restrict__ lv,
+    const int32_t* __restrict__ tgt_list, const int32_t* __restrict__ valid_off,
+    const int4* __restrict__ offtab, const double* __restrict__ bank, int Kp) {
+  constexpr int NCS = kNB / 16;
+  __shared__ TargetTile S;
+  __shared__ double Bs[2][kKS64][kNB + 1];
+  const M2LItem it = items[blockIdx.x];
+  const M2LLevel L = lv[it.level];
+  const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+  const int nthr = blockDim.x;
+  load_targets(S, it, L, tgt_list);
+  __syncthreads();
+  const double* mom = static_cast<const double*>(L.mom);
+  const int64_t per = int64_t(Kp) * Kp;
+  d4v accr[2][NCS], acci[2][NCS];
+  for (int rs = 0; rs < 2; ++rs)
+    for (int cs = 0; cs < NCS; ++cs)
+      for (int i = 0; i < 4; ++i) accr[rs][cs][i] = acci[rs][cs][i] = 0.0;
+  const int kl = lane / 16, li = lane % 16;
+  for (int v = 0; v < it.vo_count; ++v) {
+    const int4 od = offtab[valid_off[it.vo_begin + v]];
+    __syncthreads();
+    source_columns(S, L, od, it.c, Kp);
+    const double* Ar = bank + int64_t(od.w) * 2 * per;
+    const double* Ai = Ar + per;
+    for (int k0 = 0; k0 < Kp; k0 += kKS64) {
+      __syncthreads();
+      for (int e = threadIdx.x; e < kNB * kKS64; e += nthr) {
+        const int j = e / kKS64, q = e % kKS64;
+        const int64_t col = S.col[j];
+        double2 val = make_double2(0.0, 0.0);
+        if (col >= 0) val = *reinterpret_cast<const double2*>(mom + 2 * (col + k0 + q));
+        Bs[0][q][j] = val.x;
+        Bs[1][q][j] = val.y;
+      }
+      __syncthreads();
+#pragma unroll
+      for (int kk = 0; kk < kKS64; kk += 4) {
+        double ar[2], ai[2];
+#pragma unroll
+        for (int rs = 0; rs < 2; ++rs) {
+          const int64_t ka = int64_t(k0 + kk + kl) * Kp + 32 * wave + 16 * rs + li;
+          ar[rs] = Ar[ka];
+          ai[rs] = Ai[ka];
+        }
+#pragma unroll
+        for (int cs = 0; cs < NCS; ++cs) {
+          const double br = Bs[0][kk + kl][16 * cs + li];
+          const double bi = Bs[1][kk + kl][16 * cs + li];
+#pragma unroll
+          for (int rs = 0; rs < 2; ++rs) {
+            accr[rs][cs] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[rs], br, accr[rs][cs], 0, 0, 0);
+            accr[rs][cs] = __builtin_amdgcn_mfma_f64_16x16x4f64(-ai[rs], bi, accr[rs][cs], 0, 0, 0);
+            acci[rs][cs] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[rs], bi, acci[rs][cs], 0, 0, 0);
+            acci[rs][cs] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai[rs], br, acci[rs][cs], 0, 0, 0);
+          }
+        }
+      }
+    }
+  }
+  double2* out = static_cast<double2*>(L.out);
+#pragma unroll
+  for (int cs = 0; cs < NCS; ++cs) {
+    const int j = 16 * cs + li;
+    const int32_t t = S.t[j];
+    if (t < 0) continue;
+    double2* dst = out + (int64_t(t) * L.nd + it.c) * Kp;
+#pragma unroll
+    for (int rs = 0; rs < 2; ++rs)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int r = 32 * wave + 16 * rs + kl + 4 * i;
+        dst[r] = make_double2(accr[rs][cs][i], acci[rs][cs][i]);
+      }
+  }
+}
+
+// --------------------------------------------------------- work lists --
+// Candidate offsets of an item whose source box is non-empty for at least
+// one target of the block: count (pass 0) or write (pass 1) them.  One wave
+// per item; also counts the admissible blocks per offset.
+__global__ void __launch_bounds__(64) k_valid_offsets(
+    const M2LItem* __restrict__ items, int64_t n_items, const int32_t* __restrict__ cand_begin,
+    const int32_t* __restrict__ cand_count, const int32_t* __restrict__ cand,
+    const M2LLevel* __restrict__ lv, const int32_t* __restrict__ tgt_list,
+    const int4* __restrict__ offtab, int pass, int32_t* __restrict__ counts,
+    const int32_t* __restrict__ out_begin, int32_t* __restrict__ out,
+    unsigned long long* __restrict__ blocks_per_off) {
+  const int lane = threadIdx.x;
+  for (int64_t ii = blockIdx.x; ii < n_items; ii += gridDim.x) {
+    const M2LItem it = items[ii];
+    const M2LLevel L = lv[it.level];
+    const int lim = 1 << L.level;
+    int ix = 0, iy = 0, iz = 0;
+    const int32_t t = lane < it.ntgt ? tgt_list[it.tgt_begin + lane] : -1;
+    if (t >= 0) demorton3(L.keyT[t], L.level, ix, iy, iz);
+    const int32_t* cl = cand + cand_begin[ii];
+    const int nc = cand_count[ii];
+    int n = 0;
+    for (int q = 0; q < nc; ++q) {
+      const int4 od = offtab[cl[q]];
+      bool ok = false;
+      if (t >= 0) {
+        const int sx = ix - od.x, sy = iy - od.y, sz = iz - od.z;
+        if (sx >= 0 && sy >= 0 && sz >= 0 && sx < lim && sy < lim && sz < lim)
+          ok = L.gridS[morton3(sx, sy, sz, L.level)] >= 0;
+      }
+      const unsigned long long mask = __ballot(ok);
+      if (mask) {
+        if (pass == 1 && lane == 0) {
+          out[out_begin[ii] + n] = cl[q];
+          atomicAdd(&blocks_per_off[cl[q]], (unsigned long long)__popcll(mask));
+        }
+        ++n;
+      }
+    }
+    if (pass == 0 && lane == 0) counts[ii] = n;
+  }
+}
+
+}  // namespace
+
+void launch_bank(Plan& P, hipStream_t s) {
+  if (P.n_bank == 0) return;
+  std::vector<int32_t> info;
+  info.reserve(5 * P.n_bank);
+  std::vector<BankLevel> bl(P.levels + 1);
+  for (int l = 0; l <= P.levels; ++l) {
+    bl[l] = BankLevel{P.L[l].h, l, P.L[l].nd, P.L[l].dirvec.get()};
+    const LevelTable& T = P.tab[l];
+    for (size_t i = 0; i < T.adm.size(); ++i) {
+      info.push_back(l);
+      info.push_back(T.adm[i].x);
+      info.push_back(T.adm[i].y);
+      info.push_back(T.adm[i].z);
+      info.push_back(T.dir[i]);
+    }
+  }
+  DevBuf<int32_t> d_info;
+  DevBuf<BankLevel> d_bl;
+  to_device(d_info, info, s, nullptr);
+  to_device(d_bl, bl, s, nullptr);
+  const int64_t per = int64_t(P.ip.Kp) * P.ip.Kp;
+  const int64_t total = P.n_bank * per;
+  const int B = 256;
+  if (P.prec == FDM_PREC_FP64) {
+    P.bank64.alloc(2 * total, &P.tally);
+    k_bank<double><<<grid_for(total, B), B, 0, s>>>(d_info.get(), P.n_bank, d_bl.get(),
+                                                  P.kappa, P.ip, P.bank64.get());
+  } else {
+    P.bank32.alloc(2 * total, &P.tally);
+    k_bank<float><<<grid_for(total, B), B, 0, s>>>(d_info.get(), P.n_bank, d_bl.get(),
+                                                 P.kappa, P.ip, P.bank32.get());
+  }
+  FDM_LAUNCH("k_bank");
+  FDM_HIP(hipStreamSynchronize(s));
+}
+
+void build_m2l_work(Plan& P, hipStream_t s) {
+  const int p = P.levels;
+  std::vector<M2LItem> items;
+  std::vector<int32_t> tgt_list, cand, cand_begin_per_item, cand_count_per_item;
+  std::vector<int4> offtab(P.n_bank);
+  std::vector<M2LLevel> lv(p + 1);
+  for (int l = 0; l <= p; ++l) {
+    const LevelTable& T = P.tab[l];
+    LevelData& Ld = P.L[l];
+    for (size_t i = 0; i < T.adm.size(); ++i)
+      offtab[Ld.bank_base + i] = make_int4(T.adm[i].x, T.adm[i].y, T.adm[i].z,
+                                           static_cast<int>(Ld.bank_base + i));
+    M2LLevel m{};
+    m.gridS = P.S.grid[l].get();
+    m.keyT = P.T.key[l].get();
+    m.nd = Ld.nd;
+    m.level = l;
+    m.mom = P.prec == FDM_PREC_FP64 ? static_cast<const void*>(Ld.mom64.get())
+                                    : static_cast<const void*>(Ld.mom32.get());
+    m.out = Ld.loc64.get();  // FP64 coupling result, completed in place by L2L
+    lv[l] = m;
+  }
+  for (int l = std::max(P.l_min, 0); l <= p; ++l) {
+    const LevelTable& T = P.tab[l];
+    const LevelData& Ld = P.L[l];
+    // candidate offsets per (octant, direction)
+    std::vector<std::vector<int32_t>> lists(8 * Ld.nd);
+    for (size_t i = 0; i < T.adm.size(); ++i)
+      for (int q = 0; q < 8; ++q)
+        if (T.mask[i] & (1u << q))
+          lists[q * Ld.nd + T.dir[i]].push_back(static_cast<int32_t>(Ld.bank_base + i));
+    std::vector<int32_t> list_begin(8 * Ld.nd);
+    for (size_t k = 0; k < lists.size(); ++k) {
+      list_begin[k] = static_cast<int32_t>(cand.size());
+      cand.insert(cand.end(), lists[k].begin(), lists[k].end());
+    }
+    // target boxes grouped by octant, in Morton order
+    std::vector<uint32_t> keys = to_host(P.T.key[l].get(), P.T.nb[l], s);
+    std::vector<std::vector<int32_t>> by_oct(8);
+    for (size_t b = 0; b < keys.size(); ++b) by_oct[keys[b] & 7].push_back(static_cast<int32_t>(b));
+    for (int q = 0; q < 8; ++q) {
+      const auto& bx = by_oct[q];
+      for (size_t b0 = 0; b0 < bx.size(); b0 += kNB) {
+        const int nt = static_cast<int>(std::min<size_t>(kNB, bx.size() - b0));
+        const int32_t tb = static_cast<int32_t>(tgt_list.size());
+        tgt_list.insert(tgt_list.end(), bx.begin() + b0, bx.begin() + b0 + nt);
+        for (int c = 0; c < Ld.nd; ++c) {
+          items.push_back(M2LItem{l, c, tb, nt, 0, 0});
+          cand_begin_per_item.push_back(list_begin[q * Ld.nd + c]);
+          cand_count_per_item.push_back(static_cast<int32_t>(lists[q * Ld.nd + c].size()));
+        }
+      }
+    }
+  }
+  P.n_items = static_cast<int64_t>(items.size());
+  to_device(P.m2l_levels, lv, s, &P.tally);
+  P.offtab.alloc(P.n_bank, &P.tally);
+  if (P.n_bank)
+    FDM_HIP(hipMemcpyAsync(P.offtab.get(), offtab.data(), offtab.size() * sizeof(int4),
+                           hipMemcpyHostToDevice, s));
+  to_device(P.tgt_list, tgt_list, s, &P.tally);
+  if (P.n_items == 0) {
+    FDM_HIP(hipStreamSynchronize(s));
+    return;
+  }
+  DevBuf<M2LItem> d_items;
+  DevBuf<int32_t> d_cand, d_cb, d_cc, d_counts(P.n_items), d_begin;
+  to_device(d_items, items, s, nullptr);
+  to_device(d_cand, cand, s, nullptr);
+  to_device(d_cb, cand_begin_per_item, s, nullptr);
+  to_device(d_cc, cand_count_per_item, s, nullptr);
+  DevBuf<unsigned long long> d_bpo(std::max<int64_t>(P.n_bank, 1));
+  FDM_HIP(hipMemsetAsync(d_bpo.get(), 0, d_bpo.bytes(), s));
+  const unsigned G = static_cast<unsigned>(std::min<int64_t>(P.n_items, 1 << 16));
+  k_valid_offsets<<<G, 64, 0, s>>>(d_items.get(), P.n_items, d_cb.get(), d_cc.get(),
+                                   d_cand.get(), P.m2l_levels.get(), P.tgt_list.get(),
+                                   P.offtab.get(), 0, d_counts.get(), nullptr, nullptr,
+                                   nullptr);
+  FDM_LAUNCH("k_valid_offsets");
+  std::vector<int32_t> counts = to_host(d_counts.get(), P.n_items, s);
+  std::vector<int32_t> begin(P.n_items);
+  int64_t total = 0;
+  for (int64_t i = 0; i < P.n_items; ++i) {
+    begin[i] = static_cast<int32_t>(total);
+    total += counts[i];
+  }
+  to_device(d_begin, begin, s, nullptr);
+  P.valid_off.alloc(std::max<int64_t>(total, 1), &P.tally);
+  k_valid_offsets<<<G, 64, 0, s>>>(d_items.get(), P.n_items, d_cb.get(), d_cc.get(),
+                                   d_cand.get(), P.m2l_levels.get(), P.tgt_list.get(),
+                                   P.offtab.get(), 1, nullptr, d_begin.get(),
+                                   P.valid_off.get(), d_bpo.get());
+  FDM_LAUNCH("k_valid_offsets");
+  std::vector<unsigned long long> bpo = to_host(d_bpo.get(), P.n_bank, s);
+  // finish the items: offset ranges, heaviest first (longest-processing-time order)
+  for (int64_t i = 0; i < P.n_items; ++i) {
+    items[i].vo_begin = begin[i];
+    items[i].vo_count = counts[i];
+  }
+  std::stable_sort(items.begin(), items.end(), [](const M2LItem& a, const M2LItem& b) {
+    return a.vo_count > b.vo_count;
+  });
+  to_device(P.items, items, s, &P.tally);
+  // statistics and per-level offset use for export
+  P.n_couplings = 0;
+  P.n_stored = 0;
+  P.m2l_columns = total * kNB;
+  P.off_used.assign(p + 1, {});
+  for (int l = 0; l <= p; ++l) {
+    const LevelTable& T = P.tab[l];
+    for (size_t i = 0; i < T.adm.size(); ++i) {
+      const unsigned long long n = bpo[P.L[l].bank_base + i];
+      if (!n) continue;
+      P.n_couplings += static_cast<int64_t>(n);
+      P.n_stored += 1;
+      auto& u = P.off_used[l];
+      u.push_back(T.adm[i].x);
+      u.push_back(T.adm[i].y);
+      u.push_back(T.adm[i].z);
+      u.push_back(static_cast<int64_t>(n));
+      u.push_back(T.dir[i]);
+    }
+  }
+  FDM_HIP(hipStreamSynchronize(s));
+}
+
+void launch_m2l(Plan& P, hipStream_t s) {
+  if (P.n_items == 0) return;
+  const int threads = 2 * P.ip.Kp;  // one wave per 32 rows
+  if (P.prec == FDM_PREC_FP64) {
+    k_m2l_f64<<<static_cast<unsigned>(P.n_items), threads, 0, s>>>(
+        P.items.get(), P.m2l_levels.get(), P.tgt_list.get(), P.valid_off.get(),
+        P.offtab.get(), P.bank64.get(), P.ip.Kp);
+    FDM_LAUNCH("k_m2l_f64");
+  } else {
+    k_m2l_f32<<<static_cast<unsigned>(P.n_items), threads, 0, s>>>(
+        P.items.get(), P.m2l_levels.get(), P.tgt_list.get(), P.valid_off.get(),
+        P.offtab.get(), P.bank32.get(), P.ip.Kp);
+    FDM_LAUNCH("k_m2l_f32");
+  }
+}
+
+}  // namespace fdm

@@ -1,0 +1,343 @@
+// Plan construction, the matvec driver of Alg. 4, and the C ABI (fdm.h).
+#include "plan.hpp"
+
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <set>
+
+namespace fdm {
+
+namespace {
+
+thread_local std::string g_last_error;
+
+void set_error(const std::string& m) { g_last_error = m; }
+
+Interp make_interp(int m) {
+  Interp ip{};
+  ip.m1 = m + 1;
+  ip.K = ip.m1 * ip.m1 * ip.m1;
+  ip.Kp = (ip.K + 31) / 32 * 32;
+  for (int nu = 0; nu < ip.m1; ++nu)
+    ip.node[nu] = std::cos((2.0 * (nu + 1) - 1.0) * M_PI / (2.0 * ip.m1));
+  for (int nu = 0; nu < ip.m1; ++nu) {
+    double d = 1.0;
+    for (int mu = 0; mu < ip.m1; ++mu)
+      if (mu != nu) d *= ip.node[nu] - ip.node[mu];
+    ip.wgt[nu] = 1.0 / d;
+  }
+  // E1[b][j][k] = l_k(child node j in parent reference coordinates)
+  for (int b = 0; b < 2; ++b)
+    for (int j = 0; j < ip.m1; ++j) {
+      const double u = 0.5 * (ip.node[j] + (2 * b - 1));
+      for (int k = 0; k < ip.m1; ++k) {
+        double p = ip.wgt[k];
+        for (int mu = 0; mu < ip.m1; ++mu)
+          if (mu != k) p *= u - ip.node[mu];
+        ip.E1[b][j][k] = p;
+      }
+    }
+  return ip;
+}
+
+}  // namespace
+
+void plan_build(Plan& P, const double* pT, const double* pS, hipStream_t s) {
+  auto t0 = std::chrono::steady_clock::now();
+  P.ip = make_interp(P.m);
+  P.side = P.hi[0] - P.lo[0];
+  build_tree(pT, P.nT, P.lo, P.hi, P.levels, s, &P.tally, P.T);
+  build_tree(pS, P.nS, P.lo, P.hi, P.levels, s, &P.tally, P.S);
+  if (P.l_hf == -2) {
+    P.l_hf = -1;
+    for (int l = 0; l <= P.levels; ++l)
+      if (P.kappa * (P.side * std::ldexp(1.0, -l)) >= 3.2) P.l_hf = l;
+  }
+  P.tab = build_level_tables(P.kappa, P.side, P.levels, P.l_hf, P.eta2);
+  P.l_min = P.levels + 1;
+  for (int l = 0; l <= P.levels; ++l)
+    if (!P.tab[l].adm.empty()) {
+      P.l_min = l;
+      break;
+    }
+  if (P.nT == 0 || P.nS == 0) P.l_min = P.levels + 1;
+  P.L.clear();
+  P.L.resize(P.levels + 1);
+  P.n_bank = 0;
+  const int Kp = P.ip.Kp;
+  const bool mixed = P.prec != FDM_PREC_FP64;
+  for (int l = 0; l <= P.levels; ++l) {
+    LevelData& Ld = P.L[l];
+    Ld.level = l;
+    Ld.nd = direction_count(l, P.l_hf);
+    Ld.h = P.side * std::ldexp(1.0, -l);
+    to_device(Ld.dirvec, direction_vectors(l, P.l_hf), s, &P.tally);
+    Ld.bank_base = P.n_bank;
+    if (l >= P.l_min) {
+      P.n_bank += static_cast<int64_t>(P.tab[l].adm.size());
+      const int64_t ns = P.S.nb[l] * int64_t(Ld.nd) * Kp;
+      const int64_t nt = P.T.nb[l] * int64_t(Ld.nd) * Kp;
+      Ld.mom64.alloc(2 * ns, &P.tally);
+      Ld.loc64.alloc(2 * nt, &P.tally);
+      if (mixed) Ld.mom32.alloc(2 * ns, &P.tally);
+    }
+  }
+  // near-field offsets on the leaf level
+  {
+    const auto& in = P.tab[P.levels].inadm;
+    std::vector<int32_t> no;
+    for (const Off& o : in) {
+      no.push_back(o.x);
+      no.push_back(o.y);
+      no.push_back(o.z);
+    }
+    P.n_near_off = static_cast<int>(in.size());
+    to_device(P.near_off, no, s, &P.tally);
+  }
+  P.v_tree.alloc(2 * std::max<int64_t>(P.nS, 1), &P.tally);
+  P.y_tree.alloc(2 * std::max<int64_t>(P.nT, 1), &P.tally);
+  if (P.l_min <= P.levels) {
+    launch_bank(P, s);
+    build_m2l_work(P, s);
+  }
+  // near-field statistics (host, from box counts)
+  {
+    const int p = P.levels;
+    P.near_pairs = 0;
+    P.near_entries = 0;
+    if (P.nT && P.nS) {
+      std::vector<uint32_t> kT = to_host(P.T.key[p].get(), P.T.nb[p], s);
+      std::vector<int32_t> cT = to_host(P.T.count[p].get(), P.T.nb[p], s);
+      std::vector<int32_t> gS = to_host(P.S.grid[p].get(), size_t(1) << (3 * p), s);
+      std::vector<int32_t> cS = to_host(P.S.count[p].get(), P.S.nb[p], s);
+      const int lim = 1 << p;
+      for (size_t b = 0; b < kT.size(); ++b) {
+        int ix, iy, iz;
+        demorton3(kT[b], p, ix, iy, iz);
+        for (const Off& o : P.tab[p].inadm) {
+          int sx = ix - o.x, sy = iy - o.y, sz = iz - o.z;
+          if (sx < 0 || sy < 0 || sz < 0 || sx >= lim || sy >= lim || sz >= lim) continue;
+          int32_t sb = gS[morton3(sx, sy, sz, p)];
+          if (sb < 0) continue;
+          P.near_pairs += 1;
+          P.near_entries += int64_t(cT[b]) * cS[sb];
+        }
+      }
+    }
+  }
+  FDM_HIP(hipStreamSynchronize(s));
+  P.setup_ms = std::chrono::duration<double, std::milli>(
+                   std::chrono::steady_clock::now() - t0).count();
+}
+
+void plan_matvec(Plan& P, const void* v_user, void* y_user, bool c64, hipStream_t s) {
+  const int p = P.levels;
+  if (P.nT == 0) return;
+  if (P.nS == 0) {  // no sources: y = 0
+    launch_zero_c128(P.y_tree.get(), P.nT, s);
+    if (c64)
+      launch_permute_out_c64(P.y_tree.get(), P.T.perm.get(), P.nT, static_cast<float*>(y_user), s);
+    else
+      launch_permute_out(P.y_tree.get(), P.T.perm.get(), P.nT, static_cast<double*>(y_user), s);
+    return;
+  }
+  if (c64)
+    launch_permute_in_c64(static_cast<const float*>(v_user), P.S.perm.get(), P.nS,
+                          P.v_tree.get(), s);
+  else
+    launch_permute_in(static_cast<const double*>(v_user), P.S.perm.get(), P.nS,
+                      P.v_tree.get(), s);
+  if (P.l_min <= p) {
+    launch_s2m(P, s);                                   // forward transformation
+    for (int l = p - 1; l >= P.l_min; --l) launch_m2m(P, l, s);
+    launch_m2l(P, s);                                   // multiplication phase
+    for (int l = P.l_min; l < p; ++l) launch_l2l(P, l, s);  // backward transformation
+  }
+  launch_l2t(P, s);
+  launch_p2p(P, s);                                     // near field
+  if (c64)
+    launch_permute_out_c64(P.y_tree.get(), P.T.perm.get(), P.nT, static_cast<float*>(y_user), s);
+  else
+    launch_permute_out(P.y_tree.get(), P.T.perm.get(), P.nT, static_cast<double*>(y_user), s);
+  P.has_run = true;
+}
+
+}  // namespace fdm
+
+// ====================================================================== C ABI
+using namespace fdm;
+
+namespace {
+
+template <class F>
+int guarded(F&& f) {
+  try {
+    g_last_error.clear();
+    f();
+    return FDM_OK;
+  } catch (const Error& e) {
+    set_error(e.what());
+    return e.status;
+  } catch (const std::bad_alloc&) {
+    set_error("host allocation failed");
+    return FDM_ERR_OUT_OF_MEMORY;
+  } catch (const std::exception& e) {
+    set_error(e.what());
+    return FDM_ERR_STATE;
+  }
+}
+
+void check_device_ptr(const void* p, const char* what) {
+  if (!p) fail(FDM_ERR_INVALID_ARG, std::string(what) + " is NULL");
+  hipPointerAttribute_t a{};
+  if (hipPointerGetAttributes(&a, p) != hipSuccess) {
+    (void)hipGetLastError();
+    fail(FDM_ERR_INVALID_ARG, std::string(what) + " is not a device pointer");
+  }
+  if (a.type != hipMemoryTypeDevice && a.type != hipMemoryTypeManaged)
+    fail(FDM_ERR_INVALID_ARG, std::string(what) + " is not device memory");
+}
+
+}  // namespace
+
+extern "C" {
+
+int fdm_build_tree_ex(const double* points_T, int64_t n_T, const double* points_S,
+                      int64_t n_S, double kappa, const double box[6], int levels, int m,
+                      int precision, int l_hf, void* stream, fdm_plan** out) {
+  return guarded([&] {
+    if (!out) fail(FDM_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    if (n_T < 0 || n_S < 0) fail(FDM_ERR_INVALID_ARG, "negative point count");
+    if (n_T > INT32_MAX / 2 || n_S > INT32_MAX / 2)
+      fail(FDM_ERR_UNSUPPORTED, "point count too large");
+    if (!box) fail(FDM_ERR_INVALID_ARG, "box is NULL");
+    if (!std::isfinite(kappa) || kappa < 0) fail(FDM_ERR_INVALID_ARG, "kappa must be finite and >= 0");
+    if (levels < 0 || levels > 9) fail(FDM_ERR_INVALID_ARG, "levels must be in [0, 9]");
+    if (m < 1 || m > 8) fail(FDM_ERR_INVALID_ARG, "m must be in [1, 8]");
+    if (precision < FDM_PREC_FP64 || precision > FDM_PREC_BF16X3)
+      fail(FDM_ERR_INVALID_ARG, "unknown precision");
+    if (l_hf < -2 || l_hf > levels) fail(FDM_ERR_INVALID_ARG, "l_hf out of range");
+    for (int d = 0; d < 3; ++d)
+      if (!std::isfinite(box[d]) || !std::isfinite(box[d + 3]) || !(box[d + 3] > box[d]))
+        fail(FDM_ERR_INVALID_ARG, "invalid box");
+    if (!(box[3] - box[0] == box[4] - box[1] && box[3] - box[0] == box[5] - box[2]))
+      fail(FDM_ERR_UNSUPPORTED, "the root box must be a cube");
+    const int K = (m + 1) * (m + 1) * (m + 1);
+    if ((K + 31) / 32 * 32 > kMaxKp)
+      fail(FDM_ERR_UNSUPPORTED, "m > 6 is not supported by the coupling kernels");
+    if (precision == FDM_PREC_BF16X3)
+      fail(FDM_ERR_UNSUPPORTED, "the BF16 split precision is not built yet");
+    if (n_T) check_device_ptr(points_T, "points_T");
+    if (n_S) check_device_ptr(points_S, "points_S");
+    auto* h = new fdm_plan();
+    try {
+      Plan& P = h->p;
+      P.nT = n_T;
+      P.nS = n_S;
+      P.kappa = kappa;
+      for (int d = 0; d < 3; ++d) {
+        P.lo[d] = box[d];
+        P.hi[d] = box[d + 3];
+      }
+      P.levels = levels;
+      P.m = m;
+      P.prec = precision;
+      P.l_hf = l_hf;
+      plan_build(P, points_T, points_S, static_cast<hipStream_t>(stream));
+    } catch (...) {
+      (void)hipStreamSynchronize(static_cast<hipStream_t>(stream));
+      delete h;
+      throw;
+    }
+    *out = h;
+  });
+}
+
+int fdm_build_tree(const double* points_T, int64_t n_T, const double* points_S,
+                   int64_t n_S, double kappa, const double box[6], int levels, int m,
+                   int precision, void* stream, fdm_plan** out) {
+  return fdm_build_tree_ex(points_T, n_T, points_S, n_S, kappa, box, levels, m, precision,
+                           -2, stream, out);
+}
+
+static int matvec_entry(fdm_plan* plan, const void* v, void* y, void* stream, bool c64) {
+  return guarded([&] {
+    if (!plan) fail(FDM_ERR_INVALID_ARG, "plan is NULL");
+    Plan& P = plan->p;
+    if (P.nS) check_device_ptr(v, "v");
+    if (P.nT) check_device_ptr(y, "y");
+    const int64_t w = c64 ? 8 : 16;
+    if (P.nS && P.nT) {
+      const char* a = static_cast<const char*>(v);
+      const char* b = static_cast<const char*>(y);
+      if (a < b + w * P.nT && b < a + w * P.nS) fail(FDM_ERR_INVALID_ARG, "v and y overlap");
+    }
+    plan_matvec(P, v, y, c64, static_cast<hipStream_t>(stream));
+  });
+}
+
+int fdm_plan_matvec(fdm_plan* plan, const void* v, void* y, void* stream) {
+  return matvec_entry(plan, v, y, stream, false);
+}
+
+int fdm_plan_matvec_c64(fdm_plan* plan, const void* v, void* y, void* stream) {
+  return matvec_entry(plan, v, y, stream, true);
+}
+
+int fdm_plan_destroy(fdm_plan* plan) {
+  return guarded([&] {
+    if (!plan) return;
+    (void)hipDeviceSynchronize();
+    delete plan;
+  });
+}
+
+int fdm_plan_stats(const fdm_plan* plan, fdm_stats* out) {
+  return guarded([&] {
+    if (!plan || !out) fail(FDM_ERR_INVALID_ARG, "NULL argument");
+    const Plan& P = plan->p;
+    fdm_stats st{};
+    st.n_T = P.nT;
+    st.n_S = P.nS;
+    st.levels = P.levels;
+    st.m = P.m;
+    st.K = P.ip.K;
+    st.precision = P.prec;
+    st.l_hf = P.l_hf;
+    st.l_min = P.l_min;
+    st.n_couplings = P.n_couplings;
+    st.n_stored_couplings = P.n_stored;
+    st.n_bank_matrices = P.n_bank;
+    st.near_pairs = P.near_pairs;
+    st.near_entries = P.near_entries;
+    st.m2l_columns = P.m2l_columns;
+    st.device_bytes = P.tally;
+    st.setup_ms = P.setup_ms;
+    *out = st;
+  });
+}
+
+int fdm_dense_matvec(const double* points_T, int64_t n_T, const double* points_S,
+                     int64_t n_S, double kappa, const void* v, void* y, void* stream) {
+  return guarded([&] {
+    if (n_T < 0 || n_S < 0) fail(FDM_ERR_INVALID_ARG, "negative point count");
+    if (!std::isfinite(kappa) || kappa < 0) fail(FDM_ERR_INVALID_ARG, "kappa must be finite and >= 0");
+    if (n_T == 0) return;
+    check_device_ptr(points_T, "points_T");
+    check_device_ptr(y, "y");
+    if (n_S) {
+      check_device_ptr(points_S, "points_S");
+      check_device_ptr(v, "v");
+    }
+    launch_dense(points_T, n_T, points_S, n_S, kappa, static_cast<const double*>(v),
+                 static_cast<double*>(y), static_cast<hipStream_t>(stream));
+  });
+}
+
+const char* fdm_last_error(void) { return g_last_error.c_str(); }
+
+const char* fdm_version(void) { return "fdm-gfx950 0.1"; }
+
+}  // extern "C"

@@ -1,0 +1,245 @@
+// Forward transformation of Alg. 4 (Sect. 2.6): S2M on the leaves and M2M
+// up to the coarsest level that holds a coupling, in the centre-relative
+// phase form:
+//
+//   S2M  v~_{s,c}[mu] = sum_{k in s} L_{s,mu}(y_k) exp(-i kappa <y_k - m_s, c>) v_k
+//   M2M  v~_{s,c} = sum_{s'} E_{s'}^T ( conj(E~d_{s',c}) .* v~_{s',c'} )
+//        E~d_{s',c}[k] = exp(i kappa (<xi_{s',k} - m_s, c> - <xi_{s',k} - m_{s'}, c'>))
+//
+// These equal the paper's moments times exp(i kappa <m_s, c>) (the factor
+// moves into the coupling matrices), which keeps every phase argument of
+// the size of a box.  E_{s'} (Sect. 2.7) is the tensor product of two 1D
+// Lagrange interpolation matrices (child lower / upper half per axis), so it
+// is applied as three 1D passes; E~d factorises per axis as well.
+// Every direction of D^(l) is formed for every box (a superset of
+// D(s) u D^(s); the extra moments are never read).
+#include "plan.hpp"
+#include "device_math.hpp"
+
+namespace fdm {
+
+namespace {
+
+// Write one coefficient vector (K values, zero padding up to Kp) in FP64 and,
+// if requested, as the FP32 operand copy.
+__device__ __forceinline__ void store_coeffs(const double2 (&acc)[kPerLane],
+                                             double2* __restrict__ out64,
+                                             float2* __restrict__ out32,
+                                             int64_t base, int K, int Kp, int lane) {
+#pragma unroll
+  for (int i = 0; i < (kMaxK + 63) / 64 + 1; ++i) {
+    const int k = lane + 64 * i;
+    if (k < Kp) {
+      const double2 val = (k < K && i < kPerLane) ? acc[i < kPerLane ? i : 0]
+                                                  : make_double2(0.0, 0.0);
+      out64[base + k] = val;
+      if (out32) out32[base + k] = make_float2(float(val.x), float(val.y));
+    }
+  }
+}
+
+__global__ void k_permute_in(const double2* __restrict__ v_user,
+                             const int32_t* __restrict__ perm, int64_t n,
+                             double2* __restrict__ v_tree) {
+  for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < n;
+       i += int64_t(gridDim.x) * blockDim.x)
+    v_tree[i] = v_user[perm[i]];
+}
+
+__global__ void k_permute_out(const double2* __restrict__ y_tree,
+                              const int32_t* __restrict__ perm, int64_t n,
+                              double2* __restrict__ y_user) {
+  for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < n;
+       i += int64_t(gridDim.x) * blockDim.x)
+    y_user[perm[i]] = y_tree[i];
+}
+
+__global__ void k_permute_in_c64(const float2* __restrict__ v_user,
+                                 const int32_t* __restrict__ perm, int64_t n,
+                                 double2* __restrict__ v_tree) {
+  for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < n;
+       i += int64_t(gridDim.x) * blockDim.x) {
+    const float2 a = v_user[perm[i]];
+    v_tree[i] = make_double2(a.x, a.y);
+  }
+}
+
+__global__ void k_permute_out_c64(const double2* __restrict__ y_tree,
+                                  const int32_t* __restrict__ perm, int64_t n,
+                                  float2* __restrict__ y_user) {
+  for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < n;
+       i += int64_t(gridDim.x) * blockDim.x)
+    y_user[perm[i]] = make_float2(float(y_tree[i].x), float(y_tree[i].y));
+}
+
+// One wave per (leaf box, direction).
+__global__ void __launch_bounds__(64) k_s2m(
+    const double* __restrict__ x, const double* __restrict__ y,
+    const double* __restrict__ z, const double2* __restrict__ v,
+    const uint32_t* __restrict__ key, const int32_t* __restrict__ start,
+    const int32_t* __restrict__ count, int64_t nb, int level, double lo0,
+    double lo1, double lo2, double h, const double* __restrict__ dirvec, int nd,
+    double kappa, Interp ip, double2* __restrict__ mom, float2* __restrict__ mom32) {
+  __shared__ double lag[3][kMaxM1];
+  const int lane = threadIdx.x;
+  const int c = blockIdx.y;
+  const int m1 = ip.m1, K = ip.K, Kp = ip.Kp;
+  const double cx = dirvec[3 * c], cy = dirvec[3 * c + 1], cz = dirvec[3 * c + 2];
+  for (int64_t b = blockIdx.x; b < nb; b += gridDim.x) {
+    int ix, iy, iz;
+    demorton3(key[b], level, ix, iy, iz);
+    const double mx = lo0 + (ix + 0.5) * h, my = lo1 + (iy + 0.5) * h,
+                 mz = lo2 + (iz + 0.5) * h;
+    const double inv_half = 2.0 / h;
+    double2 acc[kPerLane];
+    for (int i = 0; i < kPerLane; ++i) acc[i] = make_double2(0.0, 0.0);
+    const int p0 = start[b], pn = count[b];
+    for (int pi = 0; pi < pn; ++pi) {
+      const int64_t j = p0 + pi;
+      const double dx = x[j] - mx, dy = y[j] - my, dz = z[j] - mz;
+      __syncthreads();
+      if (lane < 3 * m1) {
+        const int d = lane / m1, nu = lane % m1;
+        const double u = (d == 0 ? dx : d == 1 ? dy : dz) * inv_half;
+        lag[d][nu] = lagrange1d(ip, nu, u);
+      }
+      __syncthreads();
+      double sn, cs;
+      phase_sincos(-kappa * (dx * cx + dy * cy + dz * cz), sn, cs);
+      const double2 vj = v[j];
+      const double wr = vj.x * cs - vj.y * sn, wi = vj.x * sn + vj.y * cs;
+#pragma unroll
+      for (int i = 0; i < kPerLane; ++i) {
+        const int mu = lane + 64 * i;
+        if (mu < K) {
+          const int n3 = mu % m1, n2 = (mu / m1) % m1, n1 = mu / (m1 * m1);
+          const double L = lag[0][n1] * lag[1][n2] * lag[2][n3];
+          acc[i].x += L * wr;
+          acc[i].y += L * wi;
+        }
+      }
+    }
+    store_coeffs(acc, mom, mom32, (b * nd + c) * int64_t(Kp), K, Kp, lane);
+  }
+}
+
+// One workgroup (64 threads) per (parent box, direction).
+__global__ void __launch_bounds__(64) k_m2m(
+    const double2* __restrict__ child_mom, int nd1, const int32_t* __restrict__ grid1,
+    const uint32_t* __restrict__ key, int64_t nb, int level, double h1,
+    const double* __restrict__ dirvec, const double* __restrict__ dirvec1, int nd,
+    int l_hf, double kappa, Interp ip, double2* __restrict__ mom,
+    float2* __restrict__ mom32) {
+  __shared__ double2 buf[2][kMaxK];
+  __shared__ double2 ph[3][kMaxM1];
+  const int lane = threadIdx.x;
+  const int c = blockIdx.y;
+  const int m1 = ip.m1, K = ip.K, Kp = ip.Kp;
+  const int cp = (level + 1 <= l_hf) ? (c >> 2) : 0;  // c' = dir_(l+1)(c)
+  const double cv[3] = {dirvec[3 * c], dirvec[3 * c + 1], dirvec[3 * c + 2]};
+  const double cv1[3] = {dirvec1[3 * cp], dirvec1[3 * cp + 1], dirvec1[3 * cp + 2]};
+  for (int64_t b = blockIdx.x; b < nb; b += gridDim.x) {
+    double2 acc[kPerLane];
+    for (int i = 0; i < kPerLane; ++i) acc[i] = make_double2(0.0, 0.0);
+    const uint32_t pkey = key[b];
+    for (int q = 0; q < 8; ++q) {
+      const int32_t ch = grid1[(pkey << 3) | q];
+      if (ch < 0) continue;
+      const int bq[3] = {(q >> 2) & 1, (q >> 1) & 1, q & 1};
+      __syncthreads();
+      // per-axis factors of conj(E~d): exp(-i kappa ((xi-m_s) c - (xi-m_s') c'))
+      if (lane < 3 * m1) {
+        const int d = lane / m1, nu = lane % m1;
+        const double r = 0.5 * h1 * ip.node[nu];          // xi - m_{s'}
+        const double off = (bq[d] - 0.5) * h1;            // m_{s'} - m_s
+        double sn, cs;
+        phase_sincos(-kappa * ((r + off) * cv[d] - r * cv1[d]), sn, cs);
+        ph[d][nu] = make_double2(cs, sn);
+      }
+      __syncthreads();
+      const double2* src = child_mom + (int64_t(ch) * nd1 + cp) * Kp;
+      for (int k = lane; k < K; k += 64) {
+        const int n3 = k % m1, n2 = (k / m1) % m1, n1 = k / (m1 * m1);
+        double2 f = cmul(cmul(ph[0][n1], ph[1][n2]), ph[2][n3]);
+        buf[0][k] = cmul(f, src[k]);
+      }
+      __syncthreads();
+      // E_{s'}^T as three 1D passes: out[k] = sum_j E1[b][j][k] in[j]
+      apply_transfer(buf, ip, bq, true, lane, 64);  // result in buf[1]
+#pragma unroll
+      for (int i = 0; i < kPerLane; ++i) {
+        const int k = lane + 64 * i;
+        if (k < K) {
+          acc[i].x += buf[1][k].x;
+          acc[i].y += buf[1][k].y;
+        }
+      }
+    }
+    store_coeffs(acc, mom, mom32, (b * nd + c) * int64_t(Kp), K, Kp, lane);
+  }
+}
+
+}  // namespace
+
+void launch_permute_in(const double* v_user, const int32_t* perm, int64_t n,
+                       double* v_tree, hipStream_t s) {
+  if (n == 0) return;
+  k_permute_in<<<grid_for(n, 256), 256, 0, s>>>(
+      reinterpret_cast<const double2*>(v_user), perm, n, reinterpret_cast<double2*>(v_tree));
+  FDM_LAUNCH("k_permute_in");
+}
+
+void launch_permute_out(const double* y_tree, const int32_t* perm, int64_t n,
+                        double* y_user, hipStream_t s) {
+  if (n == 0) return;
+  k_permute_out<<<grid_for(n, 256), 256, 0, s>>>(
+      reinterpret_cast<const double2*>(y_tree), perm, n, reinterpret_cast<double2*>(y_user));
+  FDM_LAUNCH("k_permute_out");
+}
+
+void launch_permute_in_c64(const float* v_user, const int32_t* perm, int64_t n,
+                           double* v_tree, hipStream_t s) {
+  if (n == 0) return;
+  k_permute_in_c64<<<grid_for(n, 256), 256, 0, s>>>(
+      reinterpret_cast<const float2*>(v_user), perm, n, reinterpret_cast<double2*>(v_tree));
+  FDM_LAUNCH("k_permute_in_c64");
+}
+
+void launch_permute_out_c64(const double* y_tree, const int32_t* perm, int64_t n,
+                            float* y_user, hipStream_t s) {
+  if (n == 0) return;
+  k_permute_out_c64<<<grid_for(n, 256), 256, 0, s>>>(
+      reinterpret_cast<const double2*>(y_tree), perm, n, reinterpret_cast<float2*>(y_user));
+  FDM_LAUNCH("k_permute_out_c64");
+}
+
+void launch_s2m(Plan& P, hipStream_t s) {
+  const int p = P.levels;
+  LevelData& Lp = P.L[p];
+  const int64_t nb = P.S.nb[p];
+  if (nb == 0) return;
+  dim3 grid(static_cast<unsigned>(std::min<int64_t>(nb, 1 << 20)), Lp.nd);
+  k_s2m<<<grid, 64, 0, s>>>(P.S.x.get(), P.S.y.get(), P.S.z.get(),
+                            reinterpret_cast<const double2*>(P.v_tree.get()),
+                            P.S.key[p].get(), P.S.start[p].get(), P.S.count[p].get(), nb, p,
+                            P.lo[0], P.lo[1], P.lo[2], Lp.h, Lp.dirvec.get(), Lp.nd,
+                            P.kappa, P.ip, reinterpret_cast<double2*>(Lp.mom64.get()),
+                            reinterpret_cast<float2*>(Lp.mom32.get()));
+  FDM_LAUNCH("k_s2m");
+}
+
+void launch_m2m(Plan& P, int level, hipStream_t s) {
+  LevelData& Lc = P.L[level];
+  LevelData& L1 = P.L[level + 1];
+  const int64_t nb = P.S.nb[level];
+  if (nb == 0) return;
+  dim3 grid(static_cast<unsigned>(std::min<int64_t>(nb, 1 << 20)), Lc.nd);
+  k_m2m<<<grid, 64, 0, s>>>(reinterpret_cast<const double2*>(L1.mom64.get()), L1.nd,
+                            P.S.grid[level + 1].get(), P.S.key[level].get(), nb, level,
+                            L1.h, Lc.dirvec.get(), L1.dirvec.get(), Lc.nd, P.l_hf,
+                            P.kappa, P.ip, reinterpret_cast<double2*>(Lc.mom64.get()),
+                            reinterpret_cast<float2*>(Lc.mom32.get()));
+  FDM_LAUNCH("k_m2m");
+}
+
+}  // namespace fdm

@@ -1,0 +1,190 @@
+"""Thin Python binding of the C ABI in ``include/fdm.h`` (argument marshalling
+only; every step of the method runs in the gfx950 library ``libfdm.so``).
+
+Torch is used for device memory and streams: points and vectors are CUDA
+(HIP) tensors, and calls are enqueued on ``torch.cuda.current_stream()``
+unless a stream is given.  If the library is missing this module raises; it
+never falls back to another implementation.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libfdm.so")
+HEADER = os.path.join(os.path.dirname(_HERE), "include", "fdm.h")
+
+FDM_OK = 0
+STATUS = {0: "FDM_OK", -1: "FDM_ERR_INVALID_ARG", -2: "FDM_ERR_POINT_OUTSIDE_BOX",
+          -3: "FDM_ERR_UNSUPPORTED", -4: "FDM_ERR_OUT_OF_MEMORY", -5: "FDM_ERR_HIP",
+          -6: "FDM_ERR_STATE"}
+PRECISION = {"fp64": 0, "fp32": 1, "bf16x3": 2}
+
+_lib = None
+
+
+class FdmError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{STATUS.get(status, status)}: {message}")
+        self.status = status
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("n_T", ctypes.c_int64), ("n_S", ctypes.c_int64),
+                ("levels", ctypes.c_int32), ("m", ctypes.c_int32),
+                ("K", ctypes.c_int32), ("precision", ctypes.c_int32),
+                ("l_hf", ctypes.c_int32), ("l_min", ctypes.c_int32),
+                ("n_couplings", ctypes.c_int64), ("n_stored_couplings", ctypes.c_int64),
+                ("n_bank_matrices", ctypes.c_int64), ("near_pairs", ctypes.c_int64),
+                ("near_entries", ctypes.c_int64), ("m2l_columns", ctypes.c_int64),
+                ("device_bytes", ctypes.c_int64), ("setup_ms", ctypes.c_double)]
+
+
+def header_functions() -> list[str]:
+    """Names of the functions declared in include/fdm.h."""
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:int|const char\*)\s+(fdm_\w+)\s*\(", text, re.M)))
+
+
+def lib() -> ctypes.CDLL:
+    """Load ``libfdm.so`` (built by ``paper_2004_14229_amd/build.py``)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                           "`python paper_2004_14229_amd/build.py`")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i64, dbl, ci = ctypes.c_void_p, ctypes.c_int64, ctypes.c_double, ctypes.c_int
+    L.fdm_build_tree.argtypes = [vp, i64, vp, i64, dbl, ctypes.POINTER(dbl), ci, ci, ci,
+                                 vp, ctypes.POINTER(vp)]
+    L.fdm_build_tree_ex.argtypes = [vp, i64, vp, i64, dbl, ctypes.POINTER(dbl), ci, ci, ci,
+                                    ci, vp, ctypes.POINTER(vp)]
+    L.fdm_plan_matvec.argtypes = [vp, vp, vp, vp]
+    L.fdm_plan_matvec_c64.argtypes = [vp, vp, vp, vp]
+    L.fdm_plan_destroy.argtypes = [vp]
+    L.fdm_plan_stats.argtypes = [vp, ctypes.POINTER(Stats)]
+    L.fdm_plan_export.argtypes = [vp, ctypes.c_char_p, vp, i64, ctypes.POINTER(i64)]
+    L.fdm_dense_matvec.argtypes = [vp, i64, vp, i64, dbl, vp, vp, vp]
+    L.fdm_last_error.restype = ctypes.c_char_p
+    L.fdm_version.restype = ctypes.c_char_p
+    for f in ("fdm_build_tree", "fdm_build_tree_ex", "fdm_plan_matvec",
+              "fdm_plan_matvec_c64", "fdm_plan_destroy", "fdm_plan_stats",
+              "fdm_plan_export", "fdm_dense_matvec"):
+        getattr(L, f).restype = ci
+    _lib = L
+    return L
+
+
+def _check(status: int) -> None:
+    if status != FDM_OK:
+        raise FdmError(status, lib().fdm_last_error().decode())
+
+
+def _stream_handle(stream):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _ptr(t) -> ctypes.c_void_p:
+    return ctypes.c_void_p(t.data_ptr() if t is not None and t.numel() else 0)
+
+
+def _points(p):
+    import torch
+    if not isinstance(p, torch.Tensor) or not p.is_cuda:
+        raise TypeError("points must be a CUDA tensor")
+    if p.dtype != torch.float64 or p.dim() != 2 or p.shape[1] != 3:
+        raise TypeError("points must be an (n, 3) float64 tensor")
+    return p.contiguous()
+
+
+class Plan:
+    """A built plan of the fast directional matvec (wraps ``fdm_plan*``)."""
+
+    def __init__(self, points_T, points_S, kappa: float, box, levels: int, m: int,
+                 precision: str = "fp64", l_hf: int | None = None, stream=None):
+        pt, ps = _points(points_T), _points(points_S)
+        box_arr = (ctypes.c_double * 6)(*[float(b) for b in box])
+        h = ctypes.c_void_p()
+        st = lib().fdm_build_tree_ex(
+            _ptr(pt), pt.shape[0], _ptr(ps), ps.shape[0], float(kappa), box_arr,
+            int(levels), int(m), PRECISION[precision], -2 if l_hf is None else int(l_hf),
+            _stream_handle(stream), ctypes.byref(h))
+        _check(st)
+        self._h = h
+        self.n_T, self.n_S = pt.shape[0], ps.shape[0]
+        self.precision = precision
+
+    def matvec(self, v, out=None, stream=None):
+        """``y = A~ v`` (complex128, or complex64 in and out)."""
+        import torch
+        if not isinstance(v, torch.Tensor) or not v.is_cuda:
+            raise TypeError("v must be a CUDA tensor")
+        if v.dtype not in (torch.complex128, torch.complex64) or v.shape != (self.n_S,):
+            raise TypeError("v must be a complex128/complex64 vector of length n_S")
+        v = v.contiguous()
+        if out is None:
+            out = torch.empty(self.n_T, dtype=v.dtype, device=v.device)
+        elif out.dtype != v.dtype or out.shape != (self.n_T,) or not out.is_contiguous():
+            raise TypeError("out must be a contiguous vector of length n_T, same dtype as v")
+        fn = lib().fdm_plan_matvec if v.dtype == torch.complex128 else lib().fdm_plan_matvec_c64
+        _check(fn(self._h, _ptr(v), _ptr(out), _stream_handle(stream)))
+        return out
+
+    def stats(self) -> dict:
+        s = Stats()
+        _check(lib().fdm_plan_stats(self._h, ctypes.byref(s)))
+        return {name: getattr(s, name) for name, _ in Stats._fields_}
+
+    def export(self, name: str) -> np.ndarray:
+        size = ctypes.c_int64()
+        _check(lib().fdm_plan_export(self._h, name.encode(), None, 0, ctypes.byref(size)))
+        is_f64 = name.startswith(("dirs_", "mom_", "loc_"))
+        buf = np.zeros(size.value // 8, dtype=np.float64 if is_f64 else np.int64)
+        if size.value:
+            _check(lib().fdm_plan_export(self._h, name.encode(), buf.ctypes.data_as(ctypes.c_void_p),
+                                         size.value, ctypes.byref(size)))
+        if name.startswith(("mom_", "loc_")):
+            return buf.view(np.complex128)
+        if name.startswith("dirs_"):
+            return buf.reshape(-1, 3)
+        if name.startswith("off_"):
+            return buf.reshape(-1, 3)
+        return buf
+
+    def close(self) -> None:
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().fdm_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
+def dense_matvec(points_T, points_S, kappa: float, v, out=None, stream=None):
+    """Dense ``y = A v`` by direct FP64 summation on the GPU."""
+    import torch
+    pt, ps = _points(points_T), _points(points_S)
+    if v.dtype != torch.complex128 or v.shape != (ps.shape[0],):
+        raise TypeError("v must be complex128 of length n_S")
+    v = v.contiguous()
+    if out is None:
+        out = torch.empty(pt.shape[0], dtype=torch.complex128, device=v.device)
+    _check(lib().fdm_dense_matvec(_ptr(pt), pt.shape[0], _ptr(ps), ps.shape[0], float(kappa),
+                                  _ptr(v), _ptr(out), _stream_handle(stream)))
+    return out

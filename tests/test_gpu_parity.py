@@ -1,0 +1,209 @@
+"""Parity of the HIP library (through the C ABI) with the CPU oracle.
+
+Integer structure (trees, block partition, directions) must be bit-exact;
+the plain FP64 product must match the oracle's Alg. 4 to 1e-12 relative l2
+(the two use different but equal phase forms, so they agree to rounding);
+the mixed FP32 coupling step must stay within 1e-6 relative l2.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+from gpu_util import gpu_matvec, gpu_plan, rel, to_dev
+
+pytestmark = pytest.mark.gpu
+
+TOL_FP64 = 1e-12
+TOL_FP32 = 1e-6
+
+CASES = {
+    # name: (n_T, n_S, kappa, levels, m, box)
+    "lowfreq": (300, 260, 4.0, 3, 3, W.UNIT_BOX),
+    "highfreq": (700, 650, 45.0, 4, 3, W.UNIT_BOX),
+    "laplace": (400, 380, 0.0, 3, 4, W.UNIT_BOX),
+    "shifted_box": (333, 517, 9.0, 3, 2, (-2.0, 1.0, 0.5, 2.0, 5.0, 4.5)),
+    "deep_sparse": (150, 170, 30.0, 5, 2, W.UNIT_BOX),
+    "dense_only": (200, 190, 12.0, 1, 3, W.UNIT_BOX),
+    "single_box": (50, 60, 3.0, 0, 2, W.UNIT_BOX),
+    "m1": (300, 300, 10.0, 3, 1, W.UNIT_BOX),
+    "m6": (250, 240, 25.0, 3, 6, W.UNIT_BOX),
+}
+
+
+def case(name):
+    nT, nS, kappa, levels, m, box = CASES[name]
+    seed = sorted(CASES).index(name) + 100
+    return W.random_problem(seed, nT, nS, kappa, levels, m, box)
+
+
+def oracle_plan(P):
+    return oracle.build(P.points_T, P.points_S, P.kappa, P.box, P.levels, P.m)
+
+
+def check_structure(P, gp, op):
+    s = oracle.structure(op)
+    assert gp.export("l_hf")[0] == op.l_hf
+    for key in ("perm_T", "perm_S"):
+        assert np.array_equal(gp.export(key), s[key]), key
+    for l in range(P.levels + 1):
+        for tag in ("T", "S"):
+            for what in ("keys", "start", "count"):
+                k = f"{what}_{tag}{l}"
+                assert np.array_equal(gp.export(k), s[k]), k
+        assert gp.export(f"nc_{l}")[0] == s[f"nc{l}"][0], l
+        assert np.array_equal(gp.export(f"off_{l}"), s[f"off{l}"].reshape(-1, 3)), l
+        assert np.array_equal(gp.export(f"offdir_{l}"), s[f"offdir{l}"]), l
+        assert np.array_equal(gp.export(f"offcnt_{l}"), s[f"offcnt{l}"]), l
+        for tag in ("D_T", "Dh_T", "D_S", "Dh_S"):
+            assert np.array_equal(gp.export(f"{tag}{l}"), s[f"{tag}{l}"]), (tag, l)
+        if l <= op.l_hf:
+            assert np.allclose(gp.export(f"dirs_{l}"), op.dirs.vectors(l), atol=1e-15)
+    assert gp.export("near_pairs")[0] == s["near_pairs"][0]
+    assert gp.export("near_entries")[0] == s["near_entries"][0]
+
+
+@pytest.mark.parametrize("name", sorted(CASES))
+def test_structure_bit_exact(name):
+    P = case(name)
+    check_structure(P, gpu_plan(P), oracle_plan(P))
+
+
+def test_structure_paper_grid_k5():
+    P = W.config("paper_k5")
+    gp = gpu_plan(P)
+    op = oracle_plan(P)
+    check_structure(P, gp, op)
+    st = gp.stats()  # Table 1, k = 5
+    assert st["n_couplings"] == 3096 and st["n_stored_couplings"] == 316
+    assert round(100.0 * st["near_entries"] / 8 ** 10, 2) == 24.41
+
+
+def test_structure_uniform2k():
+    P = W.config("uniform2k")
+    check_structure(P, gpu_plan(P), oracle_plan(P))
+
+
+@pytest.mark.parametrize("name", sorted(CASES))
+def test_fp64_matches_oracle(name):
+    P = case(name)
+    y, _ = gpu_matvec(P)
+    yo = oracle.matvec(oracle_plan(P), P.v)
+    assert rel(y, yo) <= TOL_FP64
+
+
+def test_fp64_uniform2k_and_dense():
+    P = W.config("uniform2k")
+    y, gp = gpu_matvec(P)
+    yo = oracle.matvec(oracle_plan(P), P.v)
+    assert rel(y, yo) <= TOL_FP64
+    yd = oracle.dense_matvec(P.points_T, P.points_S, P.v, P.kappa)
+    assert 1e-5 < rel(y, yd) < 2e-3  # the method's own approximation error
+
+
+def test_fp64_paper_grid_k5():
+    P = W.config("paper_k5")
+    y, _ = gpu_matvec(P)
+    yo = oracle.matvec(oracle_plan(P), P.v)
+    assert rel(y, yo) <= TOL_FP64
+
+
+def test_moments_and_locals_match_oracle():
+    """Per-phase parity: the GPU's centre-relative moments / locals equal the
+    oracle's absolute-phase ones times exp(+i kappa <m_box, c>)."""
+    P = case("highfreq")
+    y, gp = gpu_matvec(P)
+    op = oracle_plan(P)
+    oracle.matvec(op, P.v, keep=True)
+    K = op.K
+    for l in range(P.levels + 1):
+        if not op.BT.adm_t[l].size and not (op.DS[l] | op.DhS[l]).any():
+            continue
+        cv = op.dirs.vectors(l)
+        for kind, T, need, arr in (("mom", op.TS, op.DS[l] | op.DhS[l], op.debug["mom"][l]),
+                                   ("loc", op.TT, op.DT[l] | op.DhT[l], op.debug["loc"][l])):
+            if not need.any():
+                continue
+            g = gp.export(f"{kind}_{l}").reshape(T.keys[l].shape[0], -1, K)
+            b, c = np.nonzero(need)
+            ph = np.exp(1j * P.kappa * np.sum(T.centres(l)[b] * cv[c], axis=1))
+            want = arr[b, c] * ph[:, None]
+            assert rel(g[b, c], want) <= TOL_FP64, (kind, l)
+
+
+def test_fp32_within_bound():
+    for name in ("highfreq", "m6", "laplace"):
+        P = case(name)
+        y, _ = gpu_matvec(P, "fp32")
+        yo = oracle.matvec(oracle_plan(P), P.v)
+        assert rel(y, yo) <= TOL_FP32, name
+
+
+def test_fp32_uniform2k():
+    P = W.config("uniform2k")
+    y, _ = gpu_matvec(P, "fp32")
+    op = oracle_plan(P)
+    yo = oracle.matvec(op, P.v)
+    err = rel(y, yo)
+    emulated = rel(oracle.matvec(op, P.v, m2l="fp32"), yo)
+    assert err <= TOL_FP32
+    assert err <= 10 * emulated  # same order as the emulated FP32 pipeline
+
+
+def test_deterministic_fp64():
+    P = case("highfreq")
+    gp = gpu_plan(P)
+    y1, _ = gpu_matvec(P, plan=gp)
+    y2, _ = gpu_matvec(P, plan=gp)
+    assert np.array_equal(y1, y2)
+
+
+def test_complex64_io():
+    import torch
+    P = case("lowfreq")
+    gp = gpu_plan(P)
+    v32 = P.v.astype(np.complex64)
+    y = gp.matvec(to_dev(v32))
+    torch.cuda.synchronize()
+    yo = oracle.matvec(oracle_plan(P), v32.astype(np.complex128))
+    assert y.dtype == torch.complex64
+    assert rel(y.cpu().numpy().astype(np.complex128), yo) < 1e-6
+
+
+def test_dense_gpu_matches_oracle():
+    import paper_2004_14229_amd as F
+    import torch
+    P = case("lowfreq")
+    y = F.dense_matvec(to_dev(P.points_T), to_dev(P.points_S), P.kappa, to_dev(P.v))
+    torch.cuda.synchronize()
+    yo = oracle.dense_matvec(P.points_T, P.points_S, P.v, P.kappa)
+    assert rel(y.cpu().numpy(), yo) <= 1e-13
+
+
+def test_same_points_zero_diagonal():
+    P = W.random_problem(5, 400, 400, 15.0, 3, 3)
+    P.points_S = P.points_T
+    P.same_points = True
+    y, _ = gpu_matvec(P)
+    yo = oracle.matvec(oracle_plan(P), P.v)
+    assert np.all(np.isfinite(y))
+    assert rel(y, yo) <= TOL_FP64
+
+
+def test_empty_inputs():
+    import paper_2004_14229_amd as F
+    import torch
+    P = W.random_problem(6, 50, 0, 10.0, 3, 2)
+    y, _ = gpu_matvec(P)
+    assert y.shape == (50,) and np.all(y == 0)
+    P = W.random_problem(6, 0, 40, 10.0, 3, 2)
+    y, _ = gpu_matvec(P)
+    assert y.shape == (0,)
+
+
+def test_point_outside_box_is_an_error():
+    import paper_2004_14229_amd as F
+    pts = to_dev(np.array([[0.5, 0.5, 0.5], [0.0, 0.2, 0.3]]))
+    with pytest.raises(F.FdmError) as e:
+        F.Plan(pts, pts, 1.0, W.UNIT_BOX, 2, 2)
+    assert e.value.status == -2
