@@ -111,6 +111,16 @@ int fdm_plan_matvec(fdm_plan* plan, const void* v, void* y, void* stream);
 /* As fdm_plan_matvec with complex64 v and y (FP64 accumulation inside). */
 int fdm_plan_matvec_c64(fdm_plan* plan, const void* v, void* y, void* stream);
 
+/*
+ * Per-phase timing of later matvecs with HIP events recorded on the matvec's
+ * stream (enable != 0 turns it on).  fdm_plan_phase_ms waits for the last
+ * matvec's events and writes 7 values in milliseconds: S2M, M2M, M2L, L2L,
+ * L2T, near field, whole matvec.  FDM_ERR_STATE if timing is off or no
+ * matvec ran since it was enabled.
+ */
+int fdm_plan_set_timing(fdm_plan* plan, int enable);
+int fdm_plan_phase_ms(const fdm_plan* plan, double ms[7]);
+
 /* Free a plan and all its device memory.  NULL is accepted. */
 int fdm_plan_destroy(fdm_plan* plan);
 

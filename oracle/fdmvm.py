@@ -116,6 +116,15 @@ def build(points_T, points_S, kappa, box, levels, m, l_hf=None,
                 DT, DhT, DS, DhS, cdir, rows)
 
 
+def apply_coupling(m, h, o, kappa, c, M, m2l="fp64"):
+    """One group of the coupling step: every admissible block of one level
+    and offset ``o`` shares ``A_{c,t x s}`` (Sect. 2.7); rows of ``M`` are the
+    blocks' source moments, the result rows their contributions to the
+    target locals."""
+    A = coupling_matrix(m, h, o, kappa, c)
+    return emulate.product(A, M, m2l)
+
+
 def _segments(start, count):
     """Tree slots of boxes given their ranges, plus each slot's box."""
     total = int(count.sum())
@@ -226,8 +235,8 @@ def matvec(plan: Plan, v, chunk_points: int = 65536, keep: bool = False,
         for gi in range(uo.shape[0]):
             idx = order[bounds[gi]:bounds[gi + 1]]
             cg = c[idx[0]]
-            A = coupling_matrix(m, h, uo[gi], kappa, cv[cg])
-            loc[level][t[idx], cg] += emulate.product(A, mom[level][s[idx], cg], m2l)
+            loc[level][t[idx], cg] += apply_coupling(m, h, uo[gi], kappa, cv[cg],
+                                                     mom[level][s[idx], cg], m2l)
     loc = [x.astype(np.complex128) for x in loc]
     plan.timings["m2l"] = time.perf_counter() - t2
 

@@ -142,24 +142,36 @@ void plan_matvec(Plan& P, const void* v_user, void* y_user, bool c64, hipStream_
       launch_permute_out(P.y_tree.get(), P.T.perm.get(), P.nT, static_cast<double*>(y_user), s);
     return;
   }
+  auto mark = [&](int i) {
+    if (P.timing) FDM_HIP(hipEventRecord(P.ev[i], s));
+  };
+  mark(0);
   if (c64)
     launch_permute_in_c64(static_cast<const float*>(v_user), P.S.perm.get(), P.nS,
                           P.v_tree.get(), s);
   else
     launch_permute_in(static_cast<const double*>(v_user), P.S.perm.get(), P.nS,
                       P.v_tree.get(), s);
-  if (P.l_min <= p) {
-    launch_s2m(P, s);                                   // forward transformation
+  if (P.l_min <= p) launch_s2m(P, s);                   // forward transformation
+  mark(1);
+  if (P.l_min <= p)
     for (int l = p - 1; l >= P.l_min; --l) launch_m2m(P, l, s);
-    launch_m2l(P, s);                                   // multiplication phase
+  mark(2);
+  if (P.l_min <= p) launch_m2l(P, s);                   // multiplication phase
+  mark(3);
+  if (P.l_min <= p)
     for (int l = P.l_min; l < p; ++l) launch_l2l(P, l, s);  // backward transformation
-  }
+  mark(4);
   launch_l2t(P, s);
+  mark(5);
   launch_p2p(P, s);                                     // near field
+  mark(6);
   if (c64)
     launch_permute_out_c64(P.y_tree.get(), P.T.perm.get(), P.nT, static_cast<float*>(y_user), s);
   else
     launch_permute_out(P.y_tree.get(), P.T.perm.get(), P.nT, static_cast<double*>(y_user), s);
+  mark(7);
+  P.timed_run = P.timing;
   P.has_run = true;
 }
 
@@ -286,10 +298,48 @@ int fdm_plan_matvec_c64(fdm_plan* plan, const void* v, void* y, void* stream) {
   return matvec_entry(plan, v, y, stream, true);
 }
 
+int fdm_plan_set_timing(fdm_plan* plan, int enable) {
+  return guarded([&] {
+    if (!plan) fail(FDM_ERR_INVALID_ARG, "plan is NULL");
+    Plan& P = plan->p;
+    if (enable && !P.timing) {
+      for (auto& e : P.ev) FDM_HIP(hipEventCreate(&e));
+    } else if (!enable && P.timing) {
+      FDM_HIP(hipDeviceSynchronize());
+      for (auto& e : P.ev) {
+        (void)hipEventDestroy(e);
+        e = nullptr;
+      }
+    }
+    P.timing = enable != 0;
+    P.timed_run = false;
+  });
+}
+
+int fdm_plan_phase_ms(const fdm_plan* plan, double ms[7]) {
+  return guarded([&] {
+    if (!plan || !ms) fail(FDM_ERR_INVALID_ARG, "NULL argument");
+    const Plan& P = plan->p;
+    if (!P.timing || !P.timed_run) fail(FDM_ERR_STATE, "no timed matvec");
+    FDM_HIP(hipEventSynchronize(P.ev[7]));
+    const int pairs[6][2] = {{0, 1}, {1, 2}, {2, 3}, {3, 4}, {4, 5}, {5, 6}};
+    for (int i = 0; i < 6; ++i) {
+      float t = 0;
+      FDM_HIP(hipEventElapsedTime(&t, P.ev[pairs[i][0]], P.ev[pairs[i][1]]));
+      ms[i] = t;
+    }
+    float t = 0;
+    FDM_HIP(hipEventElapsedTime(&t, P.ev[0], P.ev[7]));
+    ms[6] = t;
+  });
+}
+
 int fdm_plan_destroy(fdm_plan* plan) {
   return guarded([&] {
     if (!plan) return;
     (void)hipDeviceSynchronize();
+    for (auto& e : plan->p.ev)
+      if (e) (void)hipEventDestroy(e);
     delete plan;
   });
 }

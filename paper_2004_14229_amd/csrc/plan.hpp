@@ -118,6 +118,10 @@ struct Plan {
   double setup_ms = 0;
   bool has_run = false;
 
+  // optional per-phase timing (events on the matvec stream)
+  bool timing = false, timed_run = false;
+  hipEvent_t ev[8] = {};
+
   // structure export (host copies made at build time)
   std::vector<std::vector<int64_t>> off_used;  // per level: x,y,z,count,dir
 };

@@ -70,11 +70,14 @@ def lib() -> ctypes.CDLL:
     L.fdm_plan_stats.argtypes = [vp, ctypes.POINTER(Stats)]
     L.fdm_plan_export.argtypes = [vp, ctypes.c_char_p, vp, i64, ctypes.POINTER(i64)]
     L.fdm_dense_matvec.argtypes = [vp, i64, vp, i64, dbl, vp, vp, vp]
+    L.fdm_plan_set_timing.argtypes = [vp, ci]
+    L.fdm_plan_phase_ms.argtypes = [vp, ctypes.POINTER(dbl)]
     L.fdm_last_error.restype = ctypes.c_char_p
     L.fdm_version.restype = ctypes.c_char_p
     for f in ("fdm_build_tree", "fdm_build_tree_ex", "fdm_plan_matvec",
               "fdm_plan_matvec_c64", "fdm_plan_destroy", "fdm_plan_stats",
-              "fdm_plan_export", "fdm_dense_matvec"):
+              "fdm_plan_export", "fdm_dense_matvec", "fdm_plan_set_timing",
+              "fdm_plan_phase_ms"):
         getattr(L, f).restype = ci
     _lib = L
     return L
@@ -157,6 +160,18 @@ class Plan:
         if name.startswith("off_"):
             return buf.reshape(-1, 3)
         return buf
+
+    PHASES = ("s2m", "m2m", "m2l", "l2l", "l2t", "near", "total")
+
+    def set_timing(self, enable: bool = True) -> None:
+        """Record HIP events around each phase of later matvecs."""
+        _check(lib().fdm_plan_set_timing(self._h, int(enable)))
+
+    def phase_ms(self) -> dict:
+        """Milliseconds per phase of the last timed matvec (waits for it)."""
+        out = (ctypes.c_double * 7)()
+        _check(lib().fdm_plan_phase_ms(self._h, out))
+        return dict(zip(self.PHASES, list(out)))
 
     def close(self) -> None:
         if getattr(self, "_h", None) is not None and self._h.value:

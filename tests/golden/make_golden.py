@@ -1,0 +1,43 @@
+"""Write the stored expected values of the full-size parity tests.
+
+Calls only the oracle (and the seeded input generators): for each named
+workload, Alg. 4 of the oracle (FP64) evaluated at a seeded sample of target
+rows, saved as ``<workload>_rows.npz`` with ``rows`` (user indices) and
+``y`` (complex128).  Run from the repository root:
+
+    python tests/golden/make_golden.py uniform100k uniform1m
+"""
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+sys.path.insert(0, ROOT)
+
+import oracle  # noqa: E402
+import workloads as W  # noqa: E402
+
+SAMPLES = {"uniform100k": 64, "uniform1m": 32, "uniform4m": 8}
+
+
+def sample(name: str, R: int) -> np.ndarray:
+    P = W.config(name)
+    return np.sort(np.random.default_rng(12345).choice(P.points_T.shape[0], R, replace=False))
+
+
+def main(names):
+    for name in names:
+        P = W.config(name)
+        rows = sample(name, SAMPLES[name])
+        t = time.time()
+        y = oracle.sample_rows(P.points_T, P.points_S, P.v, P.kappa, P.box, P.levels,
+                               P.m, rows)
+        out = os.path.join(os.path.dirname(os.path.abspath(__file__)), f"{name}_rows.npz")
+        np.savez(out, rows=rows, y=y)
+        print(f"{name}: {len(rows)} rows in {time.time() - t:.1f} s -> {out}", flush=True)
+
+
+if __name__ == "__main__":
+    main(sys.argv[1:] or ["uniform100k", "uniform1m"])
