@@ -11,7 +11,10 @@ output.  Modes (operands = coupling matrix and moments of one M2L product):
 * ``fp32acc64`` as ``fp32`` but the sum over offsets accumulated in FP64;
 * ``bf16x3``    operands split into BF16 hi + lo parts, products
                 ``hi*hi + hi*lo + lo*hi`` summed in FP32, sum over offsets in
-                FP64.
+                FP64;
+* ``bf16x6``    operands split into BF16 hi + mid + lo parts (24 significant
+                bits), the six products of order <= 2 (hh, hm, mh, hl, mm,
+                lh) summed in FP32, sum over offsets in FP64.
 """
 from __future__ import annotations
 
@@ -34,6 +37,15 @@ def split_bf16(x: np.ndarray):
     return hi, lo
 
 
+def split3_bf16(x: np.ndarray):
+    """x (FP64) = hi + mid + lo + O(2^-25 |x|), each part a BF16 value."""
+    x = np.asarray(x, dtype=np.float64)
+    hi = round_bf16(x.astype(np.float32)).astype(np.float64)
+    mid = round_bf16((x - hi).astype(np.float32)).astype(np.float64)
+    lo = round_bf16((x - hi - mid).astype(np.float32)).astype(np.float64)
+    return hi.astype(np.float32), mid.astype(np.float32), lo.astype(np.float32)
+
+
 def product(A: np.ndarray, M: np.ndarray, mode: str) -> np.ndarray:
     """``M @ A.T`` (rows of moments times coupling) in the given precision."""
     if mode == "fp64":
@@ -51,6 +63,19 @@ def product(A: np.ndarray, M: np.ndarray, mode: str) -> np.ndarray:
 
         re = mm(Mr_h, Mr_l, Ar_h, Ar_l) - mm(Mi_h, Mi_l, Ai_h, Ai_l)
         im = mm(Mr_h, Mr_l, Ai_h, Ai_l) + mm(Mi_h, Mi_l, Ar_h, Ar_l)
+        return (re + 1j * im).astype(np.complex64)
+    if mode == "bf16x6":
+        Ar, Ai = split3_bf16(A.real), split3_bf16(A.imag)
+        Mr, Mi = split3_bf16(M.real), split3_bf16(M.imag)
+
+        def mm6(x, y):
+            h, m, l = x
+            H, Mm, Lo = y
+            return ((h @ H.T) + (h @ Mm.T) + (m @ H.T) + (h @ Lo.T) + (m @ Mm.T) +
+                    (l @ H.T))
+
+        re = mm6(Mr, Ar) - mm6(Mi, Ai)
+        im = mm6(Mr, Ai) + mm6(Mi, Ar)
         return (re + 1j * im).astype(np.complex64)
     raise ValueError(mode)
 

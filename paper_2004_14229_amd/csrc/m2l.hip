@@ -79,11 +79,37 @@ __global__ void k_bank(const int32_t* __restrict__ info,  // per matrix: level, 
   }
 }
 
-// Shared prologue: the block's target boxes and their integer positions.
+// Pointers taken from the per-level descriptors are generic; reading them
+// through the global address space gives global (not flat) loads, which do
+// not count against the LDS wait counter.
+template <class T>
+__device__ __forceinline__ const __attribute__((address_space(1))) T* gmem(const T* p) {
+  return (const __attribute__((address_space(1))) T*)p;
+}
+typedef float f4n __attribute__((ext_vector_type(4)));
+typedef double d2n __attribute__((ext_vector_type(2)));
+
+// 16-byte global load / store through native vector types.
+template <class V>
+__device__ __forceinline__ V gload16(const void* p) {
+  const f4n raw = *gmem(static_cast<const f4n*>(p));
+  V v;
+  __builtin_memcpy(&v, &raw, 16);
+  return v;
+}
+__device__ __forceinline__ void gstore16(void* p, double2 v) {
+  d2n raw;
+  __builtin_memcpy(&raw, &v, 16);
+  *(__attribute__((address_space(1))) d2n*)(p) = raw;
+}
+
+// Shared prologue: the block's target boxes and their integer positions;
+// col[b][j] is the first moment element of target j's source column for the
+// offset held in buffer b (or -1: empty or outside the grid).
 struct TargetTile {
   int32_t t[kNB];
   int32_t x[kNB], y[kNB], z[kNB];
-  int64_t col[kNB];  // first moment element of the source column, or -1
+  int64_t col[2][kNB];
 };
 
 __device__ __forceinline__ void load_targets(TargetTile& S, const M2LItem& it,
@@ -93,14 +119,14 @@ __device__ __forceinline__ void load_targets(TargetTile& S, const M2LItem& it,
     int32_t t = j < it.ntgt ? tgt_list[it.tgt_begin + j] : -1;
     S.t[j] = t;
     int ix = 0, iy = 0, iz = 0;
-    if (t >= 0) demorton3(L.keyT[t], L.level, ix, iy, iz);
+    if (t >= 0) demorton3(gmem(L.keyT)[t], L.level, ix, iy, iz);
     S.x[j] = ix;
     S.y[j] = iy;
     S.z[j] = iz;
   }
 }
 
-__device__ __forceinline__ void source_columns(TargetTile& S, const M2LLevel& L,
+__device__ __forceinline__ void source_columns(TargetTile& S, int buf, const M2LLevel& L,
                                                int4 od, int c, int Kp) {
   const int lim = 1 << L.level;
   for (int j = threadIdx.x; j < kNB; j += blockDim.x) {
@@ -108,194 +134,331 @@ __device__ __forceinline__ void source_columns(TargetTile& S, const M2LLevel& L,
     if (S.t[j] >= 0) {
       const int sx = S.x[j] - od.x, sy = S.y[j] - od.y, sz = S.z[j] - od.z;
       if (sx >= 0 && sy >= 0 && sz >= 0 && sx < lim && sy < lim && sz < lim) {
-        const int32_t sb = L.gridS[morton3(sx, sy, sz, L.level)];
+        const int32_t sb = gmem(L.gridS)[morton3(sx, sy, sz, L.level)];
         if (sb >= 0) col = (int64_t(sb) * L.nd + c) * Kp;
       }
     }
-    S.col[j] = col;
+    S.col[buf][j] = col;
   }
 }
 
-// ---------------------------------------------------------------- FP32 --
-// Each offset's product is summed in its own MFMA accumulator (rounding
-// relative to that product), added to an FP32 total, and every kFlush
-// offsets the total is added to the FP64 result in memory, which this
-// workgroup alone owns.
-constexpr int kKS32 = 16;  // k slab
-constexpr int kFlush = 16;
+// Precision traits of the coupling kernel.  Each wave owns 32 rows of the
+// (padded) coupling matrix and all kNB target columns of the block.
+//  FP32: v_mfma_f32_32x32x2f32, k-step 2, 2 column tiles of 32, k slab 16.
+//  FP64: v_mfma_f64_16x16x4f64, k-step 4, 2 row x 4 column tiles of 16, k slab 8.
+struct F32Traits {
+  using T = float;
+  using V16 = float4;  // 16-byte load unit
+  static constexpr int KS = 16;
+  static constexpr int NACC = 2;  // accumulator tiles per component
+  using Acc = f16v;
+};
+struct F64Traits {
+  using T = double;
+  using V16 = double2;
+  static constexpr int KS = 8;
+  static constexpr int NACC = 8;  // 2 row x 4 column tiles
+  using Acc = d4v;
+};
 
-template <int NCS>
-__device__ __forceinline__ void flush_f32(const f16v (&totr)[NCS], const f16v (&toti)[NCS],
-                                          const TargetTile& S, double2* out, int nd, int c,
-                                          int Kp, int wave, int lane, bool first) {
+template <class Tr>
+struct M2LShared {
+  TargetTile S;
+  typename Tr::T B[2][2][Tr::KS][kNB + 1];  // [buffer][re/im][k][column]
+};
+
+// Moment columns of one k slab: kNB columns x KS complex values, staged in
+// 16-byte pieces, at most one per thread (the workgroup has >= 512 threads).
+template <class Tr>
+__device__ __forceinline__ typename Tr::V16 load_cols(const M2LShared<Tr>& sh, int colbuf,
+                                                      const typename Tr::T* __restrict__ mom,
+                                                      int k0) {
+  using V = typename Tr::V16;
+  constexpr int EPV = sizeof(V) / sizeof(typename Tr::T);
+  constexpr int PPC = Tr::KS * 2 / EPV;  // pieces per column
+  static_assert(kNB * PPC <= 512, "one staged piece per thread");
+  V val{};
+  const int e = threadIdx.x;
+  if (e < kNB * PPC) {
+    const int64_t col = sh.S.col[colbuf][e / PPC];
+    if (col >= 0) val = gload16<V>(mom + 2 * (col + k0) + (e % PPC) * EPV);
+  }
+  return val;
+}
+
+template <class Tr>
+__device__ __forceinline__ void store_cols(M2LShared<Tr>& sh, int buf, typename Tr::V16 val) {
+  using T = typename Tr::T;
+  using V = typename Tr::V16;
+  constexpr int EPV = sizeof(V) / sizeof(T);
+  constexpr int PPC = Tr::KS * 2 / EPV;
+  const int e = threadIdx.x;
+  if (e < kNB * PPC) {
+    const int j = e / PPC, q = e % PPC;
+    const T* v = reinterpret_cast<const T*>(&val);
 #pragma unroll
-  for (int cs = 0; cs < NCS; ++cs) {
+    for (int u = 0; u < EPV / 2; ++u) {
+      const int k = q * (EPV / 2) + u;
+      sh.B[buf][0][k][j] = v[2 * u];
+      sh.B[buf][1][k][j] = v[2 * u + 1];
+    }
+  }
+}
+
+// MFMAs of one k slab for one wave: Re += Ar Br - Ai Bi, Im += Ar Bi + Ai Br.
+// The coupling matrix is read straight from the bank (k-major: a wave's rows
+// of one k are contiguous).
+__device__ __forceinline__ void slab_mfma(d4v (&ar)[8], d4v (&ai)[8],
+                                          const M2LShared<F64Traits>& sh, int buf,
+                                          const double* __restrict__ Ar,
+                                          const double* __restrict__ Ai, int k0, int Kp,
+                                          int wave, int lane) {
+  const int kl = lane / 16, li = lane % 16;
+  double a_r[2][2], a_i[2][2];
+#pragma unroll
+  for (int t = 0; t < 2; ++t)
+#pragma unroll
+    for (int rs = 0; rs < 2; ++rs) {
+      const int64_t ka = int64_t(k0 + 4 * t + kl) * Kp + 32 * wave + 16 * rs + li;
+      a_r[t][rs] = Ar[ka];
+      a_i[t][rs] = Ai[ka];
+    }
+#pragma unroll
+  for (int t = 0; t < 2; ++t) {
+    const int kk = 4 * t;
+#pragma unroll
+    for (int cs = 0; cs < 4; ++cs) {
+      const double b_r = sh.B[buf][0][kk + kl][16 * cs + li];
+      const double b_i = sh.B[buf][1][kk + kl][16 * cs + li];
+#pragma unroll
+      for (int rs = 0; rs < 2; ++rs) {
+        d4v& cr = ar[rs * 4 + cs];
+        d4v& ci = ai[rs * 4 + cs];
+        cr = __builtin_amdgcn_mfma_f64_16x16x4f64(a_r[t][rs], b_r, cr, 0, 0, 0);
+        cr = __builtin_amdgcn_mfma_f64_16x16x4f64(-a_i[t][rs], b_i, cr, 0, 0, 0);
+        ci = __builtin_amdgcn_mfma_f64_16x16x4f64(a_r[t][rs], b_i, ci, 0, 0, 0);
+        ci = __builtin_amdgcn_mfma_f64_16x16x4f64(a_i[t][rs], b_r, ci, 0, 0, 0);
+      }
+    }
+  }
+}
+
+// Add (or, for the first flush, store) a wave's accumulated totals into the
+// FP64 result of its rows and the block's targets.
+__device__ __forceinline__ void flush_rows(const f16v (&tr)[2], const f16v (&ti)[2],
+                                           const TargetTile& S, double2* out, int nd, int c,
+                                           int Kp, int wave, int lane, bool first) {
+#pragma unroll
+  for (int cs = 0; cs < 2; ++cs) {
     const int32_t t = S.t[32 * cs + (lane % 32)];
     if (t < 0) continue;
     double2* dst = out + (int64_t(t) * nd + c) * Kp;
 #pragma unroll
     for (int i = 0; i < 16; ++i) {
       const int r = 32 * wave + 8 * (i / 4) + 4 * (lane / 32) + (i % 4);
-      double2 v = make_double2(totr[cs][i], toti[cs][i]);
+      double2 v = make_double2(tr[cs][i], ti[cs][i]);
       if (!first) {
-        const double2 o = dst[r];
+        const double2 o = gload16<double2>(dst + r);
         v.x += o.x;
         v.y += o.y;
       }
-      dst[r] = v;
+      gstore16(dst + r, v);
     }
   }
 }
+
+__device__ __forceinline__ void flush_rows(const d4v (&tr)[8], const d4v (&ti)[8],
+                                           const TargetTile& S, double2* out, int nd, int c,
+                                           int Kp, int wave, int lane, bool first) {
+#pragma unroll
+  for (int cs = 0; cs < 4; ++cs) {
+    const int32_t t = S.t[16 * cs + (lane % 16)];
+    if (t < 0) continue;
+    double2* dst = out + (int64_t(t) * nd + c) * Kp;
+#pragma unroll
+    for (int rs = 0; rs < 2; ++rs)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int r = 32 * wave + 16 * rs + lane / 16 + 4 * i;
+        double2 v = make_double2(tr[rs * 4 + cs][i], ti[rs * 4 + cs][i]);
+        if (!first) {
+          const double2 o = gload16<double2>(dst + r);
+          v.x += o.x;
+          v.y += o.y;
+        }
+        gstore16(dst + r, v);
+      }
+  }
+}
+
+template <class A>
+__device__ __forceinline__ void zero(A& a) {
+  for (auto& x : a)
+#pragma unroll
+    for (int i = 0; i < static_cast<int>(sizeof(x) / sizeof(x[0])); ++i) x[i] = 0;
+}
+
+// The FP64 coupling kernel.  One pipeline step = one (offset, k slab): the
+// next step's moment columns are loaded into a register before this step's
+// MFMAs and stored to the other LDS buffer after them; one barrier ends each
+// step.  One FP64 accumulator chain per (row, target).
+__global__ void __launch_bounds__(kM2LMaxThreads) k_m2l_f64(
+    const M2LItem* __restrict__ items, const M2LLevel* __restrict__ lv,
+    const int32_t* __restrict__ tgt_list, const int32_t* __restrict__ valid_off,
+    const int4* __restrict__ offtab, const double* __restrict__ bank, int Kp) {
+  using Tr = F64Traits;
+  __shared__ M2LShared<Tr> sh;
+  const M2LItem it = items[blockIdx.x];
+  const M2LLevel L = lv[it.level];
+  const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+  const bool rows_here = 32 * wave < Kp;  // waves past Kp only help with loads
+  load_targets(sh.S, it, L, tgt_list);
+  __syncthreads();
+  double2* out = static_cast<double2*>(L.out);
+  d4v acr[Tr::NACC], aci[Tr::NACC];
+  zero(acr);
+  zero(aci);
+  const int nv = it.vo_count;
+  if (nv > 0) {
+    const double* mom = static_cast<const double*>(L.mom);
+    const int64_t per = int64_t(Kp) * Kp;
+    const int ns = Kp / Tr::KS;  // k slabs per offset (>= 2)
+    const int total = nv * ns;
+    int4 od_cur = offtab[valid_off[it.vo_begin]];
+    int4 od_next = od_cur;
+    source_columns(sh.S, 0, L, od_cur, it.c, Kp);
+    __syncthreads();
+    store_cols<Tr>(sh, 0, load_cols<Tr>(sh, 0, mom, 0));
+    __syncthreads();
+    for (int q = 0; q < total; ++q) {
+      const int v = q / ns, s = q % ns, cur = q & 1;
+      if (s == 0) {
+        od_cur = od_next;
+        if (v + 1 < nv) {  // source columns of the next offset
+          od_next = offtab[valid_off[it.vo_begin + v + 1]];
+          source_columns(sh.S, (v + 1) & 1, L, od_next, it.c, Kp);
+        }
+      }
+      const bool more = q + 1 < total;
+      double2 nxt{};
+      if (more) nxt = load_cols<Tr>(sh, ((q + 1) / ns) & 1, mom, ((q + 1) % ns) * Tr::KS);
+      if (rows_here) {
+        const double* Ar = bank + int64_t(od_cur.w) * 2 * per;
+        slab_mfma(acr, aci, sh, cur, Ar, Ar + per, s * Tr::KS, Kp, wave, lane);
+      }
+      if (more) store_cols<Tr>(sh, cur ^ 1, nxt);
+      __syncthreads();
+    }
+  }
+  if (rows_here) flush_rows(acr, aci, sh.S, out, L.nd, it.c, Kp, wave, lane, true);
+}
+
+__device__ __forceinline__ void load_a32(float (&a)[2][8], const float* __restrict__ Ar,
+                                         int64_t per, int k0, int Kp, int wave, int lane) {
+  const int r = 32 * wave + (lane % 32), kl = lane / 32;
+#pragma unroll
+  for (int t = 0; t < 8; ++t) {
+    const int64_t ka = int64_t(k0 + 2 * t + kl) * Kp + r;
+    a[0][t] = Ar[ka];
+    a[1][t] = Ar[per + ka];
+  }
+}
+
+__device__ __forceinline__ void mfma32(f16v (&ar)[2], f16v (&ai)[2], const float (&a)[2][8],
+                                       const M2LShared<F32Traits>& sh, int buf, int lane) {
+  const int kl = lane / 32, cl = lane % 32;
+#pragma unroll
+  for (int t = 0; t < 8; ++t) {
+    const int kk = 2 * t;
+#pragma unroll
+    for (int cs = 0; cs < 2; ++cs) {
+      const float b_r = sh.B[buf][0][kk + kl][32 * cs + cl];
+      const float b_i = sh.B[buf][1][kk + kl][32 * cs + cl];
+      ar[cs] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[0][t], b_r, ar[cs], 0, 0, 0);
+      ar[cs] = __builtin_amdgcn_mfma_f32_32x32x2f32(-a[1][t], b_i, ar[cs], 0, 0, 0);
+      ai[cs] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[0][t], b_i, ai[cs], 0, 0, 0);
+      ai[cs] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[1][t], b_r, ai[cs], 0, 0, 0);
+    }
+  }
+}
+
+// The FP32 coupling kernel.  Same pipeline.  Each offset's product is summed
+// in fresh FP32 accumulators (rounding relative to that product, not to the
+// total over all offsets), added to FP32 totals, and every kFlush offsets
+// the totals are added to the FP64 result in memory, which this workgroup
+// alone owns.
+constexpr int kFlush = 16;
 
 __global__ void __launch_bounds__(kM2LMaxThreads) k_m2l_f32(
     const M2LItem* __restrict__ items, const M2LLevel* __restrict__ lv,
     const int32_t* __restrict__ tgt_list, const int32_t* __restrict__ valid_off,
     const int4* __restrict__ offtab, const float* __restrict__ bank, int Kp) {
-  constexpr int NCS = kNB / 32;
-  __shared__ TargetTile S;
-  __shared__ float Bs[2][kKS32][kNB + 1];
+  using Tr = F32Traits;
+  __shared__ M2LShared<Tr> sh;
   const M2LItem it = items[blockIdx.x];
   const M2LLevel L = lv[it.level];
   const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
-  const int nthr = blockDim.x;
-  load_targets(S, it, L, tgt_list);
+  const bool rows_here = 32 * wave < Kp;
+  load_targets(sh.S, it, L, tgt_list);
   __syncthreads();
+  double2* out = static_cast<double2*>(L.out);
+  f16v acr[2], aci[2], tor[2], toi[2];
+  zero(acr);
+  zero(aci);
+  const int nv = it.vo_count;
+  if (nv == 0) {  // no source box: the result is zero
+    if (rows_here) flush_rows(acr, aci, sh.S, out, L.nd, it.c, Kp, wave, lane, true);
+    return;
+  }
+  zero(tor);
+  zero(toi);
   const float* mom = static_cast<const float*>(L.mom);
-  double2* out = static_cast<double2*>(L.out);
   const int64_t per = int64_t(Kp) * Kp;
-  f16v accr[NCS], acci[NCS], totr[NCS], toti[NCS];
-  for (int cs = 0; cs < NCS; ++cs)
-    for (int i = 0; i < 16; ++i) totr[cs][i] = toti[cs][i] = 0.0f;
-  const int row = 32 * wave + (lane % 32);
-  const int kl = lane / 32;
-  bool first = true;
-  for (int v = 0; v < it.vo_count; ++v) {
-    const int4 od = offtab[valid_off[it.vo_begin + v]];
-    __syncthreads();
-    source_columns(S, L, od, it.c, Kp);
-    const float* Ar = bank + int64_t(od.w) * 2 * per;
-    const float* Ai = Ar + per;
-    for (int cs = 0; cs < NCS; ++cs)
-      for (int i = 0; i < 16; ++i) accr[cs][i] = acci[cs][i] = 0.0f;
-    for (int k0 = 0; k0 < Kp; k0 += kKS32) {
-      __syncthreads();
-      for (int e = threadIdx.x; e < kNB * (kKS32 / 2); e += nthr) {
-        const int j = e / (kKS32 / 2), q = e % (kKS32 / 2);
-        const int64_t col = S.col[j];
-        float4 val = make_float4(0.f, 0.f, 0.f, 0.f);
-        if (col >= 0) val = *reinterpret_cast<const float4*>(mom + 2 * (col + k0 + 2 * q));
-        Bs[0][2 * q][j] = val.x;
-        Bs[1][2 * q][j] = val.y;
-        Bs[0][2 * q + 1][j] = val.z;
-        Bs[1][2 * q + 1][j] = val.w;
-      }
-      __syncthreads();
-#pragma unroll
-      for (int kk = 0; kk < kKS32; kk += 2) {
-        const int64_t ka = int64_t(k0 + kk + kl) * Kp + row;
-        const float ar = Ar[ka], ai = Ai[ka];
-#pragma unroll
-        for (int cs = 0; cs < NCS; ++cs) {
-          const float br = Bs[0][kk + kl][32 * cs + (lane % 32)];
-          const float bi = Bs[1][kk + kl][32 * cs + (lane % 32)];
-          accr[cs] = __builtin_amdgcn_mfma_f32_32x32x2f32(ar, br, accr[cs], 0, 0, 0);
-          accr[cs] = __builtin_amdgcn_mfma_f32_32x32x2f32(-ai, bi, accr[cs], 0, 0, 0);
-          acci[cs] = __builtin_amdgcn_mfma_f32_32x32x2f32(ar, bi, acci[cs], 0, 0, 0);
-          acci[cs] = __builtin_amdgcn_mfma_f32_32x32x2f32(ai, br, acci[cs], 0, 0, 0);
-        }
-      }
-    }
-    for (int cs = 0; cs < NCS; ++cs) {
-      totr[cs] += accr[cs];
-      toti[cs] += acci[cs];
-    }
-    if ((v + 1) % kFlush == 0 || v + 1 == it.vo_count) {
-      flush_f32(totr, toti, S, out, L.nd, it.c, Kp, wave, lane, first);
-      first = false;
-      for (int cs = 0; cs < NCS; ++cs)
-        for (int i = 0; i < 16; ++i) totr[cs][i] = toti[cs][i] = 0.0f;
-    }
-  }
-  if (first) flush_f32(totr, toti, S, out, L.nd, it.c, Kp, wave, lane, true);  // no offsets: zeros
-}
-
-// ---------------------------------------------------------------- FP64 --
-constexpr int kKS64 = 16;
-__global__ void __launch_bounds__(kM2LMaxThreads) k_m2l_f64(
-    const M2LItem* __restrict__ items, const M2LLevel* __restrict__ lv,
-    const int32_t* __restrict__ tgt_list, const int32_t* __restrict__ valid_off,
-    const int4* __restrict__ offtab, const double* __restrict__ bank, int Kp) {
-  constexpr int NCS = kNB / 16;
-  __shared__ TargetTile S;
-  __shared__ double Bs[2][kKS64][kNB + 1];
-  const M2LItem it = items[blockIdx.x];
-  const M2LLevel L = lv[it.level];
-  const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
-  const int nthr = blockDim.x;
-  load_targets(S, it, L, tgt_list);
+  const int ns = Kp / Tr::KS;  // k slabs per offset (>= 2)
+  const int total = nv * ns;
+  int4 od_cur = offtab[valid_off[it.vo_begin]];
+  int4 od_next = od_cur;
+  source_columns(sh.S, 0, L, od_cur, it.c, Kp);
   __syncthreads();
-  const double* mom = static_cast<const double*>(L.mom);
-  const int64_t per = int64_t(Kp) * Kp;
-  d4v accr[2][NCS], acci[2][NCS];
-  for (int rs = 0; rs < 2; ++rs)
-    for (int cs = 0; cs < NCS; ++cs)
-      for (int i = 0; i < 4; ++i) accr[rs][cs][i] = acci[rs][cs][i] = 0.0;
-  const int kl = lane / 16, li = lane % 16;
-  for (int v = 0; v < it.vo_count; ++v) {
-    const int4 od = offtab[valid_off[it.vo_begin + v]];
-    __syncthreads();
-    source_columns(S, L, od, it.c, Kp);
-    const double* Ar = bank + int64_t(od.w) * 2 * per;
-    const double* Ai = Ar + per;
-    for (int k0 = 0; k0 < Kp; k0 += kKS64) {
-      __syncthreads();
-      for (int e = threadIdx.x; e < kNB * kKS64; e += nthr) {
-        const int j = e / kKS64, q = e % kKS64;
-        const int64_t col = S.col[j];
-        double2 val = make_double2(0.0, 0.0);
-        if (col >= 0) val = *reinterpret_cast<const double2*>(mom + 2 * (col + k0 + q));
-        Bs[0][q][j] = val.x;
-        Bs[1][q][j] = val.y;
+  store_cols<Tr>(sh, 0, load_cols<Tr>(sh, 0, mom, 0));
+  __syncthreads();
+  bool first = true;
+  for (int q = 0; q < total; ++q) {
+    const int v = q / ns, s = q % ns, cur = q & 1;
+    if (s == 0) {
+      od_cur = od_next;
+      if (v + 1 < nv) {  // source columns of the next offset
+        od_next = offtab[valid_off[it.vo_begin + v + 1]];
+        source_columns(sh.S, (v + 1) & 1, L, od_next, it.c, Kp);
       }
-      __syncthreads();
+    }
+    const bool more = q + 1 < total;
+    float4 nxt{};
+    if (more) nxt = load_cols<Tr>(sh, ((q + 1) / ns) & 1, mom, ((q + 1) % ns) * Tr::KS);
+    if (rows_here) {
+      if (s == 0) {
+        zero(acr);
+        zero(aci);
+      }
+      float a[2][8];
+      load_a32(a, bank + int64_t(od_cur.w) * 2 * per, per, s * Tr::KS, Kp, wave, lane);
+      mfma32(acr, aci, a, sh, cur, lane);
+      if (s == ns - 1) {
 #pragma unroll
-      for (int kk = 0; kk < kKS64; kk += 4) {
-        double ar[2], ai[2];
-#pragma unroll
-        for (int rs = 0; rs < 2; ++rs) {
-          const int64_t ka = int64_t(k0 + kk + kl) * Kp + 32 * wave + 16 * rs + li;
-          ar[rs] = Ar[ka];
-          ai[rs] = Ai[ka];
+        for (int c2 = 0; c2 < 2; ++c2) {
+          tor[c2] += acr[c2];
+          toi[c2] += aci[c2];
         }
-#pragma unroll
-        for (int cs = 0; cs < NCS; ++cs) {
-          const double br = Bs[0][kk + kl][16 * cs + li];
-          const double bi = Bs[1][kk + kl][16 * cs + li];
-#pragma unroll
-          for (int rs = 0; rs < 2; ++rs) {
-            accr[rs][cs] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[rs], br, accr[rs][cs], 0, 0, 0);
-            accr[rs][cs] = __builtin_amdgcn_mfma_f64_16x16x4f64(-ai[rs], bi, accr[rs][cs], 0, 0, 0);
-            acci[rs][cs] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[rs], bi, acci[rs][cs], 0, 0, 0);
-            acci[rs][cs] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai[rs], br, acci[rs][cs], 0, 0, 0);
-          }
+        if ((v + 1) % kFlush == 0 || v + 1 == nv) {
+          flush_rows(tor, toi, sh.S, out, L.nd, it.c, Kp, wave, lane, first);
+          first = false;
+          zero(tor);
+          zero(toi);
         }
       }
     }
-  }
-  double2* out = static_cast<double2*>(L.out);
-#pragma unroll
-  for (int cs = 0; cs < NCS; ++cs) {
-    const int j = 16 * cs + li;
-    const int32_t t = S.t[j];
-    if (t < 0) continue;
-    double2* dst = out + (int64_t(t) * L.nd + it.c) * Kp;
-#pragma unroll
-    for (int rs = 0; rs < 2; ++rs)
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int r = 32 * wave + 16 * rs + kl + 4 * i;
-        dst[r] = make_double2(accr[rs][cs][i], acci[rs][cs][i]);
-      }
+    if (more) store_cols<Tr>(sh, cur ^ 1, nxt);
+    __syncthreads();
   }
 }
 
@@ -508,7 +671,7 @@ void build_m2l_work(Plan& P, hipStream_t s) {
 
 void launch_m2l(Plan& P, hipStream_t s) {
   if (P.n_items == 0) return;
-  const int threads = 2 * P.ip.Kp;  // one wave per 32 rows
+  const int threads = std::max(2 * P.ip.Kp, 512);  // one wave per 32 rows, >= 8 waves
   if (P.prec == FDM_PREC_FP64) {
     k_m2l_f64<<<static_cast<unsigned>(P.n_items), threads, 0, s>>>(
         P.items.get(), P.m2l_levels.get(), P.tgt_list.get(), P.valid_off.get(),

@@ -1,0 +1,57 @@
+"""Full-size parity: the HIP library at the benchmark workloads against the
+FP64 oracle's Alg. 4 on stored sampled rows (tests/golden/*_rows.npz, written
+by tests/golden/make_golden.py from the oracle alone).
+
+Tolerances: plain FP64 1e-12 relative l2 over the sampled rows; mixed FP32
+1e-6 (the stated bound of the mixed path); the FP32 result also against the
+plain GPU result on the full vector.
+"""
+import os
+
+import numpy as np
+import pytest
+
+import workloads as W
+from gpu_util import gpu_plan, rel, to_dev
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+_cache = {}
+
+
+def run(name, prec):
+    import torch
+    key = (name, prec)
+    if key not in _cache:
+        P = W.config(name)
+        with gpu_plan(P, prec) as plan:
+            y = plan.matvec(to_dev(P.v))
+            torch.cuda.synchronize()
+            _cache[key] = (y.cpu().numpy(), plan.stats())
+        del y
+        torch.cuda.empty_cache()
+    return _cache[key]
+
+
+def golden(name):
+    g = np.load(os.path.join(GOLDEN, f"{name}_rows.npz"))
+    return g["rows"], g["y"]
+
+
+@pytest.mark.parametrize("name", ["uniform100k", "uniform1m"])
+def test_fp64_sampled_rows(name):
+    rows, yo = golden(name)
+    y, st = run(name, "fp64")
+    assert rel(y[rows], yo) <= 1e-12
+    assert np.all(np.isfinite(y))
+
+
+@pytest.mark.parametrize("name", ["uniform100k", "uniform1m"])
+def test_fp32_sampled_rows_and_full_vector(name):
+    rows, yo = golden(name)
+    y32, st = run(name, "fp32")
+    assert rel(y32[rows], yo) <= 1e-6
+    y64, _ = run(name, "fp64")
+    assert rel(y32, y64) <= 1e-6
+    _cache.pop((name, "fp64"), None)
