@@ -583,18 +583,22 @@ void build_m2l_work(Plan& P, hipStream_t s) {
     std::vector<uint32_t> keys = to_host(P.T.key[l].get(), P.T.nb[l], s);
     std::vector<std::vector<int32_t>> by_oct(8);
     for (size_t b = 0; b < keys.size(); ++b) by_oct[keys[b] & 7].push_back(static_cast<int32_t>(b));
+    // items ordered (octant, direction, block): one group per (octant,
+    // direction), blocks in Morton order within a group
     for (int q = 0; q < 8; ++q) {
       const auto& bx = by_oct[q];
+      std::vector<std::pair<int32_t, int32_t>> blocks;  // (tgt_begin, ntgt)
       for (size_t b0 = 0; b0 < bx.size(); b0 += kNB) {
         const int nt = static_cast<int>(std::min<size_t>(kNB, bx.size() - b0));
-        const int32_t tb = static_cast<int32_t>(tgt_list.size());
+        blocks.push_back({static_cast<int32_t>(tgt_list.size()), nt});
         tgt_list.insert(tgt_list.end(), bx.begin() + b0, bx.begin() + b0 + nt);
-        for (int c = 0; c < Ld.nd; ++c) {
+      }
+      for (int c = 0; c < Ld.nd; ++c)
+        for (auto [tb, nt] : blocks) {
           items.push_back(M2LItem{l, c, tb, nt, 0, 0});
           cand_begin_per_item.push_back(list_begin[q * Ld.nd + c]);
           cand_count_per_item.push_back(static_cast<int32_t>(lists[q * Ld.nd + c].size()));
         }
-      }
     }
   }
   P.n_items = static_cast<int64_t>(items.size());
@@ -637,11 +641,13 @@ void build_m2l_work(Plan& P, hipStream_t s) {
                                    P.valid_off.get(), d_bpo.get());
   FDM_LAUNCH("k_valid_offsets");
   std::vector<unsigned long long> bpo = to_host(d_bpo.get(), P.n_bank, s);
-  // finish the items: offset ranges, heaviest first (longest-processing-time order)
+  // finish the items: offset ranges
   for (int64_t i = 0; i < P.n_items; ++i) {
     items[i].vo_begin = begin[i];
     items[i].vo_count = counts[i];
   }
+  // heaviest items first (longest-processing-time order): measured faster
+  // than keeping items of one offset group together on one XCD
   std::stable_sort(items.begin(), items.end(), [](const M2LItem& a, const M2LItem& b) {
     return a.vo_count > b.vo_count;
   });
