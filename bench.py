@@ -25,7 +25,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "matvecs/s at N=1e6 mixed vs FP64 plain; rel l2 err vs FP64 oracle"
 PEAK_TFLOPS = {"fp32": 157.3, "fp64": 78.6, "bf16x3": 2500.0}
-M2L_KERNEL = {"fp32": "k_m2l_f32", "fp64": "k_m2l_f64"}
+M2L_KERNEL = {"fp32": "k_m2l_f32", "fp64": "k_m2l_f64", "bf16x3": "k_m2l_bf16x3"}
 
 
 def parse():
@@ -34,9 +34,11 @@ def parse():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="uniform1m")
-    ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64"])
+    ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64", "bf16x3"])
     ap.add_argument("--plain-steps", type=int, default=1,
                     help="timed steps of the plain FP64 plan (0 = skip)")
+    ap.add_argument("--bf16-steps", type=int, default=1,
+                    help="timed steps of the BF16 split (bf16x3) plan (0 = skip)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-groups", type=int, default=10)
     return ap.parse_args()
@@ -177,12 +179,15 @@ def main():
            "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
            "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
            "vs_baseline": None,
-           "dtype": "f32" if args.precision == "fp32" else "f64",
+           "dtype": {"fp32": "f32", "fp64": "f64", "bf16x3": "bf16"}[args.precision],
            "data": "synthetic",
            "config": {"workload": describe(P),
-                      "precision": ("FP32 coupling products on MFMA, FP64 phases, "
-                                    "transfers, near field and sums into y"
-                                    if args.precision == "fp32" else "FP64 throughout")}}
+                      "precision": {
+                          "fp32": "FP32 coupling products on MFMA, FP64 phases, transfers, "
+                                  "near field and sums into y",
+                          "bf16x3": "BF16 hi/lo split coupling products (3 per real "
+                                    "product) on MFMA with FP32 sums, FP64 elsewhere",
+                          "fp64": "FP64 throughout"}[args.precision]}}
     out["roofline"] = {"bound": "mfma", "kernel": M2L_KERNEL[args.precision],
                        "achieved": achieved, "peak": PEAK_TFLOPS[args.precision],
                        "unit": "TFLOP/s", "frac": achieved / PEAK_TFLOPS[args.precision],
@@ -217,6 +222,30 @@ def main():
             out["plain_fp64"]["rel_l2_err_vs_oracle"] = float(
                 np.linalg.norm(y_plain[rows] - yo) / np.linalg.norm(yo))
         print(f"[bench] fp64 plain: {pms:.1f} ms/matvec", file=sys.stderr, flush=True)
+
+    if args.bf16_steps > 0 and args.precision != "bf16x3":
+        bf = F.Plan(pt, ps, P.kappa, P.box, P.levels, P.m, precision="bf16x3")
+        bwall, bph = time_plan(bf, v, y, args.bf16_steps, 1)
+        y_bf = y.cpu().numpy()
+        bf.close()
+        del bf
+        bms = 1000.0 * bwall / args.bf16_steps
+        bm2l = float(np.mean([p["m2l"] for p in bph]))
+        alg = flops / (bm2l * 1e-3) / 1e12
+        out["bf16x3"] = {"value": 1000.0 / bms, "ms_per_step": bms, "steps": args.bf16_steps,
+                         "m2l_ms": bm2l, "m2l_tflops_algorithmic": alg,
+                         "m2l_tflops_issued": 3.0 * alg,
+                         "frac_of_bf16_peak_issued": 3.0 * alg / PEAK_TFLOPS["bf16x3"],
+                         "speedup_vs_mixed": ms_per_step / bms}
+        if os.path.exists(golden):
+            g = np.load(golden)
+            out["bf16x3"]["rel_l2_err_vs_oracle"] = float(
+                np.linalg.norm(y_bf[rows] - yo) / np.linalg.norm(yo))
+            if "y_bf16x3" in g.files:
+                out["bf16x3"]["emulated_rel_l2_err"] = float(
+                    np.linalg.norm(g["y_bf16x3"] - yo) / np.linalg.norm(yo))
+        print(f"[bench] bf16x3: {bms:.1f} ms/matvec, M2L {bm2l:.1f} ms", file=sys.stderr,
+              flush=True)
 
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(P, stats, args.cpu_groups)

@@ -19,6 +19,7 @@
 // Wave w owns rows 32w .. 32w+31 of the (padded) K rows.
 #include <algorithm>
 #include <numeric>
+#include <type_traits>
 
 #include "plan.hpp"
 #include "device_math.hpp"
@@ -37,7 +38,31 @@ struct BankLevel {
   const double* dirvec;
 };
 
-// Coupling matrices in the layout of the plan precision.
+// BF16 (bfloat16) helpers: round to nearest even of an FP32 value, as the
+// raw 16 bits, and the value of such bits.  Finite inputs only.
+__device__ __forceinline__ uint16_t bf16_bits(float x) {
+  uint32_t u = __float_as_uint(x);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return static_cast<uint16_t>(u >> 16);
+}
+__device__ __forceinline__ float bf16_value(uint16_t b) {
+  return __uint_as_float(static_cast<uint32_t>(b) << 16);
+}
+
+// Position of element (row, k) of one BF16 plane: for each k step of 16 and
+// block of 32 rows, the 64 lanes' 8-element A operands of
+// v_mfma_f32_32x32x16_bf16 (lane = row % 32 + 32 * (k % 16 >= 8)) are
+// contiguous, so one wave reads one step of its rows as 1 KiB in a row.
+__host__ __device__ __forceinline__ int64_t frag_index(int row, int k, int Kp) {
+  const int ks = k / 16, kr = k % 16;
+  const int lane = row % 32 + 32 * (kr / 8);
+  return ((int64_t(ks) * (Kp / 32) + row / 32) * 64 + lane) * 8 + (kr % 8);
+}
+
+// Coupling matrices in the layout of the plan precision: FP64 or FP32 split
+// re/im planes, k-major; or, for the BF16 split precision, each FP32-rounded
+// part split into hi = bf16(x) and lo = bf16(x - hi), four planes in
+// fragment order.
 template <class T>
 __global__ void k_bank(const int32_t* __restrict__ info,  // per matrix: level, ox, oy, oz, c
                        int64_t n_mat, const BankLevel* __restrict__ lv, double kappa,
@@ -73,9 +98,21 @@ __global__ void k_bank(const int32_t* __restrict__ info,  // per matrix: level, 
       re = cs * w;
       im = sn * w;
     }
-    T* base = bank + id * 2 * per;
-    base[int64_t(kk) * Kp + row] = static_cast<T>(re);
-    base[per + int64_t(kk) * Kp + row] = static_cast<T>(im);
+    if constexpr (std::is_same<T, uint16_t>::value) {
+      // four planes (re hi, re lo, im hi, im lo) in MFMA operand order
+      T* base = bank + id * 4 * per;
+      const int64_t f = frag_index(row, kk, Kp);
+      const float fr = static_cast<float>(re), fi = static_cast<float>(im);
+      const uint16_t rh = bf16_bits(fr), ih = bf16_bits(fi);
+      base[f] = rh;
+      base[per + f] = bf16_bits(fr - bf16_value(rh));
+      base[2 * per + f] = ih;
+      base[3 * per + f] = bf16_bits(fi - bf16_value(ih));
+    } else {
+      T* base = bank + id * 2 * per;
+      base[int64_t(kk) * Kp + row] = static_cast<T>(re);
+      base[per + int64_t(kk) * Kp + row] = static_cast<T>(im);
+    }
   }
 }
 
@@ -170,7 +207,7 @@ struct M2LShared {
 // Moment columns of one k slab: kNB columns x KS complex values, staged in
 // 16-byte pieces, at most one per thread (the workgroup has >= 512 threads).
 template <class Tr>
-__device__ __forceinline__ typename Tr::V16 load_cols(const M2LShared<Tr>& sh, int colbuf,
+__device__ __forceinline__ typename Tr::V16 load_cols(const TargetTile& S, int colbuf,
                                                       const typename Tr::T* __restrict__ mom,
                                                       int k0) {
   using V = typename Tr::V16;
@@ -180,7 +217,7 @@ __device__ __forceinline__ typename Tr::V16 load_cols(const M2LShared<Tr>& sh, i
   V val{};
   const int e = threadIdx.x;
   if (e < kNB * PPC) {
-    const int64_t col = sh.S.col[colbuf][e / PPC];
+    const int64_t col = S.col[colbuf][e / PPC];
     if (col >= 0) val = gload16<V>(mom + 2 * (col + k0) + (e % PPC) * EPV);
   }
   return val;
@@ -328,7 +365,7 @@ __global__ void __launch_bounds__(kM2LMaxThreads) k_m2l_f64(
     int4 od_next = od_cur;
     source_columns(sh.S, 0, L, od_cur, it.c, Kp);
     __syncthreads();
-    store_cols<Tr>(sh, 0, load_cols<Tr>(sh, 0, mom, 0));
+    store_cols<Tr>(sh, 0, load_cols<Tr>(sh.S, 0, mom, 0));
     __syncthreads();
     for (int q = 0; q < total; ++q) {
       const int v = q / ns, s = q % ns, cur = q & 1;
@@ -341,7 +378,7 @@ __global__ void __launch_bounds__(kM2LMaxThreads) k_m2l_f64(
       }
       const bool more = q + 1 < total;
       double2 nxt{};
-      if (more) nxt = load_cols<Tr>(sh, ((q + 1) / ns) & 1, mom, ((q + 1) % ns) * Tr::KS);
+      if (more) nxt = load_cols<Tr>(sh.S, ((q + 1) / ns) & 1, mom, ((q + 1) % ns) * Tr::KS);
       if (rows_here) {
         const double* Ar = bank + int64_t(od_cur.w) * 2 * per;
         slab_mfma(acr, aci, sh, cur, Ar, Ar + per, s * Tr::KS, Kp, wave, lane);
@@ -420,7 +457,7 @@ __global__ void __launch_bounds__(kM2LMaxThreads) k_m2l_f32(
   int4 od_next = od_cur;
   source_columns(sh.S, 0, L, od_cur, it.c, Kp);
   __syncthreads();
-  store_cols<Tr>(sh, 0, load_cols<Tr>(sh, 0, mom, 0));
+  store_cols<Tr>(sh, 0, load_cols<Tr>(sh.S, 0, mom, 0));
   __syncthreads();
   bool first = true;
   for (int q = 0; q < total; ++q) {
@@ -434,7 +471,7 @@ __global__ void __launch_bounds__(kM2LMaxThreads) k_m2l_f32(
     }
     const bool more = q + 1 < total;
     float4 nxt{};
-    if (more) nxt = load_cols<Tr>(sh, ((q + 1) / ns) & 1, mom, ((q + 1) % ns) * Tr::KS);
+    if (more) nxt = load_cols<Tr>(sh.S, ((q + 1) / ns) & 1, mom, ((q + 1) % ns) * Tr::KS);
     if (rows_here) {
       if (s == 0) {
         zero(acr);
@@ -458,6 +495,183 @@ __global__ void __launch_bounds__(kM2LMaxThreads) k_m2l_f32(
       }
     }
     if (more) store_cols<Tr>(sh, cur ^ 1, nxt);
+    __syncthreads();
+  }
+}
+
+// ------------------------------------------------- BF16 split precision --
+// Each real operand x (coupling entry or moment, FP32) is split into two
+// BF16 parts x = hi + lo + O(2^-16 |x|), and a real product X Y is taken as
+// Xh Yh + Xh Yl + Xl Yh (three v_mfma_f32_32x32x16_bf16, FP32 accumulation);
+// the dropped Xl Yl term is of relative size 2^-16.  Complex products as
+// above; the FP32 per-offset sums, FP32 totals and FP64 flushes are those of
+// the FP32 kernel.
+typedef __bf16 bf8v __attribute__((ext_vector_type(8)));
+typedef unsigned int u4v __attribute__((ext_vector_type(4)));
+
+struct BF16Shared {
+  TargetTile S;
+  // [buffer][plane: re hi, re lo, im hi, im lo][column][k]: 16 k per slab,
+  // rows padded to 24 (48 bytes) so that 16 lanes' 16-byte reads of 16
+  // consecutive columns fall in distinct banks
+  alignas(16) uint16_t B[2][4][kNB][24];
+};
+constexpr int kBKS = 16;  // k per slab
+
+__device__ __forceinline__ void store_cols_bf16(BF16Shared& sh, int buf, float4 val) {
+  const int e = threadIdx.x;
+  if (e < kNB * 8) {  // piece e: column e / 8, k = 2 (e % 8) and 2 (e % 8) + 1
+    const int j = e / 8, k = 2 * (e % 8);
+    const uint16_t rh0 = bf16_bits(val.x), ih0 = bf16_bits(val.y);
+    const uint16_t rh1 = bf16_bits(val.z), ih1 = bf16_bits(val.w);
+    const uint16_t rl0 = bf16_bits(val.x - bf16_value(rh0));
+    const uint16_t il0 = bf16_bits(val.y - bf16_value(ih0));
+    const uint16_t rl1 = bf16_bits(val.z - bf16_value(rh1));
+    const uint16_t il1 = bf16_bits(val.w - bf16_value(ih1));
+    auto put = [&](int plane, uint16_t a, uint16_t b) {
+      *reinterpret_cast<uint32_t*>(&sh.B[buf][plane][j][k]) =
+          uint32_t(a) | (uint32_t(b) << 16);
+    };
+    put(0, rh0, rh1);
+    put(1, rl0, rl1);
+    put(2, ih0, ih1);
+    put(3, il0, il1);
+  }
+}
+
+__device__ __forceinline__ bf8v as_bf8(u4v v) {
+  bf8v r;
+  __builtin_memcpy(&r, &v, 16);
+  return r;
+}
+
+__device__ __forceinline__ bf8v lds_bf8(const uint16_t* p) {
+  return as_bf8(*reinterpret_cast<const u4v*>(p));
+}
+__device__ __forceinline__ bf8v neg_bf8(bf8v x) {
+  const u4v sign = {0x80008000u, 0x80008000u, 0x80008000u, 0x80008000u};
+  u4v u;
+  __builtin_memcpy(&u, &x, 16);
+  return as_bf8(u ^ sign);
+}
+
+// One k slab (one MFMA k step) for one wave: A operands from the bank in
+// fragment order, B operands from LDS.  Two passes keep few operands live:
+// first the A lo parts against the B hi parts, then the A hi parts against
+// both B parts.
+__device__ __forceinline__ void mfma_bf16x3(f16v (&ar)[2], f16v (&ai)[2],
+                                            const uint16_t* __restrict__ A, int64_t per,
+                                            const BF16Shared& sh, int buf, int s, int Kp,
+                                            int wave, int lane) {
+  const int64_t f = ((int64_t(s) * (Kp / 32) + wave) * 64 + lane) * 8;
+  const int kq = 8 * (lane / 32);
+  {
+    const bf8v arl = as_bf8(gload16<u4v>(A + per + f));
+    const bf8v ail = as_bf8(gload16<u4v>(A + 3 * per + f));
+#pragma unroll
+    for (int cs = 0; cs < 2; ++cs) {
+      const int col = 32 * cs + lane % 32;
+      const bf8v brh = lds_bf8(&sh.B[buf][0][col][kq]);
+      const bf8v bih = lds_bf8(&sh.B[buf][2][col][kq]);
+      ar[cs] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(arl, brh, ar[cs], 0, 0, 0);
+      ai[cs] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(arl, bih, ai[cs], 0, 0, 0);
+      ar[cs] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ail, neg_bf8(bih), ar[cs], 0, 0, 0);
+      ai[cs] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ail, brh, ai[cs], 0, 0, 0);
+      __builtin_amdgcn_sched_barrier(0);
+    }
+  }
+  const bf8v arh = as_bf8(gload16<u4v>(A + f));
+  const bf8v aih = as_bf8(gload16<u4v>(A + 2 * per + f));
+#pragma unroll
+  for (int cs = 0; cs < 2; ++cs) {
+    const int col = 32 * cs + lane % 32;
+    const bf8v brh = lds_bf8(&sh.B[buf][0][col][kq]);
+    const bf8v brl = lds_bf8(&sh.B[buf][1][col][kq]);
+    const bf8v bih = lds_bf8(&sh.B[buf][2][col][kq]);
+    const bf8v bil = lds_bf8(&sh.B[buf][3][col][kq]);
+    f16v r = ar[cs], i = ai[cs];
+    r = __builtin_amdgcn_mfma_f32_32x32x16_bf16(arh, brl, r, 0, 0, 0);
+    i = __builtin_amdgcn_mfma_f32_32x32x16_bf16(arh, bil, i, 0, 0, 0);
+    r = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aih, neg_bf8(bil), r, 0, 0, 0);
+    i = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aih, brl, i, 0, 0, 0);
+    r = __builtin_amdgcn_mfma_f32_32x32x16_bf16(arh, brh, r, 0, 0, 0);
+    i = __builtin_amdgcn_mfma_f32_32x32x16_bf16(arh, bih, i, 0, 0, 0);
+    r = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aih, neg_bf8(bih), r, 0, 0, 0);
+    i = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aih, brh, i, 0, 0, 0);
+    ar[cs] = r;
+    ai[cs] = i;
+    __builtin_amdgcn_sched_barrier(0);
+  }
+}
+
+__global__ void __launch_bounds__(kM2LMaxThreads) k_m2l_bf16x3(
+    const M2LItem* __restrict__ items, const M2LLevel* __restrict__ lv,
+    const int32_t* __restrict__ tgt_list, const int32_t* __restrict__ valid_off,
+    const int4* __restrict__ offtab, const uint16_t* __restrict__ bank, int Kp) {
+  __shared__ BF16Shared sh;
+  const M2LItem it = items[blockIdx.x];
+  const M2LLevel L = lv[it.level];
+  const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+  const bool rows_here = 32 * wave < Kp;
+  load_targets(sh.S, it, L, tgt_list);
+  __syncthreads();
+  double2* out = static_cast<double2*>(L.out);
+  f16v acr[2], aci[2], tor[2], toi[2];
+  zero(acr);
+  zero(aci);
+  const int nv = it.vo_count;
+  if (nv == 0) {  // no source box: the result is zero
+    if (rows_here) flush_rows(acr, aci, sh.S, out, L.nd, it.c, Kp, wave, lane, true);
+    return;
+  }
+  zero(tor);
+  zero(toi);
+  const float* mom = static_cast<const float*>(L.mom);
+  const int64_t per = int64_t(Kp) * Kp;
+  const int ns = Kp / kBKS;  // k slabs per offset
+  const int total = nv * ns;
+  int4 od_cur = offtab[valid_off[it.vo_begin]];
+  int4 od_next = od_cur;
+  source_columns(sh.S, 0, L, od_cur, it.c, Kp);
+  __syncthreads();
+  store_cols_bf16(sh, 0, load_cols<F32Traits>(sh.S, 0, mom, 0));
+  __syncthreads();
+  bool first = true;
+  for (int q = 0; q < total; ++q) {
+    const int v = q / ns, s = q % ns, cur = q & 1;
+    if (s == 0) {
+      od_cur = od_next;
+      if (v + 1 < nv) {  // source columns of the next offset
+        od_next = offtab[valid_off[it.vo_begin + v + 1]];
+        source_columns(sh.S, (v + 1) & 1, L, od_next, it.c, Kp);
+      }
+    }
+    const bool more = q + 1 < total;
+    float4 nxt{};
+    if (more)
+      nxt = load_cols<F32Traits>(sh.S, ((q + 1) / ns) & 1, mom, ((q + 1) % ns) * kBKS);
+    if (rows_here) {
+      if (s == 0) {
+        zero(acr);
+        zero(aci);
+      }
+      mfma_bf16x3(acr, aci, bank + int64_t(od_cur.w) * 4 * per, per, sh, cur, s, Kp, wave,
+                  lane);
+      if (s == ns - 1) {
+#pragma unroll
+        for (int c2 = 0; c2 < 2; ++c2) {
+          tor[c2] += acr[c2];
+          toi[c2] += aci[c2];
+        }
+        if ((v + 1) % kFlush == 0 || v + 1 == nv) {
+          flush_rows(tor, toi, sh.S, out, L.nd, it.c, Kp, wave, lane, first);
+          first = false;
+          zero(tor);
+          zero(toi);
+        }
+      }
+    }
+    if (more) store_cols_bf16(sh, cur ^ 1, nxt);
     __syncthreads();
   }
 }
@@ -534,6 +748,10 @@ void launch_bank(Plan& P, hipStream_t s) {
     P.bank64.alloc(2 * total, &P.tally);
     k_bank<double><<<grid_for(total, B), B, 0, s>>>(d_info.get(), P.n_bank, d_bl.get(),
                                                   P.kappa, P.ip, P.bank64.get());
+  } else if (P.prec == FDM_PREC_BF16X3) {
+    P.bank16.alloc(4 * total, &P.tally);
+    k_bank<uint16_t><<<grid_for(total, B), B, 0, s>>>(d_info.get(), P.n_bank, d_bl.get(),
+                                                    P.kappa, P.ip, P.bank16.get());
   } else {
     P.bank32.alloc(2 * total, &P.tally);
     k_bank<float><<<grid_for(total, B), B, 0, s>>>(d_info.get(), P.n_bank, d_bl.get(),
@@ -683,6 +901,11 @@ void launch_m2l(Plan& P, hipStream_t s) {
         P.items.get(), P.m2l_levels.get(), P.tgt_list.get(), P.valid_off.get(),
         P.offtab.get(), P.bank64.get(), P.ip.Kp);
     FDM_LAUNCH("k_m2l_f64");
+  } else if (P.prec == FDM_PREC_BF16X3) {
+    k_m2l_bf16x3<<<static_cast<unsigned>(P.n_items), threads, 0, s>>>(
+        P.items.get(), P.m2l_levels.get(), P.tgt_list.get(), P.valid_off.get(),
+        P.offtab.get(), P.bank16.get(), P.ip.Kp);
+    FDM_LAUNCH("k_m2l_bf16x3");
   } else {
     k_m2l_f32<<<static_cast<unsigned>(P.n_items), threads, 0, s>>>(
         P.items.get(), P.m2l_levels.get(), P.tgt_list.get(), P.valid_off.get(),

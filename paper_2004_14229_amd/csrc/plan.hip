@@ -239,8 +239,6 @@ int fdm_build_tree_ex(const double* points_T, int64_t n_T, const double* points_
     const int K = (m + 1) * (m + 1) * (m + 1);
     if ((K + 31) / 32 * 32 > kMaxKp)
       fail(FDM_ERR_UNSUPPORTED, "m > 6 is not supported by the coupling kernels");
-    if (precision == FDM_PREC_BF16X3)
-      fail(FDM_ERR_UNSUPPORTED, "the BF16 split precision is not built yet");
     if (n_T) check_device_ptr(points_T, "points_T");
     if (n_S) check_device_ptr(points_S, "points_S");
     auto* h = new fdm_plan();

@@ -2,8 +2,10 @@
 
 Calls only the oracle (and the seeded input generators): for each named
 workload, Alg. 4 of the oracle (FP64) evaluated at a seeded sample of target
-rows, saved as ``<workload>_rows.npz`` with ``rows`` (user indices) and
-``y`` (complex128).  Run from the repository root:
+rows, saved as ``<workload>_rows.npz`` with ``rows`` (user indices), ``y``
+(complex128) and ``y_bf16x3``: the same rows with the coupling products
+emulated in the BF16 split precision (``oracle.emulate``), which fixes the
+expected error of that precision.  Run from the repository root:
 
     python tests/golden/make_golden.py uniform100k uniform1m
 """
@@ -32,10 +34,12 @@ def main(names):
         P = W.config(name)
         rows = sample(name, SAMPLES[name])
         t = time.time()
-        y = oracle.sample_rows(P.points_T, P.points_S, P.v, P.kappa, P.box, P.levels,
-                               P.m, rows)
+        plan = oracle.build(P.points_T, P.points_S, P.kappa, P.box, P.levels, P.m,
+                            rows=rows)
+        y = oracle.matvec(plan, P.v)
+        y_bf = oracle.matvec(plan, P.v, m2l="bf16x3")
         out = os.path.join(os.path.dirname(os.path.abspath(__file__)), f"{name}_rows.npz")
-        np.savez(out, rows=rows, y=y)
+        np.savez(out, rows=rows, y=y, y_bf16x3=y_bf)
         print(f"{name}: {len(rows)} rows in {time.time() - t:.1f} s -> {out}", flush=True)
 
 

@@ -4,7 +4,8 @@ by tests/golden/make_golden.py from the oracle alone).
 
 Tolerances: plain FP64 1e-12 relative l2 over the sampled rows; mixed FP32
 1e-6 (the stated bound of the mixed path); the FP32 result also against the
-plain GPU result on the full vector.
+plain GPU result on the full vector; BF16 split products within 3x the
+error of the oracle's emulation of that arithmetic on the same rows.
 """
 import os
 
@@ -34,9 +35,9 @@ def run(name, prec):
     return _cache[key]
 
 
-def golden(name):
+def golden(name, key="y"):
     g = np.load(os.path.join(GOLDEN, f"{name}_rows.npz"))
-    return g["rows"], g["y"]
+    return g["rows"], g[key]
 
 
 @pytest.mark.parametrize("name", ["uniform100k", "uniform1m"])
@@ -55,3 +56,13 @@ def test_fp32_sampled_rows_and_full_vector(name):
     y64, _ = run(name, "fp64")
     assert rel(y32, y64) <= 1e-6
     _cache.pop((name, "fp64"), None)
+
+
+@pytest.mark.parametrize("name", ["uniform100k", "uniform1m"])
+def test_bf16x3_sampled_rows(name):
+    rows, yo = golden(name)
+    _, ye = golden(name, "y_bf16x3")
+    y, st = run(name, "bf16x3")
+    _cache.pop((name, "bf16x3"), None)
+    assert np.all(np.isfinite(y))
+    assert rel(y[rows], yo) <= 3 * rel(ye, yo)

@@ -150,6 +150,29 @@ def test_fp32_uniform2k():
     assert err <= 10 * emulated  # same order as the emulated FP32 pipeline
 
 
+def bf16x3_errors(P):
+    y, _ = gpu_matvec(P, "bf16x3")
+    op = oracle_plan(P)
+    yo = oracle.matvec(op, P.v)
+    return rel(y, yo), rel(oracle.matvec(op, P.v, m2l="bf16x3"), yo)
+
+
+@pytest.mark.parametrize("name", ["highfreq", "m6", "laplace", "m1"])
+def test_bf16x3_error_matches_emulation(name):
+    """BF16 split products: the error against the FP64 oracle is that of the
+    oracle's emulation of the same split arithmetic (dropped lo*lo term,
+    FP32 sums), within a factor 4 either way -- so the path is neither less
+    accurate than the split arithmetic allows nor secretly FP32."""
+    err, emulated = bf16x3_errors(case(name))
+    assert emulated > 0
+    assert emulated / 4 <= err <= 4 * emulated, (err, emulated)
+
+
+def test_bf16x3_uniform2k():
+    err, emulated = bf16x3_errors(W.config("uniform2k"))
+    assert err <= 4 * emulated and err <= 2e-5, (err, emulated)
+
+
 def test_deterministic_fp64():
     P = case("highfreq")
     gp = gpu_plan(P)
