@@ -96,6 +96,81 @@ int fdm_build_tree_ex(const double* points_T, int64_t n_T,
                       int precision, int l_hf, void* stream, fdm_plan** out);
 
 /*
+ * Launch shape of the coupling step (Sect. 2.6, M2L) and near field.
+ *  nb            target boxes per coupling work item: 32 or 64.
+ *  persistent    1: one workgroup per compute-unit slot, each pulling work
+ *                items from a device queue until it is empty; 0: one
+ *                workgroup per item.
+ *  lpt           1: items with the most offsets first; 0: items in (level,
+ *                octant, direction, target block) order.
+ *  p2p_in_queue  1: the near-field work (blocks of target points) is queued
+ *                behind the coupling items of the same launch; 0: separate
+ *                launch.
+ * Results do not depend on the launch shape except through nb, which
+ * changes the grouping of the FP32 partial sums (the FP64 path is summed in
+ * the same order for both nb).
+ */
+typedef struct {
+  int32_t nb;
+  int32_t persistent;
+  int32_t lpt;
+  int32_t p2p_in_queue;
+} fdm_tune;
+
+/*
+ * Plan options.
+ *  precision          an fdm_precision.
+ *  l_hf               -2 = the automatic rule of fdm_build_tree, else
+ *                     -1 .. levels.
+ *  bank_budget_bytes  0: the coupling bank (one matrix per level and
+ *                     offset, Sect. 2.7) is generated once and held by the
+ *                     plan.  > 0: the plan holds no bank; each matvec
+ *                     generates it, a range of matrices at a time, into a
+ *                     workspace of at most this many bytes (at least one
+ *                     matrix), allocated at the plan's first matvec.  Use it
+ *                     when the bank does not fit, and for plans that only run
+ *                     in a batch (which brings its own workspace).
+ *  tune               initial launch shape (NULL-equivalent: nb = 0 picks
+ *                     the defaults {64, 1, 1, 0}).
+ */
+typedef struct {
+  int32_t precision;
+  int32_t l_hf;
+  int64_t bank_budget_bytes;
+  fdm_tune tune;
+} fdm_options;
+
+/* fdm_build_tree with options (opts host, not NULL). */
+int fdm_build_tree_opts(const double* points_T, int64_t n_T,
+                        const double* points_S, int64_t n_S,
+                        double kappa, const double box[6], int levels, int m,
+                        const fdm_options* opts, void* stream, fdm_plan** out);
+
+/*
+ * Launch shape of a plan: read, or set (rebuilds the plan's work lists when
+ * nb changes; synchronises stream).  FDM_ERR_INVALID_ARG for nb not 32/64
+ * or flags not 0/1; FDM_ERR_STATE while the plan belongs to a batch.
+ */
+int fdm_plan_get_tune(const fdm_plan* plan, fdm_tune* out);
+int fdm_plan_set_tune(fdm_plan* plan, const fdm_tune* tune, void* stream);
+
+/*
+ * fdm_plan_autotune -- time the coupling step under each candidate launch
+ * shape (nb in {64, 32} x persistent in {1, 0} x lpt in {1, 0}, near field
+ * kept as set) on the plan's own data and keep the fastest.  Runs one full
+ * matvec of v into y first (same arguments as fdm_plan_matvec{,_c64}), then
+ * one coupling step per candidate, and synchronises stream.
+ *  max_candidates  how many of the 8 candidates to try, in the order above
+ *                  (1..8).
+ *  best            host, receives the chosen shape (may be NULL).
+ *  ms              host array of max_candidates doubles receiving each
+ *                  candidate's coupling-step time (may be NULL).
+ */
+int fdm_plan_autotune(fdm_plan* plan, const void* v, void* y, int c64,
+                      int max_candidates, void* stream, fdm_tune* best,
+                      double* ms);
+
+/*
  * fdm_plan_matvec -- y = A~ v by Alg. 4 (S2M, M2M, M2L, L2L, L2T, near
  * field), asynchronously on `stream`.
  *
@@ -181,6 +256,68 @@ int fdm_plan_export(const fdm_plan* plan, const char* name, void* host,
 int fdm_dense_matvec(const double* points_T, int64_t n_T,
                      const double* points_S, int64_t n_S, double kappa,
                      const void* v, void* y, void* stream);
+
+/*
+ * Batched matvecs (many independent problems, possibly of different sizes
+ * and wave numbers, one launch sequence).
+ *
+ * fdm_batch_create -- group n plans (same m and precision, each in at most
+ * one batch) into a batch.  The plans stay owned by the caller and must
+ * outlive the batch; while they belong to it they cannot be re-tuned or
+ * destroyed (FDM_ERR_STATE).  Plans built with bank_budget_bytes > 0 have
+ * their coupling banks generated during each batched matvec into one
+ * workspace owned by the batch, of workspace_bytes (0: the smaller of what
+ * all such banks need and half of the free device memory), at least one
+ * matrix; plans with resident banks use them.
+ *  plans   host array of n plan handles.
+ *  stream  used for the set-up uploads; synchronised.
+ *
+ * Each batched matvec runs: for every plan the permutation and forward
+ * transformation (S2M, M2M); then the coupling step of all plans as
+ * persistent launches pulling from one device queue over (plan, level,
+ * direction, target block) items, with every plan's near field queued
+ * behind them (one launch when all banks are resident or fit the
+ * workspace); then for every plan L2L, L2T and the permutation back.
+ */
+typedef struct fdm_batch fdm_batch;
+
+int fdm_batch_create(fdm_plan* const* plans, int n, int64_t workspace_bytes,
+                     void* stream, fdm_batch** out);
+
+/*
+ * fdm_batch_matvec -- y_i = A~_i v_i for every plan i of the batch.
+ *  v  host array of n device pointers: complex128[n_S(i)], or complex64
+ *     when c64 != 0.
+ *  y  host array of n device pointers: complex128[n_T(i)] (complex64 when
+ *     c64 != 0), overwritten.  No y may overlap any v or another y.
+ * Asynchronous on stream.  With graphs enabled (the default) and a
+ * non-NULL stream, the whole batched matvec is captured once into a HIP
+ * graph for these pointers and stream and replayed on later calls with the
+ * same pointers; other pointers re-capture.  Not re-entrant per batch.
+ */
+int fdm_batch_matvec(fdm_batch* batch, const void* const* v, void* const* y,
+                     int c64, void* stream);
+
+/* Enable (1) or disable (0) graph capture of batched matvecs. */
+int fdm_batch_set_graph(fdm_batch* batch, int enable);
+
+/* Launch shape of the batch's coupling launches (as for plans; rebuilds the
+ * work lists of its plans when nb changes; synchronises stream). */
+int fdm_batch_get_tune(const fdm_batch* batch, fdm_tune* out);
+int fdm_batch_set_tune(fdm_batch* batch, const fdm_tune* tune, void* stream);
+
+/*
+ * fdm_batch_autotune -- as fdm_plan_autotune for the batch's coupling
+ * launches: one batched matvec, then one timed coupling step per candidate
+ * (nb in {64, 32} x lpt in {1, 0}; persistent launches with the near field
+ * queued), keeping the fastest.
+ */
+int fdm_batch_autotune(fdm_batch* batch, const void* const* v, void* const* y,
+                       int c64, int max_candidates, void* stream,
+                       fdm_tune* best, double* ms);
+
+/* Free a batch (not its plans).  NULL is accepted. */
+int fdm_batch_destroy(fdm_batch* batch);
 
 /* Thread-local message of the last error ("" if none). */
 const char* fdm_last_error(void);

@@ -2,7 +2,7 @@
 // phase form:
 //
 //   L2L  g~_{t',c'} = G_{t',c'} + sum_{c : dir_(l+1)(c) = c'} E~d_{t',c} .* (E_{t'} g~_{t,c})
-//   L2T  y_j = sum_c sum_nu L_{t,nu}(x_j) exp(i kappa <x_j - m_t, c>) g~_{t,c}[nu]
+//   L2T  y_j += sum_c sum_nu L_{t,nu}(x_j) exp(i kappa <x_j - m_t, c>) g~_{t,c}[nu]
 //
 // with G the coupling (M2L) result of the box and E~d as in the forward
 // transformation.  One workgroup owns one (box, direction) local, so every
@@ -145,7 +145,10 @@ __global__ void __launch_bounds__(64) k_l2t(
         yr += cs * sr - sn * si;
         yi += cs * si + sn * sr;
       }
-      if (lane == 0) y_tree[j] = make_double2(yr, yi);
+      if (lane == 0) {  // added to the near field stored before
+        const double2 yn = y_tree[j];
+        y_tree[j] = make_double2(yn.x + yr, yn.y + yi);
+      }
     }
   }
 }
@@ -182,12 +185,7 @@ void launch_l2t(Plan& P, hipStream_t s) {
   const int p = P.levels;
   const int64_t nb = P.T.nb[p];
   if (P.nT == 0) return;
-  if (P.l_min > p || nb == 0) {  // no coupling anywhere: the far field is zero
-    k_zero_c128<<<grid_for(P.nT, 256), 256, 0, s>>>(
-        reinterpret_cast<double2*>(P.y_tree.get()), P.nT);
-    FDM_LAUNCH("k_zero_c128");
-    return;
-  }
+  if (P.l_min > p || nb == 0) return;  // no coupling anywhere: the far field is zero
   LevelData& Lp = P.L[p];
   k_l2t<<<static_cast<unsigned>(std::min<int64_t>(nb, 1 << 20)), 64, 0, s>>>(
       P.T.x.get(), P.T.y.get(), P.T.z.get(), P.T.key[p].get(), P.T.start[p].get(),

@@ -1,0 +1,786 @@
+// Device code of the coupling step of Alg. 4 (Sect. 2.6, M2L): g~_{t,c} = sum_s A~_{c,t x s} v~_{s,c}
+// over the admissible blocks, on the matrix cores.
+//
+// Bank (Sect. 2.7): the coupling matrix of a block depends only on its level
+// and offset o = i_t - i_s, so one K x K complex matrix is needed per
+// admissible (level, offset):
+//   A~[j,k] = f(xi_{t,j}, xi_{s,k}) exp(-i kappa <(xi_{t,j}-m_t) - (xi_{s,k}-m_s), c>)
+// (the paper's f_c with the plane-wave factors of the box centres moved into
+// the moments and locals), evaluated in FP64 and stored as split re/im
+// planes, transposed (k-major) so that a wave's rows of one k are contiguous
+// (FP64, FP32), or as BF16 hi/lo planes in MFMA operand order.  The bank is
+// either resident or generated, a range of matrices at a time, into a
+// workspace right before the items that use it.
+//
+// Product: one work item is a block of up to nb (32 or 64) target boxes of
+// one level, one octant (so they share the list of admissible offsets) and
+// one direction c.  Its workgroup loops over that list's offsets that hit
+// at least one non-empty source box, gathers the source moment columns
+// t - o (zero for missing boxes) through LDS and accumulates A~_o * M on the
+// MFMA units in registers; the result of each (target, c) is stored by the
+// item's first part and added to by later parts.  Complex products use four
+// real products: Re += Ar Br - Ai Bi, Im += Ar Bi + Ai Br.  Wave w owns rows
+// 32w .. 32w+31 of the (padded) K rows.
+//
+// Items are described by per-(plan, level) descriptors, so one launch can
+// serve many plans (a batch); near-field items (one thread per target point)
+// can share the launch.  Workgroups either take one item each (grid launch)
+// or stay resident and pull items from a device queue (an atomic counter)
+// until it is empty (persistent launch).
+#pragma once
+
+#include <algorithm>
+#include <type_traits>
+
+#include "plan.hpp"
+#include "device_math.hpp"
+#include "nearfield.hpp"
+
+namespace fdm {
+
+namespace {
+
+typedef float f16v __attribute__((ext_vector_type(16)));
+typedef double d4v __attribute__((ext_vector_type(4)));
+typedef float f4n __attribute__((ext_vector_type(4)));
+typedef double d2n __attribute__((ext_vector_type(2)));
+typedef __bf16 bf8v __attribute__((ext_vector_type(8)));
+typedef unsigned int u4v __attribute__((ext_vector_type(4)));
+
+// BF16 (bfloat16) helpers: round to nearest even of an FP32 value, as the
+// raw 16 bits, and the value of such bits.  Finite inputs only.
+__device__ __forceinline__ uint16_t bf16_bits(float x) {
+  uint32_t u = __float_as_uint(x);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return static_cast<uint16_t>(u >> 16);
+}
+__device__ __forceinline__ float bf16_value(uint16_t b) {
+  return __uint_as_float(static_cast<uint32_t>(b) << 16);
+}
+
+// Position of element (row, k) of one BF16 plane: for each k step of 16 and
+// block of 32 rows, the 64 lanes' 8-element A operands of
+// v_mfma_f32_32x32x16_bf16 (lane = row % 32 + 32 * (k % 16 >= 8)) are
+// contiguous, so one wave reads one step of its rows as 1 KiB in a row.
+__device__ __forceinline__ int frag_index(int row, int k, int Kp) {
+  const int ks = k / 16, kr = k % 16;
+  const int lane = row % 32 + 32 * (kr / 8);
+  return ((ks * (Kp / 32) + row / 32) * 64 + lane) * 8 + (kr % 8);
+}
+
+// Pointers taken from descriptors are generic; reading them through the
+// global address space gives global (not flat) loads, which do not count
+// against the LDS wait counter.
+template <class T>
+__device__ __forceinline__ const __attribute__((address_space(1))) T* gmem(const T* p) {
+  return (const __attribute__((address_space(1))) T*)p;
+}
+
+// 16-byte global load / store through native vector types.
+template <class V>
+__device__ __forceinline__ V gload16(const void* p) {
+  const f4n raw = *gmem(static_cast<const f4n*>(p));
+  V v;
+  __builtin_memcpy(&v, &raw, 16);
+  return v;
+}
+__device__ __forceinline__ void gstore16(void* p, double2 v) {
+  d2n raw;
+  __builtin_memcpy(&raw, &v, 16);
+  *(__attribute__((address_space(1))) d2n*)(p) = raw;
+}
+
+// Shared prologue: the block's target boxes and their integer positions;
+// col[b][j] is the first moment element of target j's source column for the
+// offset held in buffer b (or -1: empty or outside the grid).
+template <int NB>
+struct TargetTile {
+  int32_t t[NB];
+  int32_t x[NB], y[NB], z[NB];
+  int64_t col[2][NB];
+};
+
+template <int NB>
+__device__ __forceinline__ void load_targets(TargetTile<NB>& S, const M2LItem& it,
+                                             const M2LDesc& D) {
+  for (int j = threadIdx.x; j < NB; j += blockDim.x) {
+    int32_t t = j < it.ntgt ? gmem(D.tgt_list)[it.tgt_begin + j] : -1;
+    S.t[j] = t;
+    int ix = 0, iy = 0, iz = 0;
+    if (t >= 0) demorton3(gmem(D.keyT)[t], D.level, ix, iy, iz);
+    S.x[j] = ix;
+    S.y[j] = iy;
+    S.z[j] = iz;
+  }
+}
+
+template <int NB>
+__device__ __forceinline__ void source_columns(TargetTile<NB>& S, int buf, const M2LDesc& D,
+                                               int4 od, int c, int Kp) {
+  const int lim = 1 << D.level;
+  for (int j = threadIdx.x; j < NB; j += blockDim.x) {
+    int64_t col = -1;
+    if (S.t[j] >= 0) {
+      const int sx = S.x[j] - od.x, sy = S.y[j] - od.y, sz = S.z[j] - od.z;
+      if (sx >= 0 && sy >= 0 && sz >= 0 && sx < lim && sy < lim && sz < lim) {
+        const int32_t sb = gmem(D.gridS)[morton3(sx, sy, sz, D.level)];
+        if (sb >= 0) col = (int64_t(sb) * D.nd + c) * Kp;
+      }
+    }
+    S.col[buf][j] = col;
+  }
+}
+
+__device__ __forceinline__ int4 offset_of(const M2LDesc& D, int32_t vo) {
+  return D.offtab[gmem(D.valid_off)[vo]];
+}
+
+// Precision traits of the coupling kernel.  Each wave owns 32 rows of the
+// (padded) coupling matrix and all NB target columns of the block.
+//  FP32: v_mfma_f32_32x32x2f32, k-step 2, NB/32 column tiles of 32, k slab 16.
+//  FP64: v_mfma_f64_16x16x4f64, k-step 4, 2 row x NB/16 column tiles of 16, k slab 8.
+struct F32Traits {
+  using T = float;
+  using V16 = float4;  // 16-byte load unit
+  static constexpr int KS = 16;
+};
+struct F64Traits {
+  using T = double;
+  using V16 = double2;
+  static constexpr int KS = 8;
+};
+
+template <class Tr, int NB>
+struct M2LShared {
+  TargetTile<NB> S;
+  typename Tr::T B[2][2][Tr::KS][NB + 1];  // [buffer][re/im][k][column]
+};
+template <int NB>
+using F64Shared = M2LShared<F64Traits, NB>;
+template <int NB>
+using F32Shared = M2LShared<F32Traits, NB>;
+
+// Moment columns of one k slab: NB columns x KS complex values, staged in
+// 16-byte pieces, at most one per thread (the workgroup has >= 512 threads).
+template <class Tr, int NB>
+__device__ __forceinline__ typename Tr::V16 load_cols(const TargetTile<NB>& S, int colbuf,
+                                                      const typename Tr::T* __restrict__ mom,
+                                                      int k0) {
+  using V = typename Tr::V16;
+  constexpr int EPV = sizeof(V) / sizeof(typename Tr::T);
+  constexpr int PPC = Tr::KS * 2 / EPV;  // pieces per column
+  static_assert(NB * PPC <= 512, "one staged piece per thread");
+  V val{};
+  const int e = threadIdx.x;
+  if (e < NB * PPC) {
+    const int64_t col = S.col[colbuf][e / PPC];
+    if (col >= 0) val = gload16<V>(mom + 2 * (col + k0) + (e % PPC) * EPV);
+  }
+  return val;
+}
+
+template <class Tr, int NB>
+__device__ __forceinline__ void store_cols(M2LShared<Tr, NB>& sh, int buf,
+                                           typename Tr::V16 val) {
+  using T = typename Tr::T;
+  using V = typename Tr::V16;
+  constexpr int EPV = sizeof(V) / sizeof(T);
+  constexpr int PPC = Tr::KS * 2 / EPV;
+  const int e = threadIdx.x;
+  if (e < NB * PPC) {
+    const int j = e / PPC, q = e % PPC;
+    const T* v = reinterpret_cast<const T*>(&val);
+#pragma unroll
+    for (int u = 0; u < EPV / 2; ++u) {
+      const int k = q * (EPV / 2) + u;
+      sh.B[buf][0][k][j] = v[2 * u];
+      sh.B[buf][1][k][j] = v[2 * u + 1];
+    }
+  }
+}
+
+template <class A>
+__device__ __forceinline__ void zero(A& a) {
+  for (auto& x : a)
+#pragma unroll
+    for (int i = 0; i < static_cast<int>(sizeof(x) / sizeof(x[0])); ++i) x[i] = 0;
+}
+
+// ------------------------------------------------------------------ FP64 --
+// MFMAs of one k slab for one wave: Re += Ar Br - Ai Bi, Im += Ar Bi + Ai Br.
+// The coupling matrix is read straight from the bank (k-major: a wave's rows
+// of one k are contiguous).
+template <int NB>
+__device__ __forceinline__ void slab_mfma(d4v (&ar)[NB / 8], d4v (&ai)[NB / 8],
+                                          const F64Shared<NB>& sh, int buf,
+                                          const double* __restrict__ Ar,
+                                          const double* __restrict__ Ai, int k0, int Kp,
+                                          int wave, int lane) {
+  constexpr int NC = NB / 16;  // column tiles
+  const int kl = lane / 16, li = lane % 16;
+  double a_r[2][2], a_i[2][2];
+#pragma unroll
+  for (int t = 0; t < 2; ++t)
+#pragma unroll
+    for (int rs = 0; rs < 2; ++rs) {
+      const int64_t ka = int64_t(k0 + 4 * t + kl) * Kp + 32 * wave + 16 * rs + li;
+      a_r[t][rs] = gmem(Ar)[ka];
+      a_i[t][rs] = gmem(Ai)[ka];
+    }
+#pragma unroll
+  for (int t = 0; t < 2; ++t) {
+    const int kk = 4 * t;
+#pragma unroll
+    for (int cs = 0; cs < NC; ++cs) {
+      const double b_r = sh.B[buf][0][kk + kl][16 * cs + li];
+      const double b_i = sh.B[buf][1][kk + kl][16 * cs + li];
+#pragma unroll
+      for (int rs = 0; rs < 2; ++rs) {
+        d4v& cr = ar[rs * NC + cs];
+        d4v& ci = ai[rs * NC + cs];
+        cr = __builtin_amdgcn_mfma_f64_16x16x4f64(a_r[t][rs], b_r, cr, 0, 0, 0);
+        cr = __builtin_amdgcn_mfma_f64_16x16x4f64(-a_i[t][rs], b_i, cr, 0, 0, 0);
+        ci = __builtin_amdgcn_mfma_f64_16x16x4f64(a_r[t][rs], b_i, ci, 0, 0, 0);
+        ci = __builtin_amdgcn_mfma_f64_16x16x4f64(a_i[t][rs], b_r, ci, 0, 0, 0);
+      }
+    }
+  }
+}
+
+template <int NB, bool FIRST>
+__device__ __forceinline__ void flush_rows64(const d4v (&tr)[NB / 8], const d4v (&ti)[NB / 8],
+                                             const TargetTile<NB>& S, double2* out, int nd,
+                                             int c, int Kp, int wave, int lane) {
+  constexpr bool first = FIRST;
+  constexpr int NC = NB / 16;
+#pragma unroll
+  for (int cs = 0; cs < NC; ++cs) {
+    const int32_t t = S.t[16 * cs + (lane % 16)];
+    if (t < 0) continue;
+    double2* dst = out + (int64_t(t) * nd + c) * Kp;
+#pragma unroll
+    for (int rs = 0; rs < 2; ++rs)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int r = 32 * wave + 16 * rs + lane / 16 + 4 * i;
+        double2 v = make_double2(tr[rs * NC + cs][i], ti[rs * NC + cs][i]);
+        if (!first) {
+          const double2 o = gload16<double2>(dst + r);
+          v.x += o.x;
+          v.y += o.y;
+        }
+        gstore16(dst + r, v);
+        // one element at a time: hoisted loads would hold the whole tile
+        __builtin_amdgcn_sched_barrier(0);
+      }
+  }
+}
+
+// FP64 item.  One pipeline step = one (offset, k slab): the next step's
+// moment columns are loaded into a register before this step's MFMAs and
+// stored to the other LDS buffer after them; one barrier ends each step.
+// One FP64 accumulator chain per (row, target).  ADD: the launch holds later
+// parts of split items, whose results are added (a compile-time switch: the
+// add path costs registers).
+template <int NB, bool ADD>
+__device__ __forceinline__ void item_f64(F64Shared<NB>& sh, const M2LItem& it,
+                                         const M2LDesc& D, int Kp) {
+  using Tr = F64Traits;
+  const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+  const bool rows_here = 32 * wave < Kp;  // waves past Kp only help with loads
+  load_targets(sh.S, it, D);
+  __syncthreads();
+  double2* out = static_cast<double2*>(D.out);
+  d4v acr[NB / 8], aci[NB / 8];
+  zero(acr);
+  zero(aci);
+  const int nv = it.vo_count;
+  if (nv > 0) {
+    const double* mom = static_cast<const double*>(D.mom);
+    const double* bank = static_cast<const double*>(D.bank);
+    const int64_t per = int64_t(Kp) * Kp;
+    const int ns = Kp / Tr::KS;  // k slabs per offset (>= 2)
+    const int total = nv * ns;
+    int4 od_cur = offset_of(D, it.vo_begin);
+    int4 od_next = od_cur;
+    source_columns(sh.S, 0, D, od_cur, it.c, Kp);
+    __syncthreads();
+    store_cols<Tr, NB>(sh, 0, load_cols<Tr, NB>(sh.S, 0, mom, 0));
+    __syncthreads();
+    for (int q = 0; q < total; ++q) {
+      const int v = q / ns, s = q % ns, cur = q & 1;
+      if (s == 0) {
+        od_cur = od_next;
+        if (v + 1 < nv) {  // source columns of the next offset
+          od_next = offset_of(D, it.vo_begin + v + 1);
+          source_columns(sh.S, (v + 1) & 1, D, od_next, it.c, Kp);
+        }
+      }
+      const bool more = q + 1 < total;
+      double2 nxt{};
+      if (more)
+        nxt = load_cols<Tr, NB>(sh.S, ((q + 1) / ns) & 1, mom, ((q + 1) % ns) * Tr::KS);
+      if (rows_here) {
+        const double* Ar = bank + od_cur.w * 2 * per;
+        slab_mfma<NB>(acr, aci, sh, cur, Ar, Ar + per, s * Tr::KS, Kp, wave, lane);
+      }
+      if (more) store_cols<Tr, NB>(sh, cur ^ 1, nxt);
+      __syncthreads();
+    }
+  }
+  if (rows_here) {
+    if (!ADD || it.first)
+      flush_rows64<NB, true>(acr, aci, sh.S, out, D.nd, it.c, Kp, wave, lane);
+    else if (nv > 0)  // later part of a split item (streamed bank): add
+      flush_rows64<NB, false>(acr, aci, sh.S, out, D.nd, it.c, Kp, wave, lane);
+  }
+}
+
+// ------------------------------------------------------------------ FP32 --
+// Add (or store) a wave's accumulated 32x32 tiles into the FP64 result of
+// its rows and the block's targets (FP32 and BF16 items).
+template <int NB>
+__device__ __forceinline__ void flush_rows32(const f16v (&tr)[NB / 32], const f16v (&ti)[NB / 32],
+                                             const TargetTile<NB>& S, double2* out, int nd,
+                                             int c, int Kp, int wave, int lane, bool first) {
+#pragma unroll
+  for (int cs = 0; cs < NB / 32; ++cs) {
+    const int32_t t = S.t[32 * cs + (lane % 32)];
+    if (t < 0) continue;
+    double2* dst = out + (int64_t(t) * nd + c) * Kp;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      const int r = 32 * wave + 8 * (i / 4) + 4 * (lane / 32) + (i % 4);
+      double2 v = make_double2(tr[cs][i], ti[cs][i]);
+      if (!first) {
+        const double2 o = gload16<double2>(dst + r);
+        v.x += o.x;
+        v.y += o.y;
+      }
+      gstore16(dst + r, v);
+      // one element at a time: hoisted loads would hold the whole tile
+      __builtin_amdgcn_sched_barrier(0);
+    }
+  }
+}
+
+__device__ __forceinline__ void load_a32(float (&a)[2][8], const float* __restrict__ Ar,
+                                         int64_t per, int k0, int Kp, int wave, int lane) {
+  const int r = 32 * wave + (lane % 32), kl = lane / 32;
+#pragma unroll
+  for (int t = 0; t < 8; ++t) {
+    const int64_t ka = int64_t(k0 + 2 * t + kl) * Kp + r;
+    a[0][t] = gmem(Ar)[ka];
+    a[1][t] = gmem(Ar)[per + ka];
+  }
+}
+
+template <int NB>
+__device__ __forceinline__ void mfma32(f16v (&ar)[NB / 32], f16v (&ai)[NB / 32],
+                                       const float (&a)[2][8], const F32Shared<NB>& sh,
+                                       int buf, int lane) {
+  const int kl = lane / 32, cl = lane % 32;
+#pragma unroll
+  for (int t = 0; t < 8; ++t) {
+    const int kk = 2 * t;
+#pragma unroll
+    for (int cs = 0; cs < NB / 32; ++cs) {
+      const float b_r = sh.B[buf][0][kk + kl][32 * cs + cl];
+      const float b_i = sh.B[buf][1][kk + kl][32 * cs + cl];
+      ar[cs] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[0][t], b_r, ar[cs], 0, 0, 0);
+      ar[cs] = __builtin_amdgcn_mfma_f32_32x32x2f32(-a[1][t], b_i, ar[cs], 0, 0, 0);
+      ai[cs] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[0][t], b_i, ai[cs], 0, 0, 0);
+      ai[cs] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[1][t], b_r, ai[cs], 0, 0, 0);
+    }
+  }
+}
+
+// FP32 item.  Same pipeline.  Each offset's product is summed in fresh FP32
+// accumulators (rounding relative to that product, not to the total over
+// all offsets), added to FP32 totals, and every kFlush offsets the totals
+// are added to the FP64 result in memory, which this workgroup alone owns.
+constexpr int kFlush = 16;
+
+template <int NB, bool ADD>
+__device__ __forceinline__ void item_f32(F32Shared<NB>& sh, const M2LItem& it,
+                                         const M2LDesc& D, int Kp) {
+  using Tr = F32Traits;
+  constexpr int NT = NB / 32;
+  const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+  const bool rows_here = 32 * wave < Kp;
+  load_targets(sh.S, it, D);
+  __syncthreads();
+  double2* out = static_cast<double2*>(D.out);
+  f16v acr[NT], aci[NT], tor[NT], toi[NT];
+  zero(acr);
+  zero(aci);
+  const int nv = it.vo_count;
+  if (nv == 0) {  // no source box: the result is zero
+    if (rows_here && it.first)
+      flush_rows32<NB>(acr, aci, sh.S, out, D.nd, it.c, Kp, wave, lane, true);
+    return;
+  }
+  zero(tor);
+  zero(toi);
+  const float* mom = static_cast<const float*>(D.mom);
+  const float* bank = static_cast<const float*>(D.bank);
+  const int64_t per = int64_t(Kp) * Kp;
+  const int ns = Kp / Tr::KS;  // k slabs per offset (>= 2)
+  const int total = nv * ns;
+  int4 od_cur = offset_of(D, it.vo_begin);
+  int4 od_next = od_cur;
+  source_columns(sh.S, 0, D, od_cur, it.c, Kp);
+  __syncthreads();
+  store_cols<Tr, NB>(sh, 0, load_cols<Tr, NB>(sh.S, 0, mom, 0));
+  __syncthreads();
+  bool first = it.first != 0;
+  for (int q = 0; q < total; ++q) {
+    const int v = q / ns, s = q % ns, cur = q & 1;
+    if (s == 0) {
+      od_cur = od_next;
+      if (v + 1 < nv) {  // source columns of the next offset
+        od_next = offset_of(D, it.vo_begin + v + 1);
+        source_columns(sh.S, (v + 1) & 1, D, od_next, it.c, Kp);
+      }
+    }
+    const bool more = q + 1 < total;
+    float4 nxt{};
+    if (more) nxt = load_cols<Tr, NB>(sh.S, ((q + 1) / ns) & 1, mom, ((q + 1) % ns) * Tr::KS);
+    if (rows_here) {
+      if (s == 0) {
+        zero(acr);
+        zero(aci);
+      }
+      float a[2][8];
+      load_a32(a, bank + od_cur.w * 2 * per, per, s * Tr::KS, Kp, wave, lane);
+      mfma32<NB>(acr, aci, a, sh, cur, lane);
+      if (s == ns - 1) {
+#pragma unroll
+        for (int c2 = 0; c2 < NT; ++c2) {
+          tor[c2] += acr[c2];
+          toi[c2] += aci[c2];
+        }
+        if ((v + 1) % kFlush == 0 || v + 1 == nv) {
+          flush_rows32<NB>(tor, toi, sh.S, out, D.nd, it.c, Kp, wave, lane, first);
+          first = false;
+          zero(tor);
+          zero(toi);
+        }
+      }
+    }
+    if (more) store_cols<Tr, NB>(sh, cur ^ 1, nxt);
+    __syncthreads();
+  }
+}
+
+// ------------------------------------------------- BF16 split precision --
+// Each real operand x (coupling entry or moment, FP32) is split into two
+// BF16 parts x = hi + lo + O(2^-16 |x|), and a real product X Y is taken as
+// Xh Yh + Xh Yl + Xl Yh (three v_mfma_f32_32x32x16_bf16, FP32 accumulation);
+// the dropped Xl Yl term is of relative size 2^-16.  Complex products as
+// above; the FP32 per-offset sums, FP32 totals and FP64 flushes are those of
+// the FP32 items.
+template <int NB>
+struct BF16Shared {
+  TargetTile<NB> S;
+  // [buffer][plane: re hi, re lo, im hi, im lo][column][k]: 16 k per slab,
+  // rows padded to 24 (48 bytes) so that 16 lanes' 16-byte reads of 16
+  // consecutive columns fall in distinct banks
+  alignas(16) uint16_t B[2][4][NB][24];
+};
+constexpr int kBKS = 16;  // k per slab
+
+template <int NB>
+__device__ __forceinline__ void store_cols_bf16(BF16Shared<NB>& sh, int buf, float4 val) {
+  const int e = threadIdx.x;
+  if (e < NB * 8) {  // piece e: column e / 8, k = 2 (e % 8) and 2 (e % 8) + 1
+    const int j = e / 8, k = 2 * (e % 8);
+    const uint16_t rh0 = bf16_bits(val.x), ih0 = bf16_bits(val.y);
+    const uint16_t rh1 = bf16_bits(val.z), ih1 = bf16_bits(val.w);
+    const uint16_t rl0 = bf16_bits(val.x - bf16_value(rh0));
+    const uint16_t il0 = bf16_bits(val.y - bf16_value(ih0));
+    const uint16_t rl1 = bf16_bits(val.z - bf16_value(rh1));
+    const uint16_t il1 = bf16_bits(val.w - bf16_value(ih1));
+    auto put = [&](int plane, uint16_t a, uint16_t b) {
+      *reinterpret_cast<uint32_t*>(&sh.B[buf][plane][j][k]) =
+          uint32_t(a) | (uint32_t(b) << 16);
+    };
+    put(0, rh0, rh1);
+    put(1, rl0, rl1);
+    put(2, ih0, ih1);
+    put(3, il0, il1);
+  }
+}
+
+__device__ __forceinline__ bf8v as_bf8(u4v v) {
+  bf8v r;
+  __builtin_memcpy(&r, &v, 16);
+  return r;
+}
+__device__ __forceinline__ bf8v lds_bf8(const uint16_t* p) {
+  return as_bf8(*reinterpret_cast<const u4v*>(p));
+}
+__device__ __forceinline__ bf8v neg_bf8(bf8v x) {
+  const u4v sign = {0x80008000u, 0x80008000u, 0x80008000u, 0x80008000u};
+  u4v u;
+  __builtin_memcpy(&u, &x, 16);
+  return as_bf8(u ^ sign);
+}
+
+// One k slab (one MFMA k step) for one wave: A operands from the bank in
+// fragment order, B operands from LDS.  Two passes keep few operands live:
+// first the A lo parts against the B hi parts, then the A hi parts against
+// both B parts.
+template <int NB>
+__device__ __forceinline__ void mfma_bf16x3(f16v (&ar)[NB / 32], f16v (&ai)[NB / 32],
+                                            const uint16_t* __restrict__ A, int64_t per,
+                                            const BF16Shared<NB>& sh, int buf, int s, int Kp,
+                                            int wave, int lane) {
+  const int64_t f = ((int64_t(s) * (Kp / 32) + wave) * 64 + lane) * 8;
+  const int kq = 8 * (lane / 32);
+  {
+    const bf8v arl = as_bf8(gload16<u4v>(A + per + f));
+    const bf8v ail = as_bf8(gload16<u4v>(A + 3 * per + f));
+#pragma unroll
+    for (int cs = 0; cs < NB / 32; ++cs) {
+      const int col = 32 * cs + lane % 32;
+      const bf8v brh = lds_bf8(&sh.B[buf][0][col][kq]);
+      const bf8v bih = lds_bf8(&sh.B[buf][2][col][kq]);
+      ar[cs] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(arl, brh, ar[cs], 0, 0, 0);
+      ai[cs] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(arl, bih, ai[cs], 0, 0, 0);
+      ar[cs] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ail, neg_bf8(bih), ar[cs], 0, 0, 0);
+      ai[cs] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ail, brh, ai[cs], 0, 0, 0);
+      __builtin_amdgcn_sched_barrier(0);
+    }
+  }
+  const bf8v arh = as_bf8(gload16<u4v>(A + f));
+  const bf8v aih = as_bf8(gload16<u4v>(A + 2 * per + f));
+#pragma unroll
+  for (int cs = 0; cs < NB / 32; ++cs) {
+    const int col = 32 * cs + lane % 32;
+    const bf8v brh = lds_bf8(&sh.B[buf][0][col][kq]);
+    const bf8v brl = lds_bf8(&sh.B[buf][1][col][kq]);
+    const bf8v bih = lds_bf8(&sh.B[buf][2][col][kq]);
+    const bf8v bil = lds_bf8(&sh.B[buf][3][col][kq]);
+    f16v r = ar[cs], i = ai[cs];
+    r = __builtin_amdgcn_mfma_f32_32x32x16_bf16(arh, brl, r, 0, 0, 0);
+    i = __builtin_amdgcn_mfma_f32_32x32x16_bf16(arh, bil, i, 0, 0, 0);
+    r = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aih, neg_bf8(bil), r, 0, 0, 0);
+    i = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aih, brl, i, 0, 0, 0);
+    r = __builtin_amdgcn_mfma_f32_32x32x16_bf16(arh, brh, r, 0, 0, 0);
+    i = __builtin_amdgcn_mfma_f32_32x32x16_bf16(arh, bih, i, 0, 0, 0);
+    r = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aih, neg_bf8(bih), r, 0, 0, 0);
+    i = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aih, brh, i, 0, 0, 0);
+    ar[cs] = r;
+    ai[cs] = i;
+    __builtin_amdgcn_sched_barrier(0);
+  }
+}
+
+template <int NB, bool ADD>
+__device__ __forceinline__ void item_bf16(BF16Shared<NB>& sh, const M2LItem& it,
+                                          const M2LDesc& D, int Kp) {
+  constexpr int NT = NB / 32;
+  const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+  const bool rows_here = 32 * wave < Kp;
+  load_targets(sh.S, it, D);
+  __syncthreads();
+  double2* out = static_cast<double2*>(D.out);
+  f16v acr[NT], aci[NT], tor[NT], toi[NT];
+  zero(acr);
+  zero(aci);
+  const int nv = it.vo_count;
+  if (nv == 0) {  // no source box: the result is zero
+    if (rows_here && it.first)
+      flush_rows32<NB>(acr, aci, sh.S, out, D.nd, it.c, Kp, wave, lane, true);
+    return;
+  }
+  zero(tor);
+  zero(toi);
+  const float* mom = static_cast<const float*>(D.mom);
+  const uint16_t* bank = static_cast<const uint16_t*>(D.bank);
+  const int64_t per = int64_t(Kp) * Kp;
+  const int ns = Kp / kBKS;  // k slabs per offset
+  const int total = nv * ns;
+  int4 od_cur = offset_of(D, it.vo_begin);
+  int4 od_next = od_cur;
+  source_columns(sh.S, 0, D, od_cur, it.c, Kp);
+  __syncthreads();
+  store_cols_bf16<NB>(sh, 0, load_cols<F32Traits, NB>(sh.S, 0, mom, 0));
+  __syncthreads();
+  bool first = it.first != 0;
+  for (int q = 0; q < total; ++q) {
+    const int v = q / ns, s = q % ns, cur = q & 1;
+    if (s == 0) {
+      od_cur = od_next;
+      if (v + 1 < nv) {  // source columns of the next offset
+        od_next = offset_of(D, it.vo_begin + v + 1);
+        source_columns(sh.S, (v + 1) & 1, D, od_next, it.c, Kp);
+      }
+    }
+    const bool more = q + 1 < total;
+    float4 nxt{};
+    if (more)
+      nxt = load_cols<F32Traits, NB>(sh.S, ((q + 1) / ns) & 1, mom, ((q + 1) % ns) * kBKS);
+    if (rows_here) {
+      if (s == 0) {
+        zero(acr);
+        zero(aci);
+      }
+      mfma_bf16x3<NB>(acr, aci, bank + od_cur.w * 4 * per, per, sh, cur, s,
+                      Kp, wave, lane);
+      if (s == ns - 1) {
+#pragma unroll
+        for (int c2 = 0; c2 < NT; ++c2) {
+          tor[c2] += acr[c2];
+          toi[c2] += aci[c2];
+        }
+        if ((v + 1) % kFlush == 0 || v + 1 == nv) {
+          flush_rows32<NB>(tor, toi, sh.S, out, D.nd, it.c, Kp, wave, lane, first);
+          first = false;
+          zero(tor);
+          zero(toi);
+        }
+      }
+    }
+    if (more) store_cols_bf16<NB>(sh, cur ^ 1, nxt);
+    __syncthreads();
+  }
+}
+
+// ------------------------------------------------------------ launches --
+// Near-field item: thread t evaluates target point begin + t.  Out of line,
+// so that its registers do not add to the coupling items'.
+__device__ __noinline__ void item_p2p(const P2PDesc* __restrict__ dp, int32_t begin,
+                                      int32_t count) {
+  const int t = threadIdx.x;
+  if (t < count) {
+    const P2PDesc d = *dp;
+    const int64_t j = int64_t(begin) + t;
+    reinterpret_cast<double2*>(d.y)[j] = near_value(d, j);
+  }
+}
+
+// Runs the items of a launch: item blockIdx.x (grid launch) or, with a
+// queue head, items taken from the queue one at a time until it is empty.
+// Every workgroup leaves once the head passes n_items, so the grid drains.
+template <bool QUEUE, bool P2P, class F>
+__device__ __forceinline__ void run_items(const M2LItem* __restrict__ items, int64_t n_items,
+                                          const M2LDesc* __restrict__ descs,
+                                          const P2PDesc* __restrict__ p2p, int32_t* head,
+                                          int32_t& next, F&& coupling) {
+  if constexpr (!QUEUE) {
+    const M2LItem it = items[blockIdx.x];
+    if (it.desc >= 0) {
+      const M2LDesc D = descs[it.desc];
+      coupling(it, D);
+    } else if constexpr (P2P) {
+      item_p2p(p2p - it.desc - 1, it.tgt_begin, it.ntgt);
+    }
+    return;
+  }
+  for (;;) {
+    if (threadIdx.x == 0) next = atomicAdd(head, 1);
+    __syncthreads();
+    // the same value in every lane: keeps the item and its descriptor in
+    // scalar registers
+    const int64_t i = __builtin_amdgcn_readfirstlane(next);
+    if (i >= n_items) break;
+    const M2LItem it = items[i];
+    if (it.desc >= 0) {
+      const M2LDesc D = descs[it.desc];
+      coupling(it, D);
+    } else if constexpr (P2P) {
+      item_p2p(p2p - it.desc - 1, it.tgt_begin, it.ntgt);
+    }
+    __syncthreads();  // LDS and `next` are reused by the next item
+  }
+}
+
+// The coupling kernels: NB targets per item, grid (one item per workgroup)
+// or queue (persistent) launch, MAXT threads at most (512 when Kp <= 256,
+// which leaves 256 registers per lane), ADD as for the FP64 item; P2P:
+// whether near-field items may share the launch -- only in the FP32 and
+// BF16 kernels with Kp <= 256: elsewhere the coupling item takes all the
+// registers (see p2p_queue_supported).
+#define FDM_M2L_KERNEL(NAME, SHARED, ITEM, P2P)                                              \
+  template <int NB, bool QUEUE, int MAXT, bool ADD>                                          \
+  __global__ void __launch_bounds__(MAXT)                                                    \
+      NAME(const M2LItem* __restrict__ items, int64_t n_items,                               \
+           const M2LDesc* __restrict__ descs, const P2PDesc* __restrict__ p2p,               \
+           int32_t* head, int Kp) {                                                          \
+    __shared__ SHARED<NB> sh;                                                                \
+    __shared__ int32_t next;                                                                 \
+    run_items<QUEUE, P2P && MAXT == 512>(items, n_items, descs, p2p, head, next,             \
+                     [&](const M2LItem& it, const M2LDesc& D) {                              \
+                       ITEM<NB, ADD>(sh, it, D, Kp);                                         \
+                     });                                                                     \
+  }
+
+// Workgroups that stay resident at once: the grid of a persistent launch.
+template <class K>
+int64_t resident_groups(K kernel, int threads) {
+  int per_cu = 0;
+  FDM_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads, 0));
+  int dev = 0, cus = 0;
+  FDM_HIP(hipGetDevice(&dev));
+  FDM_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+  return int64_t(std::max(per_cu, 1)) * std::max(cus, 1);
+}
+
+// Launch of one coupling launch's items with the grid or the queue kernel.
+template <class KG, class KQ>
+void launch_pair(KG grid_kernel, KQ queue_kernel, const M2LLaunch& L, int Kp, bool persistent,
+                 int32_t* head, hipStream_t s, const char* name) {
+  const int threads = m2l_threads(Kp);
+  const int64_t n = L.n_items;
+  if (persistent) {
+    if (L.resident_wgs <= 0) fail(FDM_ERR_STATE, "persistent launch without a grid size");
+    const unsigned grid = static_cast<unsigned>(std::min<int64_t>(n, L.resident_wgs));
+    queue_kernel<<<grid, threads, 0, s>>>(L.items.get(), n, L.descs.get(), L.p2p.get(), head,
+                                          Kp);
+  } else {
+    grid_kernel<<<static_cast<unsigned>(n), threads, 0, s>>>(L.items.get(), n, L.descs.get(),
+                                                             L.p2p.get(), nullptr, Kp);
+  }
+  FDM_LAUNCH(name);
+}
+
+// Instantiates, for one kernel family, the launcher and the resident-group
+// count over NB in {32, 64}, MAXT in {512, 768} and ADD.
+#define FDM_M2L_LAUNCHERS(NAME, LAUNCH_FN, RESIDENT_FN, USE_ADD)                             \
+  template <int NB, int MAXT, bool ADD>                                                      \
+  void NAME##_go(const M2LLaunch& L, int Kp, bool persistent, int32_t* head, hipStream_t s) { \
+    launch_pair(NAME<NB, false, MAXT, ADD>, NAME<NB, true, MAXT, ADD>, L, Kp, persistent,    \
+                head, s, #NAME);                                                             \
+  }                                                                                          \
+  template <int NB, int MAXT, bool ADD>                                                      \
+  int64_t NAME##_res(int Kp) {                                                               \
+    return resident_groups(NAME<NB, true, MAXT, ADD>, m2l_threads(Kp));                      \
+  }                                                                                          \
+  }                                                                                          \
+  void LAUNCH_FN(const M2LLaunch& L, int Kp, int nb, bool persistent, int32_t* head,         \
+                 hipStream_t s) {                                                            \
+    const bool big = m2l_threads(Kp) > 512, add = USE_ADD && L.has_parts;                    \
+    if (nb == 32) {                                                                          \
+      if (big) (add ? NAME##_go<32, 768, true> : NAME##_go<32, 768, false>)(L, Kp, persistent, head, s); \
+      else (add ? NAME##_go<32, 512, true> : NAME##_go<32, 512, false>)(L, Kp, persistent, head, s); \
+    } else {                                                                                 \
+      if (big) (add ? NAME##_go<64, 768, true> : NAME##_go<64, 768, false>)(L, Kp, persistent, head, s); \
+      else (add ? NAME##_go<64, 512, true> : NAME##_go<64, 512, false>)(L, Kp, persistent, head, s); \
+    }                                                                                        \
+  }                                                                                          \
+  int64_t RESIDENT_FN(int nb, int Kp, bool parts) {                                          \
+    const bool big = m2l_threads(Kp) > 512, add = USE_ADD && parts;                          \
+    if (nb == 32) {                                                                          \
+      if (big) return add ? NAME##_res<32, 768, true>(Kp) : NAME##_res<32, 768, false>(Kp);  \
+      return add ? NAME##_res<32, 512, true>(Kp) : NAME##_res<32, 512, false>(Kp);           \
+    }                                                                                        \
+    if (big) return add ? NAME##_res<64, 768, true>(Kp) : NAME##_res<64, 768, false>(Kp);    \
+    return add ? NAME##_res<64, 512, true>(Kp) : NAME##_res<64, 512, false>(Kp);             \
+  }                                                                                          \
+  namespace {
+
+}  // namespace
+
+}  // namespace fdm

@@ -1,0 +1,373 @@
+// Host side of the coupling step (Sect. 2.6, M2L): the coupling bank, the
+// work items of a plan, and the launch schedules that run them -- for one
+// plan or for a batch of plans, with resident banks or with banks generated
+// into a bounded workspace a range of matrices at a time.
+#include <algorithm>
+#include <map>
+
+#include "plan.hpp"
+
+namespace fdm {
+
+int64_t bank_matrix_bytes(int prec, const Interp& ip) {
+  const int64_t per = int64_t(ip.Kp) * ip.Kp;
+  if (prec == FDM_PREC_FP64) return 2 * per * 8;
+  if (prec == FDM_PREC_BF16X3) return 4 * per * 2;
+  return 2 * per * 4;
+}
+
+namespace {
+
+BankLevel bank_level(const Plan& P, int l) {
+  return BankLevel{P.L[l].dirvec.get(), P.L[l].h, P.kappa, l, P.L[l].nd};
+}
+
+// `bank` holds bank id bank_id0 as its first matrix.
+M2LDesc level_desc(const Plan& P, int l, const void* bank, int64_t bank_id0) {
+  const LevelData& Ld = P.L[l];
+  M2LDesc d{};
+  d.gridS = P.S.grid[l].get();
+  d.keyT = P.T.key[l].get();
+  d.mom = P.prec == FDM_PREC_FP64 ? static_cast<const void*>(Ld.mom64.get())
+                                  : static_cast<const void*>(Ld.mom32.get());
+  d.out = Ld.loc64.get();  // FP64 coupling result, completed in place by L2L
+  d.tgt_list = P.tgt_list.get();
+  d.valid_off = P.valid_off.get();
+  d.offtab = P.offtab.get();
+  const int64_t mb = bank_matrix_bytes(P.prec, P.ip);
+  d.bank = reinterpret_cast<const void*>(reinterpret_cast<uintptr_t>(bank) -
+                                         static_cast<uintptr_t>(bank_id0 * mb));
+  d.nd = Ld.nd;
+  d.level = l;
+  return d;
+}
+
+const void* resident_bank(const Plan& P) {
+  if (P.prec == FDM_PREC_FP64) return P.bank64.get();
+  if (P.prec == FDM_PREC_BF16X3) return P.bank16.get();
+  return P.bank32.get();
+}
+
+// Host image of one launch while a schedule is assembled.
+struct LaunchBuilder {
+  std::vector<M2LItem> items, p2p_items;
+  std::vector<M2LDesc> descs;
+  std::vector<P2PDesc> p2p;
+  std::vector<int32_t> gen_info;
+  std::vector<BankLevel> gen_levels;
+  std::map<std::pair<const Plan*, int>, int32_t> gen_level_index;
+  int64_t n_gen = 0;
+};
+
+// Items of plan P restricted to the bank ids [b0, b1), whose matrices sit
+// at `bank` with bank id b0 at position slot0.
+void add_source(LaunchBuilder& B, const Plan& P, int64_t b0, int64_t b1, const void* bank,
+                int64_t slot0, std::vector<uint8_t>& emitted) {
+  std::vector<int32_t> desc_of(P.levels + 1, -1);
+  for (int l = std::max(P.l_min, 0); l <= P.levels; ++l) {
+    desc_of[l] = static_cast<int32_t>(B.descs.size());
+    B.descs.push_back(level_desc(P, l, bank, b0 - slot0));
+  }
+  const auto& vo = P.valid_off_h;
+  for (size_t i = 0; i < P.base_items.size(); ++i) {
+    const M2LItem& it = P.base_items[i];
+    M2LItem o = it;
+    o.desc = desc_of[it.desc];
+    if (it.vo_count == 0) {  // no source box: stored as zero once
+      if (emitted[i]) continue;
+      o.first = 1;
+    } else {
+      const auto first = vo.begin() + it.vo_begin, last = first + it.vo_count;
+      const auto lo = std::lower_bound(first, last, static_cast<int32_t>(b0));
+      const auto hi = std::lower_bound(lo, last, b1 > INT32_MAX ? INT32_MAX : static_cast<int32_t>(b1));
+      if (lo == hi) continue;
+      o.vo_begin = static_cast<int32_t>(lo - vo.begin());
+      o.vo_count = static_cast<int32_t>(hi - lo);
+      o.first = emitted[i] ? 0 : 1;
+    }
+    emitted[i] = 1;
+    B.items.push_back(o);
+  }
+}
+
+void add_generation(LaunchBuilder& B, const Plan& P, int64_t b0, int64_t b1) {
+  for (int64_t b = b0; b < b1; ++b) {
+    const int32_t* in = &P.bank_info[5 * b];
+    const auto key = std::make_pair(&P, static_cast<int>(in[0]));
+    auto f = B.gen_level_index.find(key);
+    int32_t li;
+    if (f == B.gen_level_index.end()) {
+      li = static_cast<int32_t>(B.gen_levels.size());
+      B.gen_levels.push_back(bank_level(P, in[0]));
+      B.gen_level_index[key] = li;
+    } else {
+      li = f->second;
+    }
+    B.gen_info.insert(B.gen_info.end(), {li, in[1], in[2], in[3], in[4]});
+    ++B.n_gen;
+  }
+}
+
+void add_near_field(LaunchBuilder& B, Plan& P, int chunk) {
+  if (P.nT == 0 || P.nS == 0) return;
+  const int32_t d = static_cast<int32_t>(B.p2p.size());
+  B.p2p.push_back(p2p_desc(P));
+  for (int64_t j = 0; j < P.nT; j += chunk) {
+    const int n = static_cast<int>(std::min<int64_t>(chunk, P.nT - j));
+    B.p2p_items.push_back(M2LItem{-d - 1, 0, static_cast<int32_t>(j), n, 0, 0, 1, 0});
+  }
+}
+
+M2LLaunch upload(LaunchBuilder& B, const TuneConfig& cfg, int prec, int Kp, void* ws,
+                 hipStream_t s) {
+  if (cfg.lpt)  // heaviest items first (longest-processing-time order)
+    std::stable_sort(B.items.begin(), B.items.end(), [](const M2LItem& a, const M2LItem& b) {
+      return a.vo_count > b.vo_count;
+    });
+  M2LLaunch L;
+  L.n_items = static_cast<int64_t>(B.items.size() + B.p2p_items.size());
+  L.n_p2p_items = static_cast<int64_t>(B.p2p_items.size());
+  for (const M2LItem& it : B.items) L.has_parts |= it.first == 0;
+  L.resident_wgs = m2l_resident_groups(prec, cfg.nb, Kp, L.has_parts);
+  B.items.insert(B.items.end(), B.p2p_items.begin(), B.p2p_items.end());
+  to_device(L.items, B.items, s, nullptr);
+  to_device(L.descs, B.descs, s, nullptr);
+  to_device(L.p2p, B.p2p, s, nullptr);
+  L.n_gen = B.n_gen;
+  if (B.n_gen) {
+    to_device(L.gen_info, B.gen_info, s, nullptr);
+    to_device(L.gen_levels, B.gen_levels, s, nullptr);
+    L.gen_dst = ws;
+  }
+  FDM_HIP(hipStreamSynchronize(s));  // host images go out of scope
+  return L;
+}
+
+}  // namespace
+
+std::vector<M2LLaunch> build_schedule(const std::vector<Plan*>& plans, const TuneConfig& cfg,
+                                      void* ws, int64_t ws_matrices, hipStream_t s) {
+  std::vector<LaunchBuilder> B;
+  std::vector<std::vector<uint8_t>> emitted(plans.size());
+  for (size_t p = 0; p < plans.size(); ++p) emitted[p].assign(plans[p]->base_items.size(), 0);
+  // resident banks: one launch
+  for (size_t p = 0; p < plans.size(); ++p) {
+    Plan& P = *plans[p];
+    if (P.base_items.empty() || P.bank_budget != 0) continue;
+    if (B.empty()) B.emplace_back();
+    add_source(B[0], P, 0, P.n_bank, resident_bank(P), 0, emitted[p]);
+  }
+  // streamed banks: packed into launches of at most ws_matrices matrices
+  int64_t left = 0;
+  for (size_t p = 0; p < plans.size(); ++p) {
+    Plan& P = *plans[p];
+    if (P.base_items.empty() || P.bank_budget == 0) continue;
+    if (ws_matrices <= 0) fail(FDM_ERR_INVALID_ARG, "no workspace for a streamed bank");
+    for (int64_t b = 0; b < P.n_bank;) {
+      if (left == 0) {
+        if (B.empty() || B.back().n_gen > 0 || !B.back().items.empty()) B.emplace_back();
+        left = ws_matrices;
+      }
+      const int64_t take = std::min(left, P.n_bank - b);
+      const int64_t slot0 = ws_matrices - left;
+      add_generation(B.back(), P, b, b + take);
+      add_source(B.back(), P, b, b + take, ws, slot0, emitted[p]);
+      left -= take;
+      b += take;
+    }
+  }
+  if (cfg.p2p_in_queue && !plans.empty() &&
+      p2p_queue_supported(plans[0]->prec, plans[0]->ip.Kp)) {
+    if (B.empty()) B.emplace_back();
+    for (Plan* P : plans) add_near_field(B.back(), *P, m2l_threads(P->ip.Kp));
+  }
+  std::vector<M2LLaunch> out;
+  if (plans.empty()) return out;
+  for (auto& b : B) out.push_back(upload(b, cfg, plans[0]->prec, plans[0]->ip.Kp, ws, s));
+  return out;
+}
+
+void run_schedule(std::vector<M2LLaunch>& sched, int32_t* heads, int prec, const Interp& ip,
+                  const TuneConfig& cfg, hipStream_t s) {
+  if (sched.empty()) return;
+  launch_fill_i32(heads, static_cast<int64_t>(sched.size()), 0, s);
+  for (size_t i = 0; i < sched.size(); ++i) {
+    const M2LLaunch& L = sched[i];
+    if (L.n_gen) launch_bank_matrices(L, prec, ip, s);
+    launch_m2l_items(L, prec, ip.Kp, cfg, heads + i, s);
+  }
+}
+
+void build_plan_schedule(Plan& P, hipStream_t s) {
+  void* ws = nullptr;
+  int64_t ws_mats = 0;
+  if (P.bank_budget > 0 && !P.base_items.empty()) {
+    const int64_t mb = bank_matrix_bytes(P.prec, P.ip);
+    ws_mats = std::max<int64_t>(1, std::min(P.n_bank, P.bank_budget / mb));
+    if (P.bank_ws.size() < static_cast<size_t>(ws_mats * mb)) P.bank_ws.alloc(ws_mats * mb, &P.tally);
+    ws = P.bank_ws.get();
+  }
+  P.sched = build_schedule({&P}, P.tune, ws, ws_mats, s);
+  P.heads.alloc(std::max<size_t>(P.sched.size(), 1), &P.tally);
+  P.sched_ready = true;
+}
+
+void launch_bank(Plan& P, hipStream_t s) {
+  // bank id -> (level, offset, direction), for resident and streamed banks
+  P.bank_info.clear();
+  P.bank_info.reserve(5 * P.n_bank);
+  for (int l = 0; l <= P.levels; ++l) {
+    if (l < P.l_min) continue;
+    const LevelTable& T = P.tab[l];
+    for (size_t i = 0; i < T.adm.size(); ++i)
+      P.bank_info.insert(P.bank_info.end(), {l, T.adm[i].x, T.adm[i].y, T.adm[i].z, T.dir[i]});
+  }
+  if (P.n_bank == 0 || P.bank_budget != 0) return;  // streamed: generated per matvec
+  std::vector<BankLevel> bl(P.levels + 1);
+  for (int l = 0; l <= P.levels; ++l) bl[l] = bank_level(P, l);
+  DevBuf<int32_t> d_info;
+  DevBuf<BankLevel> d_bl;
+  to_device(d_info, P.bank_info, s, nullptr);
+  to_device(d_bl, bl, s, nullptr);
+  const int64_t elems = P.n_bank * bank_matrix_bytes(P.prec, P.ip);
+  void* dst = nullptr;
+  if (P.prec == FDM_PREC_FP64) {
+    P.bank64.alloc(elems / 8, &P.tally);
+    dst = P.bank64.get();
+  } else if (P.prec == FDM_PREC_BF16X3) {
+    P.bank16.alloc(elems / 2, &P.tally);
+    dst = P.bank16.get();
+  } else {
+    P.bank32.alloc(elems / 4, &P.tally);
+    dst = P.bank32.get();
+  }
+  launch_bank_direct(d_info.get(), P.n_bank, d_bl.get(), P.prec, P.ip, dst, s);
+  FDM_HIP(hipStreamSynchronize(s));
+}
+
+void build_m2l_work(Plan& P, hipStream_t s) {
+  const int p = P.levels;
+  const int nb = P.tune.nb;
+  std::vector<M2LItem> items;
+  std::vector<int32_t> tgt_list, cand, cand_begin_per_item, cand_count_per_item;
+  std::vector<int4> offtab(P.n_bank);
+  for (int l = 0; l <= p; ++l) {
+    const LevelTable& T = P.tab[l];
+    LevelData& Ld = P.L[l];
+    if (l < P.l_min) continue;
+    for (size_t i = 0; i < T.adm.size(); ++i)
+      offtab[Ld.bank_base + i] = make_int4(T.adm[i].x, T.adm[i].y, T.adm[i].z,
+                                           static_cast<int>(Ld.bank_base + i));
+  }
+  for (int l = std::max(P.l_min, 0); l <= p; ++l) {
+    const LevelTable& T = P.tab[l];
+    const LevelData& Ld = P.L[l];
+    // candidate offsets per (octant, direction)
+    std::vector<std::vector<int32_t>> lists(8 * Ld.nd);
+    for (size_t i = 0; i < T.adm.size(); ++i)
+      for (int q = 0; q < 8; ++q)
+        if (T.mask[i] & (1u << q))
+          lists[q * Ld.nd + T.dir[i]].push_back(static_cast<int32_t>(Ld.bank_base + i));
+    std::vector<int32_t> list_begin(8 * Ld.nd);
+    for (size_t k = 0; k < lists.size(); ++k) {
+      list_begin[k] = static_cast<int32_t>(cand.size());
+      cand.insert(cand.end(), lists[k].begin(), lists[k].end());
+    }
+    // target boxes grouped by octant, in Morton order
+    std::vector<uint32_t> keys = to_host(P.T.key[l].get(), P.T.nb[l], s);
+    std::vector<std::vector<int32_t>> by_oct(8);
+    for (size_t b = 0; b < keys.size(); ++b) by_oct[keys[b] & 7].push_back(static_cast<int32_t>(b));
+    // items ordered (octant, direction, block): one group per (octant,
+    // direction), blocks in Morton order within a group
+    for (int q = 0; q < 8; ++q) {
+      const auto& bx = by_oct[q];
+      std::vector<std::pair<int32_t, int32_t>> blocks;  // (tgt_begin, ntgt)
+      for (size_t b0 = 0; b0 < bx.size(); b0 += nb) {
+        const int nt = static_cast<int>(std::min<size_t>(nb, bx.size() - b0));
+        blocks.push_back({static_cast<int32_t>(tgt_list.size()), nt});
+        tgt_list.insert(tgt_list.end(), bx.begin() + b0, bx.begin() + b0 + nt);
+      }
+      for (int c = 0; c < Ld.nd; ++c)
+        for (auto [tb, nt] : blocks) {
+          items.push_back(M2LItem{l, c, tb, nt, 0, 0, 1, 0});
+          cand_begin_per_item.push_back(list_begin[q * Ld.nd + c]);
+          cand_count_per_item.push_back(static_cast<int32_t>(lists[q * Ld.nd + c].size()));
+        }
+    }
+  }
+  const int64_t n_items = static_cast<int64_t>(items.size());
+  P.offtab.alloc(std::max<int64_t>(P.n_bank, 1), &P.tally);
+  if (P.n_bank)
+    FDM_HIP(hipMemcpyAsync(P.offtab.get(), offtab.data(), offtab.size() * sizeof(int4),
+                           hipMemcpyHostToDevice, s));
+  to_device(P.tgt_list, tgt_list, s, &P.tally);
+  P.base_items.clear();
+  P.valid_off_h.clear();
+  P.sched.clear();
+  P.sched_ready = false;
+  P.m2l_columns = 0;
+  if (n_items == 0) {
+    P.valid_off.alloc(1, &P.tally);
+    FDM_HIP(hipStreamSynchronize(s));
+    return;
+  }
+  std::vector<M2LDesc> descs(p + 1);
+  for (int l = 0; l <= p; ++l) descs[l] = level_desc(P, l, nullptr, 0);
+  DevBuf<M2LDesc> d_descs;
+  to_device(d_descs, descs, s, nullptr);
+  DevBuf<M2LItem> d_items;
+  DevBuf<int32_t> d_cand, d_cb, d_cc, d_counts(n_items), d_begin;
+  to_device(d_items, items, s, nullptr);
+  to_device(d_cand, cand, s, nullptr);
+  to_device(d_cb, cand_begin_per_item, s, nullptr);
+  to_device(d_cc, cand_count_per_item, s, nullptr);
+  DevBuf<unsigned long long> d_bpo(std::max<int64_t>(P.n_bank, 1));
+  FDM_HIP(hipMemsetAsync(d_bpo.get(), 0, d_bpo.bytes(), s));
+  launch_valid_offsets(d_items.get(), n_items, d_cb.get(), d_cc.get(), d_cand.get(),
+                       d_descs.get(), P.tgt_list.get(), P.offtab.get(), 0, d_counts.get(),
+                       nullptr, nullptr, nullptr, s);
+  std::vector<int32_t> counts = to_host(d_counts.get(), n_items, s);
+  std::vector<int32_t> begin(n_items);
+  int64_t total = 0;
+  for (int64_t i = 0; i < n_items; ++i) {
+    begin[i] = static_cast<int32_t>(total);
+    total += counts[i];
+  }
+  if (total > INT32_MAX) fail(FDM_ERR_UNSUPPORTED, "coupling work list too long");
+  to_device(d_begin, begin, s, nullptr);
+  P.valid_off.alloc(std::max<int64_t>(total, 1), &P.tally);
+  launch_valid_offsets(d_items.get(), n_items, d_cb.get(), d_cc.get(), d_cand.get(),
+                       d_descs.get(), P.tgt_list.get(), P.offtab.get(), 1, nullptr,
+                       d_begin.get(), P.valid_off.get(), d_bpo.get(), s);
+  std::vector<unsigned long long> bpo = to_host(d_bpo.get(), P.n_bank, s);
+  P.valid_off_h = to_host(P.valid_off.get(), total, s);
+  for (int64_t i = 0; i < n_items; ++i) {
+    items[i].vo_begin = begin[i];
+    items[i].vo_count = counts[i];
+  }
+  P.base_items = std::move(items);
+  // statistics and per-level offset use for export
+  P.n_couplings = 0;
+  P.n_stored = 0;
+  P.m2l_columns = total * nb;
+  P.off_used.assign(p + 1, {});
+  for (int l = 0; l <= p; ++l) {
+    if (l < P.l_min) continue;
+    const LevelTable& T = P.tab[l];
+    for (size_t i = 0; i < T.adm.size(); ++i) {
+      const unsigned long long n = bpo[P.L[l].bank_base + i];
+      if (!n) continue;
+      P.n_couplings += static_cast<int64_t>(n);
+      P.n_stored += 1;
+      auto& u = P.off_used[l];
+      u.push_back(T.adm[i].x);
+      u.push_back(T.adm[i].y);
+      u.push_back(T.adm[i].z);
+      u.push_back(static_cast<int64_t>(n));
+      u.push_back(T.dir[i]);
+    }
+  }
+  FDM_HIP(hipStreamSynchronize(s));
+}
+
+}  // namespace fdm

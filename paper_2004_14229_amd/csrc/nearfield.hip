@@ -7,57 +7,19 @@
 // level's inadmissible offsets (independent of the target octant: an
 // inadmissible pair always has an inadmissible, hence refined, parent).
 // One thread per target point in tree order, so neighbouring threads share
-// a leaf and read the same source boxes (served from L2).
-#include "plan.hpp"
-#include "device_math.hpp"
+// a leaf and read the same source boxes (served from L2).  The near field is
+// stored into y (it runs before the far field, which is added).
+#include "nearfield.hpp"
 
 namespace fdm {
 
 namespace {
 
-__device__ __forceinline__ void kernel_add(double xt, double yt, double zt, double xs,
-                                           double ys, double zs, double2 v, double kappa,
-                                           double& ar, double& ai) {
-  const double dx = xt - xs, dy = yt - ys, dz = zt - zs;
-  if (xt == xs && yt == ys && zt == zs) return;  // f(x, x) = 0
-  const double r = sqrt(dx * dx + dy * dy + dz * dz);
-  double sn, cs;
-  phase_sincos(kappa * r, sn, cs);
-  const double w = 1.0 / (4.0 * M_PI * r);
-  const double fr = cs * w, fi = sn * w;
-  ar += fr * v.x - fi * v.y;
-  ai += fr * v.y + fi * v.x;
-}
-
-// Thread per target point: loop over the near offsets of its leaf.
-__global__ void __launch_bounds__(256) k_p2p(
-    const double* __restrict__ xt, const double* __restrict__ yt,
-    const double* __restrict__ zt, const int32_t* __restrict__ leaf_of, int64_t nT,
-    const uint32_t* __restrict__ keyT, const double* __restrict__ xs,
-    const double* __restrict__ ys, const double* __restrict__ zs,
-    const double2* __restrict__ v, const int32_t* __restrict__ startS,
-    const int32_t* __restrict__ countS, const int32_t* __restrict__ gridS,
-    const int32_t* __restrict__ near_off, int n_off, int level, double kappa,
-    double2* __restrict__ y_tree) {
+// Thread per target point (stores the near field into y).
+__global__ void __launch_bounds__(256) k_p2p(P2PDesc d, int64_t nT) {
   const int64_t j = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
   if (j >= nT) return;
-  const double px = xt[j], py = yt[j], pz = zt[j];
-  int ix, iy, iz;
-  demorton3(keyT[leaf_of[j]], level, ix, iy, iz);
-  const int lim = 1 << level;
-  double ar = 0.0, ai = 0.0;
-  for (int o = 0; o < n_off; ++o) {
-    const int sx = ix - near_off[3 * o], sy = iy - near_off[3 * o + 1],
-              sz = iz - near_off[3 * o + 2];
-    if (sx < 0 || sy < 0 || sz < 0 || sx >= lim || sy >= lim || sz >= lim) continue;
-    const int32_t sb = gridS[morton3(sx, sy, sz, level)];
-    if (sb < 0) continue;
-    const int k0 = startS[sb], kn = countS[sb];
-    for (int k = k0; k < k0 + kn; ++k)
-      kernel_add(px, py, pz, xs[k], ys[k], zs[k], v[k], kappa, ar, ai);
-  }
-  const double2 prev = y_tree[j];
-  y_tree[j] = make_double2(prev.x + ar, prev.y + ai);
+  reinterpret_cast<double2*>(d.y)[j] = near_value(d, j);
 }
 
 // Dense product: thread per target, source tiles staged in LDS.
@@ -96,15 +58,33 @@ __global__ void __launch_bounds__(kDenseTile) k_dense(
 
 }  // namespace
 
-void launch_p2p(Plan& P, hipStream_t s) {
+P2PDesc p2p_desc(const Plan& P) {
   const int p = P.levels;
-  if (P.nT == 0 || P.nS == 0 || P.n_near_off == 0) return;
+  P2PDesc d{};
+  d.xt = P.T.x.get();
+  d.yt = P.T.y.get();
+  d.zt = P.T.z.get();
+  d.leaf_of = P.T.leaf_of.get();
+  d.keyT = P.T.key[p].get();
+  d.xs = P.S.x.get();
+  d.ys = P.S.y.get();
+  d.zs = P.S.z.get();
+  d.v = P.v_tree.get();
+  d.startS = P.S.start[p].get();
+  d.countS = P.S.count[p].get();
+  d.gridS = P.S.grid[p].get();
+  d.near_off = P.near_off.get();
+  d.y = P.y_tree.get();
+  d.kappa = P.kappa;
+  d.n_off = P.n_near_off;
+  d.level = p;
+  return d;
+}
+
+void launch_p2p(Plan& P, hipStream_t s) {
+  if (P.nT == 0 || P.nS == 0) return;
   const int B = 256;
-  k_p2p<<<static_cast<unsigned>((P.nT + B - 1) / B), B, 0, s>>>(
-      P.T.x.get(), P.T.y.get(), P.T.z.get(), P.T.leaf_of.get(), P.nT, P.T.key[p].get(),
-      P.S.x.get(), P.S.y.get(), P.S.z.get(), reinterpret_cast<const double2*>(P.v_tree.get()),
-      P.S.start[p].get(), P.S.count[p].get(), P.S.grid[p].get(), P.near_off.get(),
-      P.n_near_off, p, P.kappa, reinterpret_cast<double2*>(P.y_tree.get()));
+  k_p2p<<<static_cast<unsigned>((P.nT + B - 1) / B), B, 0, s>>>(p2p_desc(P), P.nT);
   FDM_LAUNCH("k_p2p");
 }
 

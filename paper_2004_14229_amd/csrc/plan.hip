@@ -1,5 +1,6 @@
 // Plan construction, the matvec driver of Alg. 4, and the C ABI (fdm.h).
 #include "plan.hpp"
+#include "capi.hpp"
 
 #include <chrono>
 #include <cmath>
@@ -11,8 +12,6 @@ namespace fdm {
 namespace {
 
 thread_local std::string g_last_error;
-
-void set_error(const std::string& m) { g_last_error = m; }
 
 Interp make_interp(int m) {
   Interp ip{};
@@ -131,20 +130,51 @@ void plan_build(Plan& P, const double* pT, const double* pS, hipStream_t s) {
                    std::chrono::steady_clock::now() - t0).count();
 }
 
+// Forward pass of one plan: user v -> tree order, S2M, M2M.
+void plan_upward(Plan& P, const void* v_user, bool c64, hipStream_t s) {
+  if (c64)
+    launch_permute_in_c64(static_cast<const float*>(v_user), P.S.perm.get(), P.nS,
+                          P.v_tree.get(), s);
+  else
+    launch_permute_in(static_cast<const double*>(v_user), P.S.perm.get(), P.nS,
+                      P.v_tree.get(), s);
+  if (P.l_min <= P.levels) {
+    launch_s2m(P, s);
+    for (int l = P.levels - 1; l >= P.l_min; --l) launch_m2m(P, l, s);
+  }
+}
+
+// Backward pass of one plan: L2L, L2T (added to the near field already in
+// y_tree), tree order -> user y.
+void plan_downward(Plan& P, void* y_user, bool c64, hipStream_t s) {
+  if (P.l_min <= P.levels)
+    for (int l = P.l_min; l < P.levels; ++l) launch_l2l(P, l, s);
+  launch_l2t(P, s);
+  if (c64)
+    launch_permute_out_c64(P.y_tree.get(), P.T.perm.get(), P.nT, static_cast<float*>(y_user), s);
+  else
+    launch_permute_out(P.y_tree.get(), P.T.perm.get(), P.nT, static_cast<double*>(y_user), s);
+}
+
+void plan_zero_output(Plan& P, void* y_user, bool c64, hipStream_t s) {
+  launch_zero_c128(P.y_tree.get(), P.nT, s);
+  if (c64)
+    launch_permute_out_c64(P.y_tree.get(), P.T.perm.get(), P.nT, static_cast<float*>(y_user), s);
+  else
+    launch_permute_out(P.y_tree.get(), P.T.perm.get(), P.nT, static_cast<double*>(y_user), s);
+}
+
 void plan_matvec(Plan& P, const void* v_user, void* y_user, bool c64, hipStream_t s) {
-  const int p = P.levels;
   if (P.nT == 0) return;
   if (P.nS == 0) {  // no sources: y = 0
-    launch_zero_c128(P.y_tree.get(), P.nT, s);
-    if (c64)
-      launch_permute_out_c64(P.y_tree.get(), P.T.perm.get(), P.nT, static_cast<float*>(y_user), s);
-    else
-      launch_permute_out(P.y_tree.get(), P.T.perm.get(), P.nT, static_cast<double*>(y_user), s);
+    plan_zero_output(P, y_user, c64, s);
     return;
   }
+  if (!P.sched_ready) build_plan_schedule(P, s);
   auto mark = [&](int i) {
     if (P.timing) FDM_HIP(hipEventRecord(P.ev[i], s));
   };
+  const int p = P.levels;
   mark(0);
   if (c64)
     launch_permute_in_c64(static_cast<const float*>(v_user), P.S.perm.get(), P.nS,
@@ -157,14 +187,14 @@ void plan_matvec(Plan& P, const void* v_user, void* y_user, bool c64, hipStream_
   if (P.l_min <= p)
     for (int l = p - 1; l >= P.l_min; --l) launch_m2m(P, l, s);
   mark(2);
-  if (P.l_min <= p) launch_m2l(P, s);                   // multiplication phase
+  run_schedule(P.sched, P.heads.get(), P.prec, P.ip, P.tune, s);  // multiplication phase
   mark(3);
+  if (!P.tune.p2p_in_queue || !p2p_queue_supported(P.prec, P.ip.Kp)) launch_p2p(P, s);           // near field (stored)
+  mark(4);
   if (P.l_min <= p)
     for (int l = P.l_min; l < p; ++l) launch_l2l(P, l, s);  // backward transformation
-  mark(4);
-  launch_l2t(P, s);
   mark(5);
-  launch_p2p(P, s);                                     // near field
+  launch_l2t(P, s);                                     // far field (added)
   mark(6);
   if (c64)
     launch_permute_out_c64(P.y_tree.get(), P.T.perm.get(), P.nT, static_cast<float*>(y_user), s);
@@ -180,25 +210,10 @@ void plan_matvec(Plan& P, const void* v_user, void* y_user, bool c64, hipStream_
 // ====================================================================== C ABI
 using namespace fdm;
 
-namespace {
+namespace fdm {
 
-template <class F>
-int guarded(F&& f) {
-  try {
-    g_last_error.clear();
-    f();
-    return FDM_OK;
-  } catch (const Error& e) {
-    set_error(e.what());
-    return e.status;
-  } catch (const std::bad_alloc&) {
-    set_error("host allocation failed");
-    return FDM_ERR_OUT_OF_MEMORY;
-  } catch (const std::exception& e) {
-    set_error(e.what());
-    return FDM_ERR_STATE;
-  }
-}
+void set_error(const std::string& m) { g_last_error = m; }
+void clear_error() { g_last_error.clear(); }
 
 void check_device_ptr(const void* p, const char* what) {
   if (!p) fail(FDM_ERR_INVALID_ARG, std::string(what) + " is NULL");
@@ -211,16 +226,48 @@ void check_device_ptr(const void* p, const char* what) {
     fail(FDM_ERR_INVALID_ARG, std::string(what) + " is not device memory");
 }
 
-}  // namespace
+TuneConfig check_tune(const fdm_tune& t) {
+  if (t.nb != 32 && t.nb != 64) fail(FDM_ERR_INVALID_ARG, "tune.nb must be 32 or 64");
+  for (int v : {t.persistent, t.lpt, t.p2p_in_queue})
+    if (v != 0 && v != 1) fail(FDM_ERR_INVALID_ARG, "tune flags must be 0 or 1");
+  TuneConfig c;
+  c.nb = t.nb;
+  c.persistent = t.persistent;
+  c.lpt = t.lpt;
+  c.p2p_in_queue = t.p2p_in_queue;
+  return c;
+}
+
+fdm_tune to_c(const TuneConfig& c) {
+  fdm_tune t{};
+  t.nb = c.nb;
+  t.persistent = c.persistent;
+  t.lpt = c.lpt;
+  t.p2p_in_queue = c.p2p_in_queue;
+  return t;
+}
+
+void apply_plan_tune(Plan& P, const TuneConfig& c, hipStream_t s) {
+  const bool rebuild = c.nb != P.tune.nb;
+  P.tune = c;
+  if (rebuild && P.l_min <= P.levels) build_m2l_work(P, s);
+  P.sched.clear();
+  P.sched_ready = false;
+  FDM_HIP(hipStreamSynchronize(s));
+}
+
+}  // namespace fdm
 
 extern "C" {
 
-int fdm_build_tree_ex(const double* points_T, int64_t n_T, const double* points_S,
-                      int64_t n_S, double kappa, const double box[6], int levels, int m,
-                      int precision, int l_hf, void* stream, fdm_plan** out) {
+int fdm_build_tree_opts(const double* points_T, int64_t n_T, const double* points_S,
+                        int64_t n_S, double kappa, const double box[6], int levels, int m,
+                        const fdm_options* opts, void* stream, fdm_plan** out) {
   return guarded([&] {
     if (!out) fail(FDM_ERR_INVALID_ARG, "out is NULL");
     *out = nullptr;
+    if (!opts) fail(FDM_ERR_INVALID_ARG, "opts is NULL");
+    const int precision = opts->precision, l_hf = opts->l_hf;
     if (n_T < 0 || n_S < 0) fail(FDM_ERR_INVALID_ARG, "negative point count");
     if (n_T > INT32_MAX / 2 || n_S > INT32_MAX / 2)
       fail(FDM_ERR_UNSUPPORTED, "point count too large");
@@ -231,6 +278,9 @@ int fdm_build_tree_ex(const double* points_T, int64_t n_T, const double* points_
     if (precision < FDM_PREC_FP64 || precision > FDM_PREC_BF16X3)
       fail(FDM_ERR_INVALID_ARG, "unknown precision");
     if (l_hf < -2 || l_hf > levels) fail(FDM_ERR_INVALID_ARG, "l_hf out of range");
+    if (opts->bank_budget_bytes < 0) fail(FDM_ERR_INVALID_ARG, "negative bank budget");
+    TuneConfig tune;
+    if (opts->tune.nb != 0) tune = check_tune(opts->tune);
     for (int d = 0; d < 3; ++d)
       if (!std::isfinite(box[d]) || !std::isfinite(box[d + 3]) || !(box[d + 3] > box[d]))
         fail(FDM_ERR_INVALID_ARG, "invalid box");
@@ -255,6 +305,14 @@ int fdm_build_tree_ex(const double* points_T, int64_t n_T, const double* points_
       P.m = m;
       P.prec = precision;
       P.l_hf = l_hf;
+      P.tune = tune;
+      P.bank_budget = opts->bank_budget_bytes;
+      if (P.bank_budget > 0) {
+        Interp ip{};
+        ip.Kp = (K + 31) / 32 * 32;
+        if (P.bank_budget < bank_matrix_bytes(precision, ip))
+          fail(FDM_ERR_INVALID_ARG, "bank budget below one coupling matrix");
+      }
       plan_build(P, points_T, points_S, static_cast<hipStream_t>(stream));
     } catch (...) {
       (void)hipStreamSynchronize(static_cast<hipStream_t>(stream));
@@ -265,11 +323,37 @@ int fdm_build_tree_ex(const double* points_T, int64_t n_T, const double* points_
   });
 }
 
+int fdm_build_tree_ex(const double* points_T, int64_t n_T, const double* points_S,
+                      int64_t n_S, double kappa, const double box[6], int levels, int m,
+                      int precision, int l_hf, void* stream, fdm_plan** out) {
+  fdm_options o{};
+  o.precision = precision;
+  o.l_hf = l_hf;
+  return fdm_build_tree_opts(points_T, n_T, points_S, n_S, kappa, box, levels, m, &o, stream,
+                             out);
+}
+
 int fdm_build_tree(const double* points_T, int64_t n_T, const double* points_S,
                    int64_t n_S, double kappa, const double box[6], int levels, int m,
                    int precision, void* stream, fdm_plan** out) {
   return fdm_build_tree_ex(points_T, n_T, points_S, n_S, kappa, box, levels, m, precision,
                            -2, stream, out);
+}
+
+int fdm_plan_get_tune(const fdm_plan* plan, fdm_tune* out) {
+  return guarded([&] {
+    if (!plan || !out) fail(FDM_ERR_INVALID_ARG, "NULL argument");
+    *out = to_c(plan->p.tune);
+  });
+}
+
+int fdm_plan_set_tune(fdm_plan* plan, const fdm_tune* tune, void* stream) {
+  return guarded([&] {
+    if (!plan || !tune) fail(FDM_ERR_INVALID_ARG, "NULL argument");
+    Plan& P = plan->p;
+    if (P.batch_owner) fail(FDM_ERR_STATE, "the plan belongs to a batch");
+    apply_plan_tune(P, check_tune(*tune), static_cast<hipStream_t>(stream));
+  });
 }
 
 static int matvec_entry(fdm_plan* plan, const void* v, void* y, void* stream, bool c64) {
@@ -320,7 +404,9 @@ int fdm_plan_phase_ms(const fdm_plan* plan, double ms[7]) {
     const Plan& P = plan->p;
     if (!P.timing || !P.timed_run) fail(FDM_ERR_STATE, "no timed matvec");
     FDM_HIP(hipEventSynchronize(P.ev[7]));
-    const int pairs[6][2] = {{0, 1}, {1, 2}, {2, 3}, {3, 4}, {4, 5}, {5, 6}};
+    // S2M, M2M, M2L (with the near field when it shares the launch), L2L,
+    // L2T, near field
+    const int pairs[6][2] = {{0, 1}, {1, 2}, {2, 3}, {4, 5}, {5, 6}, {3, 4}};
     for (int i = 0; i < 6; ++i) {
       float t = 0;
       FDM_HIP(hipEventElapsedTime(&t, P.ev[pairs[i][0]], P.ev[pairs[i][1]]));
@@ -335,6 +421,7 @@ int fdm_plan_phase_ms(const fdm_plan* plan, double ms[7]) {
 int fdm_plan_destroy(fdm_plan* plan) {
   return guarded([&] {
     if (!plan) return;
+    if (plan->p.batch_owner) fail(FDM_ERR_STATE, "the plan belongs to a batch");
     (void)hipDeviceSynchronize();
     for (auto& e : plan->p.ev)
       if (e) (void)hipEventDestroy(e);

@@ -1,5 +1,6 @@
 // The plan: trees, block-partition tables, direction tables, coupling bank
-// and the workspaces of one fast directional matvec.
+// and the workspaces of one fast directional matvec; and the batch of plans
+// whose coupling and near-field work runs from one device queue.
 #pragma once
 
 #include <array>
@@ -36,30 +37,83 @@ int direction_index(int level, int l_hf, const Off& o);
 std::vector<double> direction_vectors(int level, int l_hf);  // nd * 3
 int direction_count(int level, int l_hf);
 
-// Coupling-kernel work item: one block of <= kNB target boxes of one octant
-// on one level, for one direction, with its list of offsets that hit at
-// least one non-empty source box.
-constexpr int kNB = 64;
-// One wave per 32 padded rows: Kp <= 384, i.e. m <= 6, in the coupling kernels.
+// ------------------------------------------------------- coupling work --
+// A coupling work item is a block of <= nb target boxes (nb = 32 or 64) of
+// one octant on one level, for one direction, with the list of offsets that
+// hit at least one non-empty source box.  One wave per 32 padded rows:
+// Kp <= 384, i.e. m <= 6, in the coupling kernels.
+constexpr int kMaxNB = 64;
 constexpr int kM2LMaxThreads = 768;
 constexpr int kMaxKp = kM2LMaxThreads / 2;
-struct M2LItem {
-  int32_t level;
-  int32_t c;
-  int32_t tgt_begin;  // into tgt_list
-  int32_t ntgt;
-  int32_t vo_begin;   // into valid_off
-  int32_t vo_count;
+
+// Descriptor of one (plan, level) of a coupling launch.
+struct M2LDesc {
+  const int32_t* gridS;      // source box grid of the level
+  const uint32_t* keyT;      // target box keys of the level
+  const void* mom;           // operand moments [nbS][nd][Kp] complex
+  void* out;                 // FP64 result [nbT][nd][Kp] complex
+  const int32_t* tgt_list;   // target boxes of the plan's items
+  const int32_t* valid_off;  // bank ids of the plan's items' offsets
+  const int4* offtab;        // per bank id: offset x, y, z and bank id
+  // bank id b is matrix b counted from `bank`; for a workspace holding a
+  // range of ids this address lies before the workspace (never read there)
+  const void* bank;
+  int32_t nd, level;
 };
 
-// Per-level device view used by the coupling kernel.
-struct M2LLevel {
-  const int32_t* gridS;   // source box grid of the level
-  const uint32_t* keyT;   // target box keys
-  const void* mom;        // operand moments [nbS][nd][Kp] complex
-  void* out;              // coupling result [nbT][nd][Kp] complex
-  int32_t nd;
-  int32_t level;
+// Descriptor of one plan's near field in a queued launch.
+struct P2PDesc {
+  const double *xt, *yt, *zt;
+  const int32_t* leaf_of;
+  const uint32_t* keyT;  // leaf keys of the target tree
+  const double *xs, *ys, *zs;
+  const double* v;       // complex128 charges, tree order
+  const int32_t *startS, *countS, *gridS;
+  const int32_t* near_off;
+  double* y;             // complex128 result, tree order (stored)
+  double kappa;
+  int32_t n_off, level;
+};
+
+// Queue item.  desc >= 0: coupling item of descriptor `desc` -- targets
+// tgt_list[tgt_begin .. +ntgt), direction c, offsets valid_off[vo_begin ..
+// +vo_count); `first` = 1 for the first part of a (target block, c), whose
+// result is stored, 0 for later parts (streamed banks), which add to it.
+// desc < 0: near-field item of P2P descriptor -desc-1 for target points
+// tgt_begin .. +ntgt (tree order).
+struct M2LItem {
+  int32_t desc, c, tgt_begin, ntgt, vo_begin, vo_count, first, pad;
+};
+
+// One matrix to generate into a streamed bank: level descriptor index,
+// offset and direction.
+struct BankLevel {
+  const double* dirvec;
+  double h, kappa;
+  int32_t level, nd;
+};
+
+// Launch shape and order picked by the autotuner.
+struct TuneConfig {
+  int nb = 64;           // target boxes per coupling item (32 or 64)
+  int persistent = 1;    // 1: persistent workgroups pulling from a device queue
+  int lpt = 1;           // 1: heaviest items first; 0: (level, octant, direction, block)
+  int p2p_in_queue = 0;  // near-field items in the coupling launch
+};
+
+// One coupling launch: optional bank generation into a workspace, then the
+// queue of items over the descriptors.
+struct M2LLaunch {
+  int64_t n_gen = 0;
+  DevBuf<int32_t> gen_info;     // per matrix: bank level index, ox, oy, oz, c
+  DevBuf<BankLevel> gen_levels;
+  void* gen_dst = nullptr;      // workspace (matrices in gen order)
+  int64_t n_items = 0, n_p2p_items = 0;
+  int64_t resident_wgs = 0;     // grid of the persistent launch
+  bool has_parts = false;       // holds later parts of split items
+  DevBuf<M2LItem> items;
+  DevBuf<M2LDesc> descs;
+  DevBuf<P2PDesc> p2p;
 };
 
 struct LevelData {
@@ -90,18 +144,27 @@ struct Plan {
   std::vector<LevelTable> tab;
   std::vector<LevelData> L;  // index = level
 
-  // coupling bank: one K x K complex matrix per admissible (level, offset)
+  // coupling bank: one K x K complex matrix per admissible (level, offset),
+  // resident, or generated chunk by chunk into a workspace of at most
+  // bank_budget bytes during each matvec (streamed)
   int64_t n_bank = 0;
+  int64_t bank_budget = 0;  // 0: resident
   DevBuf<double> bank64;
   DevBuf<float> bank32;
   DevBuf<uint16_t> bank16;
+  DevBuf<uint8_t> bank_ws;
+  std::vector<int32_t> bank_info;  // per bank id: level, ox, oy, oz, c
 
-  // coupling work
-  DevBuf<M2LItem> items;
+  // coupling work (per plan; a batch builds its own launches from it)
+  TuneConfig tune;
+  std::vector<M2LItem> base_items;  // desc = level, first = 1, in build order
+  std::vector<int32_t> valid_off_h;
   DevBuf<int32_t> tgt_list, valid_off;
-  DevBuf<M2LLevel> m2l_levels;
   DevBuf<int4> offtab;  // per bank matrix: offset x, y, z and bank id
-  int64_t n_items = 0;
+  std::vector<M2LLaunch> sched;
+  DevBuf<int32_t> heads;  // one queue head per launch
+  bool sched_ready = false;
+  const void* batch_owner = nullptr;  // the batch holding this plan, if any
 
   // near field
   DevBuf<int32_t> near_off;  // x, y, z triples at the leaf level
@@ -110,7 +173,6 @@ struct Plan {
   // workspaces
   DevBuf<double> v_tree;  // complex128 [nS]
   DevBuf<double> y_tree;  // complex128 [nT]
-  DevBuf<double> io64;    // complex128 staging for complex64 I/O
 
   // statistics
   int64_t n_couplings = 0, n_stored = 0, near_pairs = 0, near_entries = 0;
@@ -129,8 +191,12 @@ struct Plan {
 void plan_build(Plan& P, const double* pT, const double* pS, hipStream_t s);
 // v_user / y_user are complex128, or complex64 when c64 is set.
 void plan_matvec(Plan& P, const void* v_user, void* y_user, bool c64, hipStream_t s);
+// The parts of a matvec around the coupling launches (batched matvecs).
+void plan_upward(Plan& P, const void* v_user, bool c64, hipStream_t s);
+void plan_downward(Plan& P, void* y_user, bool c64, hipStream_t s);
+void plan_zero_output(Plan& P, void* y_user, bool c64, hipStream_t s);
 
-// kernel launchers (upward.hip, downward.hip, nearfield.hip, m2l.hip)
+// ------------------------------------------------------------ kernels --
 void launch_permute_in(const double* v_user, const int32_t* perm, int64_t n,
                        double* v_tree, hipStream_t s);
 void launch_permute_out(const double* y_tree, const int32_t* perm, int64_t n,
@@ -143,17 +209,88 @@ void launch_s2m(Plan& P, hipStream_t s);
 void launch_m2m(Plan& P, int level, hipStream_t s);
 void launch_l2l(Plan& P, int level, hipStream_t s);
 void launch_zero_c128(double* p, int64_t n, hipStream_t s);
-void launch_l2t(Plan& P, hipStream_t s);
-void launch_p2p(Plan& P, hipStream_t s);
-void launch_bank(Plan& P, hipStream_t s);
-void launch_m2l(Plan& P, hipStream_t s);
-void build_m2l_work(Plan& P, hipStream_t s);
+void launch_fill_i32(int32_t* p, int64_t n, int32_t value, hipStream_t s);
+void launch_l2t(Plan& P, hipStream_t s);  // adds the far field to y_tree
+void launch_p2p(Plan& P, hipStream_t s);  // stores the near field into y_tree
 void launch_dense(const double* pT, int64_t nT, const double* pS, int64_t nS,
                   double kappa, const double* v, double* y, hipStream_t s);
+P2PDesc p2p_desc(const Plan& P);
+
+// coupling work and schedules (m2l_work.hip)
+void launch_bank(Plan& P, hipStream_t s);  // resident bank
+void build_m2l_work(Plan& P, hipStream_t s);  // base items for P.tune.nb
+int64_t bank_matrix_bytes(int prec, const Interp& ip);
+// Rebuild the plan's own launches (after a change of its tune config).
+void build_plan_schedule(Plan& P, hipStream_t s);
+// A bank range [b0, b1) of one plan in a coupling launch.
+struct SchedSource {
+  Plan* P;
+  int64_t b0, b1;
+};
+// Launches covering every coupling item of `plans` once (and their near
+// field when cfg.p2p_in_queue): resident banks in one launch; streamed
+// banks packed into launches of at most ws_matrices generated matrices.
+std::vector<M2LLaunch> build_schedule(const std::vector<Plan*>& plans, const TuneConfig& cfg,
+                                      void* ws, int64_t ws_matrices, hipStream_t s);
+void run_schedule(std::vector<M2LLaunch>& sched, int32_t* heads, int prec, const Interp& ip,
+                  const TuneConfig& cfg, hipStream_t s);
+
+// coupling kernels (m2l.hip)
+void launch_bank_matrices(const M2LLaunch& L, int prec, const Interp& ip, hipStream_t s);
+void launch_bank_direct(const int32_t* info, int64_t n_mat, const BankLevel* lv, int prec,
+                        const Interp& ip, void* dst, hipStream_t s);
+void launch_m2l_items(const M2LLaunch& L, int prec, int Kp, const TuneConfig& cfg,
+                      int32_t* head, hipStream_t s);
+void launch_valid_offsets(const M2LItem* items, int64_t n_items, const int32_t* cand_begin,
+                          const int32_t* cand_count, const int32_t* cand, const M2LDesc* descs,
+                          const int32_t* tgt_list, const int4* offtab, int pass,
+                          int32_t* counts, const int32_t* out_begin, int32_t* out,
+                          unsigned long long* blocks_per_off, hipStream_t s);
+int m2l_threads(int Kp);
+// Near-field items can share the coupling launch (FP32 / BF16, Kp <= 256);
+// otherwise the near field runs as its own launch whatever the tune says.
+inline bool p2p_queue_supported(int prec, int Kp) {
+  return prec != FDM_PREC_FP64 && Kp <= 256;
+}
+int64_t m2l_resident_groups(int prec, int nb, int Kp, bool parts);
+// per-precision coupling launches (m2l_f64.hip, m2l_f32.hip, m2l_bf16.hip)
+void launch_items_f64(const M2LLaunch& L, int Kp, int nb, bool persistent, int32_t* head,
+                      hipStream_t s);
+void launch_items_f32(const M2LLaunch& L, int Kp, int nb, bool persistent, int32_t* head,
+                      hipStream_t s);
+void launch_items_bf16(const M2LLaunch& L, int Kp, int nb, bool persistent, int32_t* head,
+                       hipStream_t s);
+int64_t resident_f64(int nb, int Kp, bool parts);
+int64_t resident_f32(int nb, int Kp, bool parts);
+int64_t resident_bf16(int nb, int Kp, bool parts);
+
+// launch-shape helpers of the C ABI (plan.hip)
+TuneConfig check_tune(const fdm_tune& t);
+fdm_tune to_c(const TuneConfig& c);
+void apply_plan_tune(Plan& P, const TuneConfig& c, hipStream_t s);
 
 }  // namespace fdm
 
-// The opaque handle of the C ABI.
+// The opaque handles of the C ABI.
 struct fdm_plan {
   fdm::Plan p;
+};
+
+struct fdm_batch {
+  std::vector<fdm::Plan*> plans;
+  int prec = 0;
+  fdm::Interp ip;
+  fdm::TuneConfig tune;
+  int64_t ws_bytes = 0;
+  fdm::DevBuf<uint8_t> ws;
+  std::vector<fdm::M2LLaunch> sched;
+  fdm::DevBuf<int32_t> heads;
+  // graph of the whole batched matvec, for the pointers it was captured with
+  hipGraphExec_t graph = nullptr;
+  std::vector<const void*> graph_v;
+  std::vector<void*> graph_y;
+  hipStream_t graph_stream = nullptr;
+  int graph_c64 = -1;
+  bool use_graph = true;
+  int64_t tally = 0;
 };

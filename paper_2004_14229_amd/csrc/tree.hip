@@ -164,4 +164,10 @@ void build_tree(const double* pts_user, int64_t n, const double lo[3],
   FDM_HIP(hipStreamSynchronize(s));
 }
 
+void launch_fill_i32(int32_t* p, int64_t n, int32_t value, hipStream_t s) {
+  if (n == 0) return;
+  k_fill_i32<<<grid_for(n, 256), 256, 0, s>>>(p, n, value);
+  FDM_LAUNCH("k_fill_i32");
+}
+
 }  // namespace fdm

@@ -33,6 +33,23 @@ class FdmError(RuntimeError):
         self.status = status
 
 
+class Tune(ctypes.Structure):
+    _fields_ = [("nb", ctypes.c_int32), ("persistent", ctypes.c_int32),
+                ("lpt", ctypes.c_int32), ("p2p_in_queue", ctypes.c_int32)]
+
+    def as_dict(self) -> dict:
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+    @classmethod
+    def from_dict(cls, d: dict) -> "Tune":
+        return cls(*(int(d[name]) for name, _ in cls._fields_))
+
+
+class Options(ctypes.Structure):
+    _fields_ = [("precision", ctypes.c_int32), ("l_hf", ctypes.c_int32),
+                ("bank_budget_bytes", ctypes.c_int64), ("tune", Tune)]
+
+
 class Stats(ctypes.Structure):
     _fields_ = [("n_T", ctypes.c_int64), ("n_S", ctypes.c_int64),
                 ("levels", ctypes.c_int32), ("m", ctypes.c_int32),
@@ -72,12 +89,29 @@ def lib() -> ctypes.CDLL:
     L.fdm_dense_matvec.argtypes = [vp, i64, vp, i64, dbl, vp, vp, vp]
     L.fdm_plan_set_timing.argtypes = [vp, ci]
     L.fdm_plan_phase_ms.argtypes = [vp, ctypes.POINTER(dbl)]
+    L.fdm_build_tree_opts.argtypes = [vp, i64, vp, i64, dbl, ctypes.POINTER(dbl), ci, ci,
+                                      ctypes.POINTER(Options), vp, ctypes.POINTER(vp)]
+    L.fdm_plan_get_tune.argtypes = [vp, ctypes.POINTER(Tune)]
+    L.fdm_plan_set_tune.argtypes = [vp, ctypes.POINTER(Tune), vp]
+    L.fdm_plan_autotune.argtypes = [vp, vp, vp, ci, ci, vp, ctypes.POINTER(Tune),
+                                    ctypes.POINTER(dbl)]
+    L.fdm_batch_create.argtypes = [ctypes.POINTER(vp), ci, i64, vp, ctypes.POINTER(vp)]
+    L.fdm_batch_matvec.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(vp), ci, vp]
+    L.fdm_batch_set_graph.argtypes = [vp, ci]
+    L.fdm_batch_get_tune.argtypes = [vp, ctypes.POINTER(Tune)]
+    L.fdm_batch_set_tune.argtypes = [vp, ctypes.POINTER(Tune), vp]
+    L.fdm_batch_autotune.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(vp), ci, ci, vp,
+                                     ctypes.POINTER(Tune), ctypes.POINTER(dbl)]
+    L.fdm_batch_destroy.argtypes = [vp]
     L.fdm_last_error.restype = ctypes.c_char_p
     L.fdm_version.restype = ctypes.c_char_p
-    for f in ("fdm_build_tree", "fdm_build_tree_ex", "fdm_plan_matvec",
+    for f in ("fdm_build_tree", "fdm_build_tree_ex", "fdm_build_tree_opts", "fdm_plan_matvec",
               "fdm_plan_matvec_c64", "fdm_plan_destroy", "fdm_plan_stats",
               "fdm_plan_export", "fdm_dense_matvec", "fdm_plan_set_timing",
-              "fdm_plan_phase_ms"):
+              "fdm_plan_phase_ms", "fdm_plan_get_tune", "fdm_plan_set_tune",
+              "fdm_plan_autotune", "fdm_batch_create", "fdm_batch_matvec",
+              "fdm_batch_set_graph", "fdm_batch_get_tune", "fdm_batch_set_tune",
+              "fdm_batch_autotune", "fdm_batch_destroy"):
         getattr(L, f).restype = ci
     _lib = L
     return L
@@ -111,14 +145,16 @@ class Plan:
     """A built plan of the fast directional matvec (wraps ``fdm_plan*``)."""
 
     def __init__(self, points_T, points_S, kappa: float, box, levels: int, m: int,
-                 precision: str = "fp64", l_hf: int | None = None, stream=None):
+                 precision: str = "fp64", l_hf: int | None = None, stream=None,
+                 bank_budget: int = 0, tune: dict | None = None):
         pt, ps = _points(points_T), _points(points_S)
         box_arr = (ctypes.c_double * 6)(*[float(b) for b in box])
+        opts = Options(PRECISION[precision], -2 if l_hf is None else int(l_hf),
+                       int(bank_budget), Tune.from_dict(tune) if tune else Tune(0, 0, 0, 0))
         h = ctypes.c_void_p()
-        st = lib().fdm_build_tree_ex(
+        st = lib().fdm_build_tree_opts(
             _ptr(pt), pt.shape[0], _ptr(ps), ps.shape[0], float(kappa), box_arr,
-            int(levels), int(m), PRECISION[precision], -2 if l_hf is None else int(l_hf),
-            _stream_handle(stream), ctypes.byref(h))
+            int(levels), int(m), ctypes.byref(opts), _stream_handle(stream), ctypes.byref(h))
         _check(st)
         self._h = h
         self.n_T, self.n_S = pt.shape[0], ps.shape[0]
@@ -161,6 +197,29 @@ class Plan:
             return buf.reshape(-1, 3)
         return buf
 
+    def get_tune(self) -> dict:
+        t = Tune()
+        _check(lib().fdm_plan_get_tune(self._h, ctypes.byref(t)))
+        return t.as_dict()
+
+    def set_tune(self, tune: dict, stream=None) -> None:
+        t = Tune.from_dict({**self.get_tune(), **tune})
+        _check(lib().fdm_plan_set_tune(self._h, ctypes.byref(t), _stream_handle(stream)))
+
+    def autotune(self, v, out=None, max_candidates: int = 8, stream=None):
+        """Time the coupling step under each launch shape and keep the
+        fastest; also computes ``out = A~ v``.  Returns (best, times_ms, out)."""
+        import torch
+        v = v.contiguous()
+        if out is None:
+            out = torch.empty(self.n_T, dtype=v.dtype, device=v.device)
+        best = Tune()
+        ms = (ctypes.c_double * max_candidates)()
+        _check(lib().fdm_plan_autotune(self._h, _ptr(v), _ptr(out),
+                                       int(v.dtype == torch.complex64), int(max_candidates),
+                                       _stream_handle(stream), ctypes.byref(best), ms))
+        return best.as_dict(), list(ms), out
+
     PHASES = ("s2m", "m2m", "m2l", "l2l", "l2t", "near", "total")
 
     def set_timing(self, enable: bool = True) -> None:
@@ -174,8 +233,9 @@ class Plan:
         return dict(zip(self.PHASES, list(out)))
 
     def close(self) -> None:
+        """Free the plan (FdmError while it belongs to a live batch)."""
         if getattr(self, "_h", None) is not None and self._h.value:
-            lib().fdm_plan_destroy(self._h)
+            _check(lib().fdm_plan_destroy(self._h))
             self._h = None
 
     def __del__(self):
@@ -203,3 +263,85 @@ def dense_matvec(points_T, points_S, kappa: float, v, out=None, stream=None):
     _check(lib().fdm_dense_matvec(_ptr(pt), pt.shape[0], _ptr(ps), ps.shape[0], float(kappa),
                                   _ptr(v), _ptr(out), _stream_handle(stream)))
     return out
+
+
+class Batch:
+    """Many plans (same m and precision) whose matvecs run together: one
+    device queue for all coupling work and near fields, the whole batched
+    matvec captured in a HIP graph (wraps ``fdm_batch*``).  The plans must
+    outlive the batch."""
+
+    def __init__(self, plans, workspace_bytes: int = 0, stream=None):
+        self.plans = list(plans)
+        arr = (ctypes.c_void_p * len(self.plans))(*[p._h.value for p in self.plans])
+        h = ctypes.c_void_p()
+        _check(lib().fdm_batch_create(arr, len(self.plans), int(workspace_bytes),
+                                      _stream_handle(stream), ctypes.byref(h)))
+        self._h = h
+
+    def _vectors(self, vs, outs):
+        import torch
+        if len(vs) != len(self.plans):
+            raise ValueError("one v per plan")
+        dtype = vs[0].dtype
+        if dtype not in (torch.complex128, torch.complex64):
+            raise TypeError("v must be complex128 or complex64")
+        vs = [v.contiguous() for v in vs]
+        for v, p in zip(vs, self.plans):
+            if v.dtype != dtype or v.shape != (p.n_S,) or not v.is_cuda:
+                raise TypeError("each v must be a CUDA vector of its plan's n_S, one dtype")
+        if outs is None:
+            outs = [torch.empty(p.n_T, dtype=dtype, device=vs[0].device) for p in self.plans]
+        for y, p in zip(outs, self.plans):
+            if y.dtype != dtype or y.shape != (p.n_T,) or not y.is_contiguous():
+                raise TypeError("each out must be a contiguous vector of its plan's n_T")
+        n = len(self.plans)
+        va = (ctypes.c_void_p * n)(*[v.data_ptr() if v.numel() else None for v in vs])
+        ya = (ctypes.c_void_p * n)(*[y.data_ptr() if y.numel() else None for y in outs])
+        return vs, outs, va, ya, int(dtype == torch.complex64)
+
+    def matvec(self, vs, outs=None, stream=None):
+        """``outs[i] = A~_i vs[i]`` for every plan; returns outs."""
+        vs, outs, va, ya, c64 = self._vectors(vs, outs)
+        _check(lib().fdm_batch_matvec(self._h, va, ya, c64, _stream_handle(stream)))
+        return outs
+
+    def set_graph(self, enable: bool) -> None:
+        _check(lib().fdm_batch_set_graph(self._h, int(enable)))
+
+    def get_tune(self) -> dict:
+        t = Tune()
+        _check(lib().fdm_batch_get_tune(self._h, ctypes.byref(t)))
+        return t.as_dict()
+
+    def set_tune(self, tune: dict, stream=None) -> None:
+        t = Tune.from_dict({**self.get_tune(), **tune})
+        _check(lib().fdm_batch_set_tune(self._h, ctypes.byref(t), _stream_handle(stream)))
+
+    def autotune(self, vs, outs=None, max_candidates: int = 4, stream=None):
+        """Time the batch's coupling launches under each candidate launch
+        shape and keep the fastest; also computes outs.  Returns
+        (best, times_ms, outs)."""
+        vs, outs, va, ya, c64 = self._vectors(vs, outs)
+        best = Tune()
+        ms = (ctypes.c_double * max_candidates)()
+        _check(lib().fdm_batch_autotune(self._h, va, ya, c64, int(max_candidates),
+                                        _stream_handle(stream), ctypes.byref(best), ms))
+        return best.as_dict(), list(ms), outs
+
+    def close(self) -> None:
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().fdm_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

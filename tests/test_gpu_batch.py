@@ -1,0 +1,238 @@
+"""Launch shapes, streamed coupling banks and batched matvecs on the GPU,
+against the FP64 oracle (Alg. 4) on the same seeded inputs.
+
+Tolerances as for single plans: plain FP64 1e-12 relative l2, mixed FP32
+1e-6; complex64 outputs add their own rounding (2^-24 relative per entry).
+Resident-bank FP64 results do not depend on the launch shape at all (every
+target's sum over offsets runs in one order; offsets a smaller target
+block skips only add exact zeros), so they are compared bit for bit.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+from gpu_util import gpu_plan, rel, to_dev
+
+pytestmark = pytest.mark.gpu
+
+TOL_FP64 = 1e-12
+TOL_FP32 = 1e-6
+
+TUNES = [dict(nb=nb, persistent=p, lpt=l, p2p_in_queue=q)
+         for nb in (64, 32) for p in (1, 0) for l in (1, 0) for q in (0, 1)]
+
+
+_oracle_cache = {}
+
+
+def oracle_y(P):
+    key = (P.name, P.points_T.shape[0], P.points_S.shape[0], P.kappa, P.levels, P.m,
+           P.points_T[:1].tobytes(), P.v[:1].tobytes())
+    if key not in _oracle_cache:
+        _oracle_cache[key] = oracle.matvec(
+            oracle.build(P.points_T, P.points_S, P.kappa, P.box, P.levels, P.m), P.v)
+    return _oracle_cache[key]
+
+
+def plan_y(P, precision="fp64", bank_budget=0, tune=None):
+    import torch
+    import paper_2004_14229_amd as F
+    pt = to_dev(P.points_T)
+    ps = to_dev(P.points_S)
+    with F.Plan(pt, ps, P.kappa, P.box, P.levels, P.m, precision=precision,
+                bank_budget=bank_budget, tune=tune) as plan:
+        y = plan.matvec(to_dev(P.v))
+        torch.cuda.synchronize()
+        return y.cpu().numpy(), plan.stats()
+
+
+def small_batch(count=6, seed=41, m=5):
+    return W.batch_problems(seed=seed, count=count, m=m, n_lo=400, n_hi=2500)
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", TOL_FP64), ("fp32", TOL_FP32),
+                                           ("bf16x3", 2e-5)])
+def test_every_launch_shape_matches_oracle(precision, tol):
+    P = W.random_problem(301, 700, 650, 45.0, 4, 3)
+    yo = oracle_y(P)
+    ys = []
+    for t in TUNES:
+        y, _ = plan_y(P, precision, tune=t)
+        assert rel(y, yo) <= tol, t
+        ys.append(y)
+    if precision == "fp64":
+        for y, t in zip(ys[1:], TUNES[1:]):
+            assert np.array_equal(y, ys[0]), t
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", TOL_FP64), ("fp32", TOL_FP32)])
+def test_streamed_bank_matches_oracle(precision, tol):
+    """Bank generated during the matvec, a few matrices at a time, so that
+    items are split over many launches (first part stored, later parts
+    added)."""
+    P = W.random_problem(302, 900, 800, 40.0, 4, 3)
+    yo = oracle_y(P)
+    y_res, st = plan_y(P, precision)
+    K = (P.m + 1) ** 3
+    Kp = (K + 31) // 32 * 32
+    mat = Kp * Kp * (16 if precision == "fp64" else 8)
+    n = st["n_bank_matrices"]
+    assert n > 20
+    for budget in (mat, 7 * mat, (n // 3) * mat):
+        for t in (TUNES[0], TUNES[-1]):
+            y, st2 = plan_y(P, precision, bank_budget=budget, tune=t)
+            assert rel(y, yo) <= tol, (budget, t)
+            assert st2["n_couplings"] == st["n_couplings"]
+    assert rel(y_res, yo) <= tol
+
+
+def test_streamed_bank_uniform2k_fp32():
+    P = W.config("uniform2k")
+    yo = oracle_y(P)
+    y, st = plan_y(P, "fp32", bank_budget=50 * 128 * 128 * 8)
+    assert rel(y, yo) <= TOL_FP32
+
+
+def _batch_vectors(probs, c64):
+    import torch
+    dt = np.complex64 if c64 else np.complex128
+    return [torch.from_numpy(P.v.astype(dt)).cuda() for P in probs]
+
+
+def _batch_check(probs, ys, tol, c64):
+    for P, y in zip(probs, ys):
+        yo = oracle_y(P)
+        yy = y.cpu().numpy().astype(np.complex128)
+        assert rel(yy, yo) <= tol + (1e-7 if c64 else 0.0), P.name
+
+
+@pytest.mark.parametrize("precision,tol,c64,budget", [
+    ("fp64", TOL_FP64, False, 0), ("fp32", TOL_FP32, True, 0),
+    ("fp32", TOL_FP32, True, 1), ("fp64", TOL_FP64, False, 1)])
+def test_batch_matches_oracle(precision, tol, c64, budget):
+    """Small batch of uneven uniform and clustered problems (the batched
+    workload's generator at small N); budget 1: streamed banks, generated
+    into the batch's workspace (a third of their total) over several
+    launches."""
+    import torch
+    import paper_2004_14229_amd as F
+    probs = small_batch()
+    K = (probs[0].m + 1) ** 3
+    Kp = (K + 31) // 32 * 32
+    mat = Kp * Kp * (16 if precision == "fp64" else 8)
+    plans = [gpu_plan(P, precision) if not budget else
+             F.Plan(to_dev(P.points_T), to_dev(P.points_S), P.kappa, P.box, P.levels, P.m,
+                    precision=precision, bank_budget=mat)
+             for P in probs]
+    ws = 0
+    if budget:
+        total = sum(p.stats()["n_bank_matrices"] for p in plans)
+        ws = max(1, total // 3) * mat
+    with F.Batch(plans, workspace_bytes=ws) as b:
+        ys = b.matvec(_batch_vectors(probs, c64))
+        torch.cuda.synchronize()
+        _batch_check(probs, ys, tol, c64)
+    for p in plans:
+        p.close()
+
+
+def test_batch_graph_replays_match_eager():
+    """The batched matvec captured in a HIP graph and replayed several
+    times, with eager work and synchronisations between replays; every
+    replay equals the eager (uncaptured) result bit for bit."""
+    import torch
+    import paper_2004_14229_amd as F
+    probs = small_batch(count=5, seed=43)
+    plans = [gpu_plan(P, "fp32") for P in probs]
+    s = torch.cuda.Stream()
+    with F.Batch(plans) as b:
+        vs = _batch_vectors(probs, True)
+        torch.cuda.synchronize()
+        b.set_graph(False)
+        with torch.cuda.stream(s):
+            eager = [y.clone() for y in b.matvec(vs, stream=s)]
+        s.synchronize()
+        b.set_graph(True)
+        outs = [torch.empty_like(y) for y in eager]
+        for r in range(4):
+            with torch.cuda.stream(s):
+                for y in outs:
+                    y.fill_(float("nan"))
+                b.matvec(vs, outs, stream=s)
+            s.synchronize()
+            extra = torch.randn(1000, device="cuda").sum()  # eager work between replays
+            torch.cuda.synchronize()
+            assert torch.isfinite(extra)
+            for y, e in zip(outs, eager):
+                assert torch.equal(y, e), r
+        _batch_check(probs, outs, TOL_FP32, True)
+    for p in plans:
+        p.close()
+
+
+def test_batch_with_empty_problems():
+    import torch
+    import paper_2004_14229_amd as F
+    probs = small_batch(count=3, seed=44)
+    probs.append(W.random_problem(45, 50, 0, 10.0, 3, 5))
+    probs.append(W.random_problem(46, 0, 40, 10.0, 3, 5))
+    plans = [gpu_plan(P, "fp64") for P in probs]
+    with F.Batch(plans) as b:
+        ys = b.matvec(_batch_vectors(probs, False))
+        torch.cuda.synchronize()
+        for P, y in zip(probs[:3], ys[:3]):
+            assert rel(y.cpu().numpy(), oracle_y(P)) <= TOL_FP64
+        assert ys[3].shape == (50,) and torch.all(ys[3] == 0)
+        assert ys[4].shape == (0,)
+    for p in plans:
+        p.close()
+
+
+def test_plan_in_batch_cannot_be_destroyed_or_retuned():
+    import paper_2004_14229_amd as F
+    probs = small_batch(count=2, seed=47)
+    plans = [gpu_plan(P, "fp64") for P in probs]
+    b = F.Batch(plans)
+    with pytest.raises(F.FdmError):
+        plans[0].set_tune({"nb": 32})
+    with pytest.raises(F.FdmError):
+        plans[0].close()
+    b.close()
+    plans[0].set_tune({"nb": 32})
+    for p in plans:
+        p.close()
+
+
+def test_autotune_plan_and_batch():
+    """The autotuner times every candidate, keeps the fastest, and the
+    tuned plan / batch still matches the oracle."""
+    import torch
+    import paper_2004_14229_amd as F
+    P = W.random_problem(303, 800, 760, 35.0, 4, 3)
+    yo = oracle_y(P)
+    plan = gpu_plan(P, "fp32")
+    best, ms, y = plan.autotune(to_dev(P.v))
+    torch.cuda.synchronize()
+    assert len(ms) == 8 and all(t > 0 for t in ms)
+    assert best == plan.get_tune()
+    assert rel(y.cpu().numpy(), yo) <= TOL_FP32
+    y2 = plan.matvec(to_dev(P.v))
+    torch.cuda.synchronize()
+    assert rel(y2.cpu().numpy(), yo) <= TOL_FP32
+    plan.close()
+
+    probs = small_batch(count=4, seed=48)
+    plans = [gpu_plan(Q, "fp32") for Q in probs]
+    with F.Batch(plans) as b:
+        vs = _batch_vectors(probs, True)
+        best, ms, ys = b.autotune(vs)
+        torch.cuda.synchronize()
+        assert len(ms) == 4 and all(t > 0 for t in ms)
+        assert best == b.get_tune() and best["persistent"] == 1
+        _batch_check(probs, ys, TOL_FP32, True)
+        ys = b.matvec(vs)
+        torch.cuda.synchronize()
+        _batch_check(probs, ys, TOL_FP32, True)
+    for p in plans:
+        p.close()
