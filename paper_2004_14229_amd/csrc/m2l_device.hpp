@@ -131,8 +131,18 @@ __device__ __forceinline__ void source_columns(TargetTile<NB>& S, int buf, const
   }
 }
 
+// Offset list entries are the same for the whole workgroup and read-only
+// during the launch: reading them through the constant address space gives
+// scalar loads (served by the scalar cache), as for kernel arguments.
+template <class T>
+__device__ __forceinline__ const __attribute__((address_space(4))) T* cmem(const T* p) {
+  return (const __attribute__((address_space(4))) T*)p;
+}
+
 __device__ __forceinline__ int4 offset_of(const M2LDesc& D, int32_t vo) {
-  return D.offtab[gmem(D.valid_off)[vo]];
+  const int32_t b = *cmem(D.valid_off + vo);
+  const int32_t* o = reinterpret_cast<const int32_t*>(D.offtab) + 4 * int64_t(b);
+  return make_int4(*cmem(o), *cmem(o + 1), *cmem(o + 2), *cmem(o + 3));
 }
 
 // Precision traits of the coupling kernel.  Each wave owns 32 rows of the
@@ -227,6 +237,7 @@ __device__ __forceinline__ void slab_mfma(d4v (&ar)[NB / 8], d4v (&ai)[NB / 8],
       a_r[t][rs] = gmem(Ar)[ka];
       a_i[t][rs] = gmem(Ai)[ka];
     }
+  __builtin_amdgcn_sched_barrier(0);  // loads first: their latency overlaps the MFMAs
 #pragma unroll
   for (int t = 0; t < 2; ++t) {
     const int kk = 4 * t;
@@ -270,8 +281,6 @@ __device__ __forceinline__ void flush_rows64(const d4v (&tr)[NB / 8], const d4v 
           v.y += o.y;
         }
         gstore16(dst + r, v);
-        // one element at a time: hoisted loads would hold the whole tile
-        __builtin_amdgcn_sched_barrier(0);
       }
   }
 }
@@ -358,8 +367,6 @@ __device__ __forceinline__ void flush_rows32(const f16v (&tr)[NB / 32], const f1
         v.y += o.y;
       }
       gstore16(dst + r, v);
-      // one element at a time: hoisted loads would hold the whole tile
-      __builtin_amdgcn_sched_barrier(0);
     }
   }
 }
@@ -453,6 +460,9 @@ __device__ __forceinline__ void item_f32(F32Shared<NB>& sh, const M2LItem& it,
       }
       float a[2][8];
       load_a32(a, bank + od_cur.w * 2 * per, per, s * Tr::KS, Kp, wave, lane);
+      // issue all of the slab's coupling-matrix loads before its MFMAs, so
+      // that their latency overlaps the first products
+      __builtin_amdgcn_sched_barrier(0);
       mfma32<NB>(acr, aci, a, sh, cur, lane);
       if (s == ns - 1) {
 #pragma unroll
@@ -528,9 +538,9 @@ __device__ __forceinline__ bf8v neg_bf8(bf8v x) {
 }
 
 // One k slab (one MFMA k step) for one wave: A operands from the bank in
-// fragment order, B operands from LDS.  Two passes keep few operands live:
-// first the A lo parts against the B hi parts, then the A hi parts against
-// both B parts.
+// fragment order, B operands from LDS.  Two passes keep few B operands
+// live: first the A lo parts against the B hi parts, then the A hi parts
+// against both B parts.
 template <int NB>
 __device__ __forceinline__ void mfma_bf16x3(f16v (&ar)[NB / 32], f16v (&ai)[NB / 32],
                                             const uint16_t* __restrict__ A, int64_t per,
@@ -538,9 +548,13 @@ __device__ __forceinline__ void mfma_bf16x3(f16v (&ar)[NB / 32], f16v (&ai)[NB /
                                             int wave, int lane) {
   const int64_t f = ((int64_t(s) * (Kp / 32) + wave) * 64 + lane) * 8;
   const int kq = 8 * (lane / 32);
+  // all four A loads first: their latency overlaps the lo-part products
+  const bf8v arl = as_bf8(gload16<u4v>(A + per + f));
+  const bf8v ail = as_bf8(gload16<u4v>(A + 3 * per + f));
+  const bf8v arh = as_bf8(gload16<u4v>(A + f));
+  const bf8v aih = as_bf8(gload16<u4v>(A + 2 * per + f));
+  __builtin_amdgcn_sched_barrier(0);
   {
-    const bf8v arl = as_bf8(gload16<u4v>(A + per + f));
-    const bf8v ail = as_bf8(gload16<u4v>(A + 3 * per + f));
 #pragma unroll
     for (int cs = 0; cs < NB / 32; ++cs) {
       const int col = 32 * cs + lane % 32;
@@ -553,8 +567,6 @@ __device__ __forceinline__ void mfma_bf16x3(f16v (&ar)[NB / 32], f16v (&ai)[NB /
       __builtin_amdgcn_sched_barrier(0);
     }
   }
-  const bf8v arh = as_bf8(gload16<u4v>(A + f));
-  const bf8v aih = as_bf8(gload16<u4v>(A + 2 * per + f));
 #pragma unroll
   for (int cs = 0; cs < NB / 32; ++cs) {
     const int col = 32 * cs + lane % 32;

@@ -190,7 +190,7 @@ std::vector<M2LLaunch> build_schedule(const std::vector<Plan*>& plans, const Tun
 void run_schedule(std::vector<M2LLaunch>& sched, int32_t* heads, int prec, const Interp& ip,
                   const TuneConfig& cfg, hipStream_t s) {
   if (sched.empty()) return;
-  launch_fill_i32(heads, static_cast<int64_t>(sched.size()), 0, s);
+  if (cfg.persistent) launch_fill_i32(heads, static_cast<int64_t>(sched.size()), 0, s);
   for (size_t i = 0; i < sched.size(); ++i) {
     const M2LLaunch& L = sched[i];
     if (L.n_gen) launch_bank_matrices(L, prec, ip, s);
