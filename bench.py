@@ -39,6 +39,8 @@ def parse():
                     help="timed steps of the plain FP64 plan (0 = skip)")
     ap.add_argument("--bf16-steps", type=int, default=1,
                     help="timed steps of the BF16 split (bf16x3) plan (0 = skip)")
+    ap.add_argument("--batch-steps", type=int, default=2,
+                    help="timed batched matvecs of the 64-problem workload (0 = skip)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-groups", type=int, default=10)
     return ap.parse_args()
@@ -66,6 +68,18 @@ def time_plan(plan, v, y, steps, warmup):
     return wall, phases
 
 
+def kernel_source_sha(kernel: str) -> str:
+    """SHA-256 of the sources that define a coupling kernel (shared device
+    code + its precision's file)."""
+    csrc = os.path.join(ROOT, "paper_2004_14229_amd", "csrc")
+    part = {"k_m2l_f32": "m2l_f32.hip", "k_m2l_f64": "m2l_f64.hip",
+            "k_m2l_bf16x3": "m2l_bf16.hip"}[kernel]
+    h = hashlib.sha256()
+    for f in ("m2l_device.hpp", part):
+        h.update(open(os.path.join(csrc, f), "rb").read())
+    return h.hexdigest()
+
+
 def traffic_for(kernel: str, workload: str, launch_flops: float):
     """HBM bytes per launch from committed rocprofv3 counter summaries, if
     they were taken on the current kernel source."""
@@ -73,8 +87,7 @@ def traffic_for(kernel: str, workload: str, launch_flops: float):
     if not os.path.exists(path):
         return None
     rec = json.load(open(path))
-    src = open(os.path.join(ROOT, "paper_2004_14229_amd", "csrc", "m2l.hip"), "rb").read()
-    if rec.get("source_sha256") != hashlib.sha256(src).hexdigest():
+    if rec.get("source_sha256") != kernel_source_sha(kernel):
         return None
     return rec.get("hbm_bytes_per_launch")
 
@@ -137,6 +150,74 @@ def cpu_baseline(P, stats, groups: int, seed: int = 7):
                        f"{sample_s:.1f} s; scaled to N_SC={stats['n_stored_couplings']} "
                        f"matrices + N_C={stats['n_couplings']} blocks = {t_full:.0f} s "
                        f"per matvec (S2M/M2M/L2L/L2T/near field not counted)")}
+
+
+def batched(steps: int) -> dict:
+    """The batched workload: 64 independent problems (N log-uniform in
+    [1e4, 2e5], kappa uniform in [10, 80], half uniform, half clustered, m=5,
+    complex64 v) in one batch: mixed FP32 coupling, banks generated into the
+    batch's workspace during each matvec, coupling and near-field work of all
+    problems from one device queue, the whole batched matvec replayed as a
+    HIP graph, launch shape picked by the autotuner."""
+    import torch
+    import paper_2004_14229_amd as F
+    import workloads as W
+    probs = W.batch_problems()
+    t0 = time.perf_counter()
+    plans = []
+    for Q in probs:
+        qt = torch.from_numpy(Q.points_T).cuda()
+        qs = torch.from_numpy(Q.points_S).cuda()
+        plans.append(F.Plan(qt, qs, Q.kappa, Q.box, Q.levels, Q.m, precision="fp32",
+                            bank_budget=1 << 30))
+        del qt, qs
+    b = F.Batch(plans)
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t0
+    vs = [torch.from_numpy(Q.v.astype(np.complex64)).cuda() for Q in probs]
+    torch.cuda.synchronize()
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        best, tune_ms, ys = b.autotune(vs, max_candidates=4, stream=stream)
+        b.matvec(vs, ys, stream=stream)  # graph capture + first replay
+    stream.synchronize()
+    t1 = time.perf_counter()
+    with torch.cuda.stream(stream):
+        for _ in range(steps):
+            b.matvec(vs, ys, stream=stream)
+    stream.synchronize()
+    wall = (time.perf_counter() - t1) / steps
+    K = (probs[0].m + 1) ** 3
+    stats = [p.stats() for p in plans]
+    flops = sum(8.0 * K * K * st["n_couplings"] for st in stats)
+    res = {"workload": ("64 problems, N log-uniform in [1e4, 2e5] (sum %d), kappa U[10,80], "
+                        "32 uniform + 32 clustered (8 blobs, sigma 0.05), 4-5 levels, m=5, "
+                        "complex64 v and y" % sum(Q.points_T.shape[0] for Q in probs)),
+           "value": 1.0 / wall, "unit": "batches/s", "problem_matvecs_per_s": 64.0 / wall,
+           "ms_per_batch": 1000.0 * wall, "steps": steps, "setup_s": setup_s,
+           "precision": "FP32 coupling, banks generated per matvec into the batch workspace",
+           "tune": best, "autotune_m2l_ms": tune_ms,
+           "m2l_flops": flops, "tflops_whole_batch": flops / wall / 1e12}
+    golden = os.path.join(ROOT, "tests", "golden", "batch_rows.npz")
+    if os.path.exists(golden):
+        g = np.load(golden)
+        errs, num, den = {}, 0.0, 0.0
+        for key in g.files:
+            if not key.startswith("rows"):
+                continue
+            i = int(key[4:])
+            yy = ys[i].cpu().numpy().astype(np.complex128)[g[key]]
+            yo = g[f"y{i}"]
+            errs[str(i)] = float(np.linalg.norm(yy - yo) / np.linalg.norm(yo))
+            num += float(np.linalg.norm(yy - yo) ** 2)
+            den += float(np.linalg.norm(yo) ** 2)
+        res["rel_l2_err_vs_oracle"] = errs
+        res["rel_l2_err_vs_oracle_pooled"] = (num / den) ** 0.5
+    b.close()
+    for p in plans:
+        p.close()
+    print(f"[bench] batched: {1000.0 * wall:.1f} ms per batch of 64", file=sys.stderr, flush=True)
+    return res
 
 
 def main():
@@ -246,6 +327,11 @@ def main():
                     np.linalg.norm(g["y_bf16x3"] - yo) / np.linalg.norm(yo))
         print(f"[bench] bf16x3: {bms:.1f} ms/matvec, M2L {bm2l:.1f} ms", file=sys.stderr,
               flush=True)
+
+    if args.batch_steps > 0:
+        del pt, ps, v, y
+        torch.cuda.empty_cache()
+        out["batched"] = batched(args.batch_steps)
 
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(P, stats, args.cpu_groups)

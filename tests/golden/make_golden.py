@@ -8,6 +8,11 @@ emulated in the BF16 split precision (``oracle.emulate``), which fixes the
 expected error of that precision.  Run from the repository root:
 
     python tests/golden/make_golden.py uniform100k uniform1m
+    python tests/golden/make_golden.py batch
+
+``batch``: the batched workload (64 problems of ``workloads.batch_problems``),
+oracle rows of four of its problems (two uniform, two clustered), saved as
+``batch_rows.npz`` with ``rows<i>`` and ``y<i>`` for problem i.
 """
 import os
 import sys
@@ -22,6 +27,8 @@ import oracle  # noqa: E402
 import workloads as W  # noqa: E402
 
 SAMPLES = {"uniform100k": 64, "uniform1m": 32, "uniform4m": 8}
+BATCH_GOLDEN = (2, 4, 35, 46)  # problem indices in workloads.batch_problems()
+BATCH_ROWS = 16
 
 
 def sample(name: str, R: int) -> np.ndarray:
@@ -29,7 +36,28 @@ def sample(name: str, R: int) -> np.ndarray:
     return np.sort(np.random.default_rng(12345).choice(P.points_T.shape[0], R, replace=False))
 
 
+def batch() -> None:
+    probs = W.batch_problems()
+    out = {}
+    for i in BATCH_GOLDEN:
+        P = probs[i]
+        rows = np.sort(np.random.default_rng(1000 + i).choice(P.points_T.shape[0], BATCH_ROWS,
+                                                              replace=False))
+        t = time.time()
+        plan = oracle.build(P.points_T, P.points_S, P.kappa, P.box, P.levels, P.m, rows=rows)
+        out[f"rows{i}"] = rows
+        out[f"y{i}"] = oracle.matvec(plan, P.v)
+        print(f"batch problem {i}: N={P.points_T.shape[0]} {len(rows)} rows in "
+              f"{time.time() - t:.1f} s", flush=True)
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "batch_rows.npz")
+    np.savez(path, **out)
+    print(f"-> {path}")
+
+
 def main(names):
+    if "batch" in names:
+        batch()
+        names = [n for n in names if n != "batch"]
     for name in names:
         P = W.config(name)
         rows = sample(name, SAMPLES[name])

@@ -5,7 +5,9 @@ by tests/golden/make_golden.py from the oracle alone).
 Tolerances: plain FP64 1e-12 relative l2 over the sampled rows; mixed FP32
 1e-6 (the stated bound of the mixed path); the FP32 result also against the
 plain GPU result on the full vector; BF16 split products within 3x the
-error of the oracle's emulation of that arithmetic on the same rows.
+error of the oracle's emulation of that arithmetic on the same rows.  The
+batched workload (64 problems, complex64 in and out, mixed FP32): 1e-6 plus
+the complex64 rounding of y (1e-7) on the stored rows of four problems.
 """
 import os
 
@@ -66,3 +68,39 @@ def test_bf16x3_sampled_rows(name):
     _cache.pop((name, "bf16x3"), None)
     assert np.all(np.isfinite(y))
     assert rel(y[rows], yo) <= 3 * rel(ye, yo)
+
+
+def test_batched_workload_sampled_rows():
+    """The 64-problem batched workload as the benchmark runs it: mixed FP32,
+    banks generated into the batch workspace, one device queue, graph
+    replay on a side stream."""
+    import torch
+    import paper_2004_14229_amd as F
+    g = np.load(os.path.join(GOLDEN, "batch_rows.npz"))
+    probs = W.batch_problems()
+    plans = [F.Plan(to_dev(Q.points_T), to_dev(Q.points_S), Q.kappa, Q.box, Q.levels, Q.m,
+                    precision="fp32", bank_budget=1 << 30) for Q in probs]
+    try:
+        with F.Batch(plans) as b:
+            vs = [torch.from_numpy(Q.v.astype(np.complex64)).cuda() for Q in probs]
+            torch.cuda.synchronize()
+            s = torch.cuda.Stream()
+            with torch.cuda.stream(s):
+                ys = b.matvec(vs, stream=s)
+                ys2 = b.matvec(vs, [torch.empty_like(y) for y in ys], stream=s)
+            s.synchronize()
+            checked = 0
+            for key in g.files:
+                if not key.startswith("rows"):
+                    continue
+                i = int(key[4:])
+                for out in (ys, ys2):
+                    yy = out[i].cpu().numpy().astype(np.complex128)[g[key]]
+                    assert rel(yy, g[f"y{i}"]) <= 1e-6 + 1e-7, i
+                checked += 1
+            assert checked == 4
+            for y in ys:
+                assert torch.isfinite(torch.view_as_real(y)).all()
+    finally:
+        for p in plans:
+            p.close()
