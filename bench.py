@@ -42,6 +42,8 @@ def parse():
     ap.add_argument("--batch-steps", type=int, default=2,
                     help="timed batched matvecs of the 64-problem workload (0 = skip)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only copy 1 GiB device to device (calibrates HBM byte counters)")
     ap.add_argument("--cpu-groups", type=int, default=10)
     return ap.parse_args()
 
@@ -229,6 +231,15 @@ def main():
     import torch
     import paper_2004_14229_amd as F
     import workloads as W
+
+    if args.copy_probe:
+        a = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes": a.numel() * 4}))
+        return
 
     P = W.config(args.workload)
     dev = torch.device("cuda:0")
