@@ -41,6 +41,9 @@ def parse():
                     help="timed steps of the BF16 split (bf16x3) plan (0 = skip)")
     ap.add_argument("--batch-steps", type=int, default=2,
                     help="timed batched matvecs of the 64-problem workload (0 = skip)")
+    ap.add_argument("--bank-budget-gb", type=float, default=0.0,
+                    help="> 0: generate the coupling bank during each matvec into a "
+                         "workspace of this many GB (for banks that do not fit)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only copy 1 GiB device to device (calibrates HBM byte counters)")
@@ -54,16 +57,26 @@ def describe(P) -> str:
             f"(K={(P.m + 1) ** 3}), complex128 v with N(0,1) parts")
 
 
-def time_plan(plan, v, y, steps, warmup):
+def time_plan(plan, v, y, steps, warmup, tag=""):
+    """Warmup and timed matvecs; the launch schedule (and a streamed bank's
+    workspace) is built before.  Matvecs with several coupling launches
+    report each launch as it completes."""
     import torch
     plan.set_timing(True)
+    plan.prepare()
+    n_launch = plan.coupling_launches()
     for _ in range(warmup):
         plan.matvec(v, out=y)
     torch.cuda.synchronize()
     phases = []
     t0 = time.perf_counter()
-    for _ in range(steps):
+    for k in range(steps):
         plan.matvec(v, out=y)
+        if n_launch > 1:
+            for i in range(n_launch):
+                ms = plan.wait_launch(i)
+                print(f"[bench] {tag} step {k + 1}/{steps}: coupling launch {i + 1}/{n_launch} "
+                      f"done at {ms / 1000:.1f} s", file=sys.stderr, flush=True)
         phases.append(plan.phase_ms())  # waits for this step's events
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
@@ -249,13 +262,15 @@ def main():
     y = torch.empty(P.points_T.shape[0], dtype=torch.complex128, device=dev)
 
     t0 = time.perf_counter()
-    plan = F.Plan(pt, ps, P.kappa, P.box, P.levels, P.m, precision=args.precision)
+    budget = int(args.bank_budget_gb * 1e9)
+    plan = F.Plan(pt, ps, P.kappa, P.box, P.levels, P.m, precision=args.precision,
+                  bank_budget=budget)
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t0
     stats = plan.stats()
     print(f"[bench] {args.precision} plan built in {setup_s:.1f} s: N_C={stats['n_couplings']} "
           f"N_SC={stats['n_stored_couplings']}", file=sys.stderr, flush=True)
-    wall, phases = time_plan(plan, v, y, args.steps, args.warmup)
+    wall, phases = time_plan(plan, v, y, args.steps, args.warmup, args.precision)
     y_mixed = y.cpu().numpy()
     plan.close()
     del plan
@@ -289,6 +304,8 @@ def main():
     out["setup_s"] = setup_s
     out["plan"] = {k: stats[k] for k in ("n_couplings", "n_stored_couplings", "m2l_columns",
                                          "near_entries", "device_bytes", "l_hf", "l_min")}
+    out["plan"]["bank"] = (f"generated per matvec into a {args.bank_budget_gb:g} GB workspace"
+                           if budget else "resident")
 
     golden = os.path.join(ROOT, "tests", "golden", f"{args.workload}_rows.npz")
     if os.path.exists(golden):
@@ -297,9 +314,11 @@ def main():
         out["rel_l2_err_vs_oracle"] = float(np.linalg.norm(y_mixed[rows] - yo) / np.linalg.norm(yo))
         out["oracle_rows"] = int(rows.shape[0])
 
+    y_plain = None
     if args.plain_steps > 0 and args.precision != "fp64":
-        plain = F.Plan(pt, ps, P.kappa, P.box, P.levels, P.m, precision="fp64")
-        pwall, pph = time_plan(plain, v, y, args.plain_steps, 1)
+        plain = F.Plan(pt, ps, P.kappa, P.box, P.levels, P.m, precision="fp64",
+                       bank_budget=budget)
+        pwall, pph = time_plan(plain, v, y, args.plain_steps, min(args.warmup, 1), "fp64")
         y_plain = y.cpu().numpy()
         plain.close()
         del plain
@@ -316,8 +335,9 @@ def main():
         print(f"[bench] fp64 plain: {pms:.1f} ms/matvec", file=sys.stderr, flush=True)
 
     if args.bf16_steps > 0 and args.precision != "bf16x3":
-        bf = F.Plan(pt, ps, P.kappa, P.box, P.levels, P.m, precision="bf16x3")
-        bwall, bph = time_plan(bf, v, y, args.bf16_steps, 1)
+        bf = F.Plan(pt, ps, P.kappa, P.box, P.levels, P.m, precision="bf16x3",
+                    bank_budget=budget)
+        bwall, bph = time_plan(bf, v, y, args.bf16_steps, min(args.warmup, 1), "bf16x3")
         y_bf = y.cpu().numpy()
         bf.close()
         del bf
@@ -336,6 +356,9 @@ def main():
             if "y_bf16x3" in g.files:
                 out["bf16x3"]["emulated_rel_l2_err"] = float(
                     np.linalg.norm(g["y_bf16x3"] - yo) / np.linalg.norm(yo))
+        if y_plain is not None:
+            out["bf16x3"]["rel_l2_err_vs_plain_gpu"] = float(
+                np.linalg.norm(y_bf - y_plain) / np.linalg.norm(y_plain))
         print(f"[bench] bf16x3: {bms:.1f} ms/matvec, M2L {bm2l:.1f} ms", file=sys.stderr,
               flush=True)
 

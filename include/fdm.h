@@ -196,6 +196,22 @@ int fdm_plan_matvec_c64(fdm_plan* plan, const void* v, void* y, void* stream);
 int fdm_plan_set_timing(fdm_plan* plan, int enable);
 int fdm_plan_phase_ms(const fdm_plan* plan, double ms[7]);
 
+/*
+ * fdm_plan_prepare -- build now what the plan's first matvec would build:
+ * its coupling launch schedule and, for a streamed bank, the workspace
+ * (synchronises stream).  Matvecs after it allocate nothing.
+ */
+int fdm_plan_prepare(fdm_plan* plan, void* stream);
+
+/*
+ * Progress of a long matvec: the number of coupling launches of the plan's
+ * schedule (FDM_ERR_STATE before fdm_plan_prepare or the first matvec), and,
+ * with timing on, a wait for launch i (0-based) of the last timed matvec,
+ * returning the milliseconds from the matvec's start to that launch's end.
+ */
+int fdm_plan_coupling_launches(const fdm_plan* plan, int* n);
+int fdm_plan_wait_launch(const fdm_plan* plan, int i, double* ms);
+
 /* Free a plan and all its device memory.  NULL is accepted. */
 int fdm_plan_destroy(fdm_plan* plan);
 

@@ -188,14 +188,23 @@ std::vector<M2LLaunch> build_schedule(const std::vector<Plan*>& plans, const Tun
 }
 
 void run_schedule(std::vector<M2LLaunch>& sched, int32_t* heads, int prec, const Interp& ip,
-                  const TuneConfig& cfg, hipStream_t s) {
+                  const TuneConfig& cfg, hipStream_t s, hipEvent_t* done) {
   if (sched.empty()) return;
   if (cfg.persistent) launch_fill_i32(heads, static_cast<int64_t>(sched.size()), 0, s);
   for (size_t i = 0; i < sched.size(); ++i) {
     const M2LLaunch& L = sched[i];
     if (L.n_gen) launch_bank_matrices(L, prec, ip, s);
     launch_m2l_items(L, prec, ip.Kp, cfg, heads + i, s);
+    if (done) FDM_HIP(hipEventRecord(done[i], s));
   }
+}
+
+void plan_launch_events(Plan& P) {
+  for (hipEvent_t e : P.launch_ev) (void)hipEventDestroy(e);
+  P.launch_ev.clear();
+  if (!P.timing) return;
+  P.launch_ev.resize(P.sched.size(), nullptr);
+  for (auto& e : P.launch_ev) FDM_HIP(hipEventCreate(&e));
 }
 
 void build_plan_schedule(Plan& P, hipStream_t s) {
@@ -210,6 +219,7 @@ void build_plan_schedule(Plan& P, hipStream_t s) {
   P.sched = build_schedule({&P}, P.tune, ws, ws_mats, s);
   P.heads.alloc(std::max<size_t>(P.sched.size(), 1), &P.tally);
   P.sched_ready = true;
+  plan_launch_events(P);
 }
 
 void launch_bank(Plan& P, hipStream_t s) {

@@ -187,7 +187,8 @@ void plan_matvec(Plan& P, const void* v_user, void* y_user, bool c64, hipStream_
   if (P.l_min <= p)
     for (int l = p - 1; l >= P.l_min; --l) launch_m2m(P, l, s);
   mark(2);
-  run_schedule(P.sched, P.heads.get(), P.prec, P.ip, P.tune, s);  // multiplication phase
+  run_schedule(P.sched, P.heads.get(), P.prec, P.ip, P.tune, s,   // multiplication phase
+               P.timing && P.launch_ev.size() == P.sched.size() ? P.launch_ev.data() : nullptr);
   mark(3);
   if (!P.tune.p2p_in_queue || !p2p_queue_supported(P.prec, P.ip.Kp)) launch_p2p(P, s);           // near field (stored)
   mark(4);
@@ -395,6 +396,37 @@ int fdm_plan_set_timing(fdm_plan* plan, int enable) {
     }
     P.timing = enable != 0;
     P.timed_run = false;
+    if (P.sched_ready) plan_launch_events(P);
+  });
+}
+
+int fdm_plan_prepare(fdm_plan* plan, void* stream) {
+  return guarded([&] {
+    if (!plan) fail(FDM_ERR_INVALID_ARG, "plan is NULL");
+    Plan& P = plan->p;
+    if (!P.sched_ready) build_plan_schedule(P, static_cast<hipStream_t>(stream));
+  });
+}
+
+int fdm_plan_coupling_launches(const fdm_plan* plan, int* n) {
+  return guarded([&] {
+    if (!plan || !n) fail(FDM_ERR_INVALID_ARG, "NULL argument");
+    if (!plan->p.sched_ready) fail(FDM_ERR_STATE, "the plan has no launch schedule yet");
+    *n = static_cast<int>(plan->p.sched.size());
+  });
+}
+
+int fdm_plan_wait_launch(const fdm_plan* plan, int i, double* ms) {
+  return guarded([&] {
+    if (!plan || !ms) fail(FDM_ERR_INVALID_ARG, "NULL argument");
+    const Plan& P = plan->p;
+    if (!P.timing || !P.timed_run) fail(FDM_ERR_STATE, "no timed matvec");
+    if (i < 0 || i >= static_cast<int>(P.launch_ev.size()))
+      fail(FDM_ERR_INVALID_ARG, "launch index out of range");
+    FDM_HIP(hipEventSynchronize(P.launch_ev[i]));
+    float t = 0;
+    FDM_HIP(hipEventElapsedTime(&t, P.ev[0], P.launch_ev[i]));
+    *ms = t;
   });
 }
 
@@ -424,6 +456,8 @@ int fdm_plan_destroy(fdm_plan* plan) {
     if (plan->p.batch_owner) fail(FDM_ERR_STATE, "the plan belongs to a batch");
     (void)hipDeviceSynchronize();
     for (auto& e : plan->p.ev)
+      if (e) (void)hipEventDestroy(e);
+    for (auto& e : plan->p.launch_ev)
       if (e) (void)hipEventDestroy(e);
     delete plan;
   });

@@ -183,6 +183,7 @@ struct Plan {
   // optional per-phase timing (events on the matvec stream)
   bool timing = false, timed_run = false;
   hipEvent_t ev[8] = {};
+  std::vector<hipEvent_t> launch_ev;  // one per coupling launch (timing on)
 
   // structure export (host copies made at build time)
   std::vector<std::vector<int64_t>> off_used;  // per level: x,y,z,count,dir
@@ -222,6 +223,8 @@ void build_m2l_work(Plan& P, hipStream_t s);  // base items for P.tune.nb
 int64_t bank_matrix_bytes(int prec, const Interp& ip);
 // Rebuild the plan's own launches (after a change of its tune config).
 void build_plan_schedule(Plan& P, hipStream_t s);
+// (Re)create the per-launch timing events of the plan's schedule.
+void plan_launch_events(Plan& P);
 // A bank range [b0, b1) of one plan in a coupling launch.
 struct SchedSource {
   Plan* P;
@@ -232,8 +235,9 @@ struct SchedSource {
 // banks packed into launches of at most ws_matrices generated matrices.
 std::vector<M2LLaunch> build_schedule(const std::vector<Plan*>& plans, const TuneConfig& cfg,
                                       void* ws, int64_t ws_matrices, hipStream_t s);
+// done: optional events recorded after each launch (one per launch).
 void run_schedule(std::vector<M2LLaunch>& sched, int32_t* heads, int prec, const Interp& ip,
-                  const TuneConfig& cfg, hipStream_t s);
+                  const TuneConfig& cfg, hipStream_t s, hipEvent_t* done = nullptr);
 
 // coupling kernels (m2l.hip)
 void launch_bank_matrices(const M2LLaunch& L, int prec, const Interp& ip, hipStream_t s);

@@ -89,6 +89,9 @@ def lib() -> ctypes.CDLL:
     L.fdm_dense_matvec.argtypes = [vp, i64, vp, i64, dbl, vp, vp, vp]
     L.fdm_plan_set_timing.argtypes = [vp, ci]
     L.fdm_plan_phase_ms.argtypes = [vp, ctypes.POINTER(dbl)]
+    L.fdm_plan_prepare.argtypes = [vp, vp]
+    L.fdm_plan_coupling_launches.argtypes = [vp, ctypes.POINTER(ci)]
+    L.fdm_plan_wait_launch.argtypes = [vp, ci, ctypes.POINTER(dbl)]
     L.fdm_build_tree_opts.argtypes = [vp, i64, vp, i64, dbl, ctypes.POINTER(dbl), ci, ci,
                                       ctypes.POINTER(Options), vp, ctypes.POINTER(vp)]
     L.fdm_plan_get_tune.argtypes = [vp, ctypes.POINTER(Tune)]
@@ -109,6 +112,7 @@ def lib() -> ctypes.CDLL:
               "fdm_plan_matvec_c64", "fdm_plan_destroy", "fdm_plan_stats",
               "fdm_plan_export", "fdm_dense_matvec", "fdm_plan_set_timing",
               "fdm_plan_phase_ms", "fdm_plan_get_tune", "fdm_plan_set_tune",
+              "fdm_plan_prepare", "fdm_plan_coupling_launches", "fdm_plan_wait_launch",
               "fdm_plan_autotune", "fdm_batch_create", "fdm_batch_matvec",
               "fdm_batch_set_graph", "fdm_batch_get_tune", "fdm_batch_set_tune",
               "fdm_batch_autotune", "fdm_batch_destroy"):
@@ -219,6 +223,21 @@ class Plan:
                                        int(v.dtype == torch.complex64), int(max_candidates),
                                        _stream_handle(stream), ctypes.byref(best), ms))
         return best.as_dict(), list(ms), out
+
+    def prepare(self, stream=None) -> None:
+        """Build the launch schedule (and streamed-bank workspace) now."""
+        _check(lib().fdm_plan_prepare(self._h, _stream_handle(stream)))
+
+    def coupling_launches(self) -> int:
+        n = ctypes.c_int()
+        _check(lib().fdm_plan_coupling_launches(self._h, ctypes.byref(n)))
+        return n.value
+
+    def wait_launch(self, i: int) -> float:
+        """Wait for coupling launch i of the last timed matvec; ms since its start."""
+        ms = ctypes.c_double()
+        _check(lib().fdm_plan_wait_launch(self._h, int(i), ctypes.byref(ms)))
+        return ms.value
 
     PHASES = ("s2m", "m2m", "m2l", "l2l", "l2t", "near", "total")
 
