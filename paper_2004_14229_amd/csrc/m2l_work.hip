@@ -157,8 +157,21 @@ std::vector<M2LLaunch> build_schedule(const std::vector<Plan*>& plans, const Tun
     if (B.empty()) B.emplace_back();
     add_source(B[0], P, 0, P.n_bank, resident_bank(P), 0, emitted[p]);
   }
-  // streamed banks: packed into launches of at most ws_matrices matrices
+  // streamed banks: consecutive bank ids packed into launches of at most
+  // ws_matrices matrices, and of about equal work (blocks using the
+  // matrices): as few launches as the workspace allows, none much longer
+  // than the others (the leaf levels have few matrices but most blocks)
+  int64_t n_mats = 0;
+  double total_work = 0;
+  for (Plan* P : plans) {
+    if (P->base_items.empty() || P->bank_budget == 0) continue;
+    n_mats += P->n_bank;
+    for (int64_t w : P->bank_work) total_work += static_cast<double>(w);
+  }
+  const int64_t n_min = ws_matrices > 0 ? (n_mats + ws_matrices - 1) / ws_matrices : 0;
+  const double target = n_min > 0 ? total_work / static_cast<double>(n_min) : 0.0;
   int64_t left = 0;
+  double acc = 0;
   for (size_t p = 0; p < plans.size(); ++p) {
     Plan& P = *plans[p];
     if (P.base_items.empty() || P.bank_budget == 0) continue;
@@ -167,13 +180,25 @@ std::vector<M2LLaunch> build_schedule(const std::vector<Plan*>& plans, const Tun
       if (left == 0) {
         if (B.empty() || B.back().n_gen > 0 || !B.back().items.empty()) B.emplace_back();
         left = ws_matrices;
+        acc = 0;
       }
-      const int64_t take = std::min(left, P.n_bank - b);
+      int64_t e = b;
+      while (e < P.n_bank && e - b < left) {
+        const double w = static_cast<double>(P.bank_work[e]);
+        if (acc > 0 && acc + w > target) break;
+        acc += w;
+        ++e;
+      }
+      if (e == b) {  // this launch's work is full: next launch
+        left = 0;
+        continue;
+      }
       const int64_t slot0 = ws_matrices - left;
-      add_generation(B.back(), P, b, b + take);
-      add_source(B.back(), P, b, b + take, ws, slot0, emitted[p]);
-      left -= take;
-      b += take;
+      add_generation(B.back(), P, b, e);
+      add_source(B.back(), P, b, e, ws, slot0, emitted[p]);
+      left -= e - b;
+      if (e < P.n_bank) left = 0;  // full (matrices or work): next launch
+      b = e;
     }
   }
   if (cfg.p2p_in_queue && !plans.empty() &&
@@ -350,6 +375,7 @@ void build_m2l_work(Plan& P, hipStream_t s) {
                        d_descs.get(), P.tgt_list.get(), P.offtab.get(), 1, nullptr,
                        d_begin.get(), P.valid_off.get(), d_bpo.get(), s);
   std::vector<unsigned long long> bpo = to_host(d_bpo.get(), P.n_bank, s);
+  P.bank_work.assign(bpo.begin(), bpo.end());
   P.valid_off_h = to_host(P.valid_off.get(), total, s);
   for (int64_t i = 0; i < n_items; ++i) {
     items[i].vo_begin = begin[i];

@@ -154,6 +154,7 @@ struct Plan {
   DevBuf<uint16_t> bank16;
   DevBuf<uint8_t> bank_ws;
   std::vector<int32_t> bank_info;  // per bank id: level, ox, oy, oz, c
+  std::vector<int64_t> bank_work;  // per bank id: admissible blocks using it
 
   // coupling work (per plan; a batch builds its own launches from it)
   TuneConfig tune;
