@@ -44,6 +44,8 @@ def parse():
     ap.add_argument("--bank-budget-gb", type=float, default=0.0,
                     help="> 0: generate the coupling bank during each matvec into a "
                          "workspace of this many GB (for banks that do not fit)")
+    ap.add_argument("--compact", type=int, default=1, choices=[0, 1, 2],
+                    help="FP32 column compaction: 0 never, 1 sparse levels, 2 every level")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only copy 1 GiB device to device (calibrates HBM byte counters)")
@@ -167,7 +169,7 @@ def cpu_baseline(P, stats, groups: int, seed: int = 7):
                        f"per matvec (S2M/M2M/L2L/L2T/near field not counted)")}
 
 
-def batched(steps: int) -> dict:
+def batched(steps: int, compact: int = 1) -> dict:
     """The batched workload: 64 independent problems (N log-uniform in
     [1e4, 2e5], kappa uniform in [10, 80], half uniform, half clustered, m=5,
     complex64 v) in one batch: mixed FP32 coupling, banks generated into the
@@ -184,7 +186,7 @@ def batched(steps: int) -> dict:
         qt = torch.from_numpy(Q.points_T).cuda()
         qs = torch.from_numpy(Q.points_S).cuda()
         plans.append(F.Plan(qt, qs, Q.kappa, Q.box, Q.levels, Q.m, precision="fp32",
-                            bank_budget=1 << 30))
+                            bank_budget=1 << 30, tune={"compact": compact}))
         del qt, qs
     b = F.Batch(plans)
     torch.cuda.synchronize()
@@ -264,7 +266,7 @@ def main():
     t0 = time.perf_counter()
     budget = int(args.bank_budget_gb * 1e9)
     plan = F.Plan(pt, ps, P.kappa, P.box, P.levels, P.m, precision=args.precision,
-                  bank_budget=budget)
+                  bank_budget=budget, tune={"compact": args.compact})
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t0
     stats = plan.stats()
@@ -365,7 +367,7 @@ def main():
     if args.batch_steps > 0:
         del pt, ps, v, y
         torch.cuda.empty_cache()
-        out["batched"] = batched(args.batch_steps)
+        out["batched"] = batched(args.batch_steps, args.compact)
 
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(P, stats, args.cpu_groups)

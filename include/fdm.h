@@ -106,15 +106,24 @@ int fdm_build_tree_ex(const double* points_T, int64_t n_T,
  *  p2p_in_queue  1: the near-field work (blocks of target points) is queued
  *                behind the coupling items of the same launch; 0: separate
  *                launch.
+ *  compact       column compaction of the mixed FP32 coupling items (nb
+ *                64): per offset only the target boxes whose source box is
+ *                non-empty take matrix-core columns.
+ *                0: never; 1: on levels where it saves at least a fifth of
+ *                the columns (sparse leaf levels); 2: on every level.  No
+ *                effect in the other precisions.
  * Results do not depend on the launch shape except through nb, which
  * changes the grouping of the FP32 partial sums (the FP64 path is summed in
- * the same order for both nb).
+ * the same order for both nb), and compaction, which may change the FP32
+ * rounding of the products (same partial sums, same flush points).  A zero
+ * fdm_options.tune.nb selects the defaults {64, 1, 1, 0, 1}.
  */
 typedef struct {
   int32_t nb;
   int32_t persistent;
   int32_t lpt;
   int32_t p2p_in_queue;
+  int32_t compact;
 } fdm_tune;
 
 /*
@@ -131,7 +140,7 @@ typedef struct {
  *                     when the bank does not fit, and for plans that only run
  *                     in a batch (which brings its own workspace).
  *  tune               initial launch shape (NULL-equivalent: nb = 0 picks
- *                     the defaults {64, 1, 1, 0}).
+ *                     the defaults {64, 1, 1, 0, 1}).
  */
 typedef struct {
   int32_t precision;
@@ -148,8 +157,9 @@ int fdm_build_tree_opts(const double* points_T, int64_t n_T,
 
 /*
  * Launch shape of a plan: read, or set (rebuilds the plan's work lists when
- * nb changes; synchronises stream).  FDM_ERR_INVALID_ARG for nb not 32/64
- * or flags not 0/1; FDM_ERR_STATE while the plan belongs to a batch.
+ * nb changes; synchronises stream).  FDM_ERR_INVALID_ARG for nb not 32/64,
+ * flags not 0/1 or compact not 0..2; FDM_ERR_STATE while the plan belongs
+ * to a batch.
  */
 int fdm_plan_get_tune(const fdm_plan* plan, fdm_tune* out);
 int fdm_plan_set_tune(fdm_plan* plan, const fdm_tune* tune, void* stream);
@@ -157,7 +167,7 @@ int fdm_plan_set_tune(fdm_plan* plan, const fdm_tune* tune, void* stream);
 /*
  * fdm_plan_autotune -- time the coupling step under each candidate launch
  * shape (nb in {64, 32} x persistent in {1, 0} x lpt in {1, 0}, near field
- * kept as set) on the plan's own data and keep the fastest.  Runs one full
+ * and compaction kept as set) on the plan's own data and keep the fastest.  Runs one full
  * matvec of v into y first (same arguments as fdm_plan_matvec{,_c64}), then
  * one coupling step per candidate, and synchronises stream.
  *  max_candidates  how many of the 8 candidates to try, in the order above
@@ -226,7 +236,8 @@ typedef struct {
   int64_t near_pairs;           /* inadmissible leaf blocks                */
   int64_t near_entries;         /* sum of #t * #s over inadmissible blocks  */
   int64_t m2l_columns;          /* coupling products issued by the M2L
-                                   kernel, incl. zero-padded columns        */
+                                   kernel under the plan's launch shape,
+                                   incl. zero-padded columns                */
   int64_t device_bytes;         /* device memory held by the plan          */
   double setup_ms;              /* wall time of fdm_build_tree             */
 } fdm_stats;

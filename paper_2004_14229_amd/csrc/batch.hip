@@ -120,7 +120,7 @@ double time_on_stream(hipStream_t s, F&& f) {
   return ms;
 }
 
-std::vector<TuneConfig> candidates(bool persistent_only, int p2p_in_queue) {
+std::vector<TuneConfig> candidates(bool persistent_only, int p2p_in_queue, int compact) {
   std::vector<TuneConfig> out;
   for (int nb : {64, 32})
     for (int pers : {1, 0}) {
@@ -131,6 +131,7 @@ std::vector<TuneConfig> candidates(bool persistent_only, int p2p_in_queue) {
         c.persistent = pers;
         c.lpt = lpt;
         c.p2p_in_queue = p2p_in_queue;
+        c.compact = compact;
         out.push_back(c);
       }
     }
@@ -151,7 +152,7 @@ int fdm_plan_autotune(fdm_plan* plan, const void* v, void* y, int c64, int max_c
     if (!plan) fail(FDM_ERR_INVALID_ARG, "plan is NULL");
     Plan& P = plan->p;
     if (P.batch_owner) fail(FDM_ERR_STATE, "the plan belongs to a batch");
-    const auto cand = candidates(false, P.tune.p2p_in_queue);
+    const auto cand = candidates(false, P.tune.p2p_in_queue, P.tune.compact);
     if (max_candidates < 1 || max_candidates > static_cast<int>(cand.size()))
       fail(FDM_ERR_INVALID_ARG, "max_candidates out of range");
     if (P.nS) check_device_ptr(v, "v");
@@ -202,6 +203,7 @@ int fdm_batch_create(fdm_plan* const* plans, int n, int64_t workspace_bytes, voi
       b->tune.persistent = 1;
       b->tune.lpt = 1;
       b->tune.p2p_in_queue = 1;
+      b->tune.compact = plans[0]->p.tune.compact;
       const int64_t mb = bank_matrix_bytes(b->prec, b->ip);
       int64_t need = 0;
       for (int i = 0; i < n; ++i) {
@@ -282,7 +284,7 @@ int fdm_batch_autotune(fdm_batch* batch, const void* const* v, void* const* y, i
   return guarded([&] {
     if (!batch) fail(FDM_ERR_INVALID_ARG, "batch is NULL");
     fdm_batch& b = *batch;
-    const auto cand = candidates(true, 1);
+    const auto cand = candidates(true, 1, b.tune.compact);
     if (max_candidates < 1 || max_candidates > static_cast<int>(cand.size()))
       fail(FDM_ERR_INVALID_ARG, "max_candidates out of range");
     check_vectors(b, v, y, c64);

@@ -93,11 +93,17 @@ __device__ __forceinline__ void gstore16(void* p, double2 v) {
 // Shared prologue: the block's target boxes and their integer positions;
 // col[b][j] is the first moment element of target j's source column for the
 // offset held in buffer b (or -1: empty or outside the grid).
+//
+// Compacted offsets (FP32 items with NB = 64 at sparse levels): the first
+// nval[b] entries of col[b] are the non-empty source columns only, and
+// inv[b][j] is the entry of target slot j (-1: empty source).
 template <int NB>
 struct TargetTile {
   int32_t t[NB];
   int32_t x[NB], y[NB], z[NB];
   int64_t col[2][NB];
+  int32_t inv[2][NB];
+  int32_t nval[2];
 };
 
 template <int NB>
@@ -114,21 +120,46 @@ __device__ __forceinline__ void load_targets(TargetTile<NB>& S, const M2LItem& i
   }
 }
 
+// First moment element of target slot j's source column for offset od, or
+// -1 (no target, source outside the grid or empty).
+template <int NB>
+__device__ __forceinline__ int64_t source_column(const TargetTile<NB>& S, int j,
+                                                 const M2LDesc& D, int4 od, int c, int Kp) {
+  const int lim = 1 << D.level;
+  int64_t col = -1;
+  if (S.t[j] >= 0) {
+    const int sx = S.x[j] - od.x, sy = S.y[j] - od.y, sz = S.z[j] - od.z;
+    if (sx >= 0 && sy >= 0 && sz >= 0 && sx < lim && sy < lim && sz < lim) {
+      const int32_t sb = gmem(D.gridS)[morton3(sx, sy, sz, D.level)];
+      if (sb >= 0) col = (int64_t(sb) * D.nd + c) * Kp;
+    }
+  }
+  return col;
+}
+
 template <int NB>
 __device__ __forceinline__ void source_columns(TargetTile<NB>& S, int buf, const M2LDesc& D,
                                                int4 od, int c, int Kp) {
-  const int lim = 1 << D.level;
-  for (int j = threadIdx.x; j < NB; j += blockDim.x) {
-    int64_t col = -1;
-    if (S.t[j] >= 0) {
-      const int sx = S.x[j] - od.x, sy = S.y[j] - od.y, sz = S.z[j] - od.z;
-      if (sx >= 0 && sy >= 0 && sz >= 0 && sx < lim && sy < lim && sz < lim) {
-        const int32_t sb = gmem(D.gridS)[morton3(sx, sy, sz, D.level)];
-        if (sb >= 0) col = (int64_t(sb) * D.nd + c) * Kp;
-      }
-    }
-    S.col[buf][j] = col;
-  }
+  for (int j = threadIdx.x; j < NB; j += blockDim.x)
+    S.col[buf][j] = source_column(S, j, D, od, c, Kp);
+}
+
+// Compacted form: wave 0 (one lane per target slot) lists the non-empty
+// source columns in slot order.
+template <int NB>
+__device__ __forceinline__ void source_columns_compact(TargetTile<NB>& S, int buf,
+                                                       const M2LDesc& D, int4 od, int c,
+                                                       int Kp) {
+  static_assert(NB == 64, "one wave compacts the block");
+  if (threadIdx.x >= 64) return;
+  const int j = threadIdx.x;
+  const int64_t col = source_column(S, j, D, od, c, Kp);
+  const unsigned long long mask = __ballot(col >= 0);
+  const int i = __builtin_amdgcn_mbcnt_hi(static_cast<uint32_t>(mask >> 32),
+                                          __builtin_amdgcn_mbcnt_lo(static_cast<uint32_t>(mask), 0));
+  if (col >= 0) S.col[buf][i] = col;
+  S.inv[buf][j] = col >= 0 ? i : -1;
+  if (j == 0) S.nval[buf] = __popcll(mask);
 }
 
 // Offset list entries are the same for the whole workgroup and read-only
@@ -481,6 +512,179 @@ __device__ __forceinline__ void item_f32(F32Shared<NB>& sh, const M2LItem& it,
     if (more) store_cols<Tr, NB>(sh, cur ^ 1, nxt);
     __syncthreads();
   }
+}
+
+// ------------------------------------------- FP32, compacted columns --
+// At sparse levels most target slots of a block see an empty source box
+// for a given offset, and their zero columns cost the matrix cores as much
+// as the others.  A compacted item (NB = 64) takes, per offset, only the
+// non-empty source columns, 32 at a time (one MFMA column tile per pass;
+// a second pass, which reads the coupling matrix again, only for offsets
+// with more than 32), and adds each pass's 32x32 per-offset sums into the
+// FP32 totals of the target slots with a lane permutation.  Per-offset
+// sums, totals and flush points are those of the plain FP32 item; only
+// zero columns are skipped.
+
+// Moment columns of one k slab for compacted entries base .. base+31.
+__device__ __forceinline__ float4 load_cols_compact(const TargetTile<64>& S, int colbuf,
+                                                    int base, const float* __restrict__ mom,
+                                                    int k0) {
+  constexpr int PPC = F32Traits::KS * 2 / 4;  // float4 pieces per column
+  float4 val{};
+  const int e = threadIdx.x;
+  if (e < 32 * PPC) {
+    const int i = base + e / PPC;
+    if (i < S.nval[colbuf])
+      val = gload16<float4>(mom + 2 * (S.col[colbuf][i] + k0) + (e % PPC) * 4);
+  }
+  return val;
+}
+
+// One column tile of one k slab (columns 0 .. 31 of the staged slab).
+__device__ __forceinline__ void mfma32_tile(f16v& ar, f16v& ai, const float (&a)[2][8],
+                                            const F32Shared<64>& sh, int buf, int lane) {
+  const int kl = lane / 32, cl = lane % 32;
+#pragma unroll
+  for (int t = 0; t < 8; ++t) {
+    const int kk = 2 * t;
+    const float b_r = sh.B[buf][0][kk + kl][cl];
+    const float b_i = sh.B[buf][1][kk + kl][cl];
+    ar = __builtin_amdgcn_mfma_f32_32x32x2f32(a[0][t], b_r, ar, 0, 0, 0);
+    ar = __builtin_amdgcn_mfma_f32_32x32x2f32(-a[1][t], b_i, ar, 0, 0, 0);
+    ai = __builtin_amdgcn_mfma_f32_32x32x2f32(a[0][t], b_i, ai, 0, 0, 0);
+    ai = __builtin_amdgcn_mfma_f32_32x32x2f32(a[1][t], b_r, ai, 0, 0, 0);
+  }
+}
+
+// Adds a pass's per-offset sums (compacted entries base .. base+31, lane
+// (i - base) + 32 h holding rows of half h) into the totals of the target
+// slots (slot j in tile j / 32, lane j % 32 + 32 h).  Rows are the same in
+// both layouts, so lane L of tile cs takes its value from lane
+// inv[j] - base + 32 (L / 32) of the pass, when slot j's entry is in the pass.
+__device__ __forceinline__ void scatter_add(f16v (&tor)[2], f16v (&toi)[2], const f16v& ar,
+                                            const f16v& ai, const TargetTile<64>& S, int buf,
+                                            int base, int lane) {
+#pragma unroll
+  for (int cs = 0; cs < 2; ++cs) {
+    const int ic = S.inv[buf][32 * cs + lane % 32] - base;
+    const bool in = ic >= 0 && ic < 32;
+    const int addr = 4 * ((in ? ic : 0) + 32 * (lane / 32));
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+      const float vr = __int_as_float(__builtin_amdgcn_ds_bpermute(addr, __float_as_int(ar[e])));
+      const float vi = __int_as_float(__builtin_amdgcn_ds_bpermute(addr, __float_as_int(ai[e])));
+      if (in) {
+        tor[cs][e] += vr;
+        toi[cs][e] += vi;
+      }
+    }
+  }
+}
+
+// Compacted FP32 item.  One pipeline step = one (offset, pass, k slab); an
+// offset's pass count is known once its columns are compacted, which
+// happens one offset ahead (double-buffered column lists).
+__device__ __forceinline__ void item_f32_compact(F32Shared<64>& sh, const M2LItem& it,
+                                                 const M2LDesc& D, int Kp) {
+  using Tr = F32Traits;
+  const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+  const bool rows_here = 32 * wave < Kp;
+  load_targets(sh.S, it, D);
+  __syncthreads();
+  double2* out = static_cast<double2*>(D.out);
+  f16v tor[2], toi[2];
+  zero(tor);
+  zero(toi);
+  const int nv = it.vo_count;
+  if (nv == 0) {  // no source box: the result is zero
+    if (rows_here && it.first)
+      flush_rows32<64>(tor, toi, sh.S, out, D.nd, it.c, Kp, wave, lane, true);
+    return;
+  }
+  const float* mom = static_cast<const float*>(D.mom);
+  const float* bank = static_cast<const float*>(D.bank);
+  const int64_t per = int64_t(Kp) * Kp;
+  const int ns = Kp / Tr::KS;  // k slabs per pass (>= 2)
+  auto passes = [&](int b) {
+    const int n = __builtin_amdgcn_readfirstlane(sh.S.nval[b]);
+    return std::max(1, (n + 31) / 32);
+  };
+  int4 od_cur = offset_of(D, it.vo_begin);
+  int4 od_next = od_cur;
+  source_columns_compact(sh.S, 0, D, od_cur, it.c, Kp);
+  __syncthreads();
+  int np = passes(0);
+  {
+    const float4 v0 = load_cols_compact(sh.S, 0, 0, mom, 0);
+    if (threadIdx.x < 256) store_cols<Tr, 64>(sh, 0, v0);
+  }
+  __syncthreads();
+  bool first = it.first != 0;
+  f16v acr, aci;
+  int v = 0, p = 0, s = 0, cur = 0;
+  for (;;) {
+    if (s == 0 && p == 0 && v + 1 < nv) {  // compact the next offset's columns
+      od_next = offset_of(D, it.vo_begin + v + 1);
+      source_columns_compact(sh.S, (v + 1) & 1, D, od_next, it.c, Kp);
+    }
+    int v2 = v, p2 = p, s2 = s + 1;
+    if (s2 == ns) {
+      s2 = 0;
+      if (++p2 == np) {
+        p2 = 0;
+        ++v2;
+      }
+    }
+    const bool more = v2 < nv;
+    float4 nxt{};
+    if (more) nxt = load_cols_compact(sh.S, v2 & 1, 32 * p2, mom, s2 * Tr::KS);
+    if (rows_here) {
+      if (s == 0) {
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+          acr[i] = 0.f;
+          aci[i] = 0.f;
+        }
+      }
+      float a[2][8];
+      load_a32(a, bank + od_cur.w * 2 * per, per, s * Tr::KS, Kp, wave, lane);
+      __builtin_amdgcn_sched_barrier(0);
+      mfma32_tile(acr, aci, a, sh, cur, lane);
+      if (s == ns - 1) {
+        scatter_add(tor, toi, acr, aci, sh.S, v & 1, 32 * p, lane);
+        if (v2 != v && ((v + 1) % kFlush == 0 || !more)) {
+          flush_rows32<64>(tor, toi, sh.S, out, D.nd, it.c, Kp, wave, lane, first);
+          first = false;
+          zero(tor);
+          zero(toi);
+        }
+      }
+    }
+    if (more && threadIdx.x < 256) store_cols<Tr, 64>(sh, cur ^ 1, nxt);
+    __syncthreads();
+    if (!more) break;
+    if (v2 != v) {
+      od_cur = od_next;
+      np = passes(v2 & 1);
+    }
+    v = v2;
+    p = p2;
+    s = s2;
+    cur ^= 1;
+  }
+}
+
+// FP32 item: compacted where the level asks for it (NB = 64).
+template <int NB, bool ADD>
+__device__ __forceinline__ void item_f32k(F32Shared<NB>& sh, const M2LItem& it,
+                                          const M2LDesc& D, int Kp) {
+  if constexpr (NB == 64) {
+    if (D.compact) {
+      item_f32_compact(sh, it, D, Kp);
+      return;
+    }
+  }
+  item_f32<NB, ADD>(sh, it, D, Kp);
 }
 
 // ------------------------------------------------- BF16 split precision --

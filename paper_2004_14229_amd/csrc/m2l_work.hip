@@ -22,8 +22,32 @@ BankLevel bank_level(const Plan& P, int l) {
   return BankLevel{P.L[l].dirvec.get(), P.L[l].h, P.kappa, l, P.L[l].nd};
 }
 
+// Whether level l's FP32 items take compacted columns under `cfg`: mode 1
+// when the compacted tiles (32 columns each) save at least a fifth of the
+// plain items' columns (nb per offset).
+bool level_compact(const Plan& P, int l, const TuneConfig& cfg) {
+  if (!cfg.compact || !compact_supported(P.prec, cfg.nb) || P.tune.nb != cfg.nb)
+    return false;
+  if (cfg.compact == 2) return true;
+  if (l >= static_cast<int>(P.level_pairs.size())) return false;
+  return 5 * 32 * P.level_tiles[l] <= 4 * int64_t(cfg.nb) * P.level_pairs[l];
+}
+
+}  // namespace
+
+int64_t issued_columns(const Plan& P, const TuneConfig& cfg) {
+  int64_t n = 0;
+  for (size_t l = 0; l < P.level_pairs.size(); ++l)
+    n += level_compact(P, static_cast<int>(l), cfg) ? 32 * P.level_tiles[l]
+                                                     : int64_t(P.tune.nb) * P.level_pairs[l];
+  return n;
+}
+
+namespace {
+
 // `bank` holds bank id bank_id0 as its first matrix.
-M2LDesc level_desc(const Plan& P, int l, const void* bank, int64_t bank_id0) {
+M2LDesc level_desc(const Plan& P, int l, const void* bank, int64_t bank_id0,
+                   const TuneConfig& cfg) {
   const LevelData& Ld = P.L[l];
   M2LDesc d{};
   d.gridS = P.S.grid[l].get();
@@ -39,6 +63,7 @@ M2LDesc level_desc(const Plan& P, int l, const void* bank, int64_t bank_id0) {
                                          static_cast<uintptr_t>(bank_id0 * mb));
   d.nd = Ld.nd;
   d.level = l;
+  d.compact = level_compact(P, l, cfg) ? 1 : 0;
   return d;
 }
 
@@ -62,11 +87,11 @@ struct LaunchBuilder {
 // Items of plan P restricted to the bank ids [b0, b1), whose matrices sit
 // at `bank` with bank id b0 at position slot0.
 void add_source(LaunchBuilder& B, const Plan& P, int64_t b0, int64_t b1, const void* bank,
-                int64_t slot0, std::vector<uint8_t>& emitted) {
+                int64_t slot0, const TuneConfig& cfg, std::vector<uint8_t>& emitted) {
   std::vector<int32_t> desc_of(P.levels + 1, -1);
   for (int l = std::max(P.l_min, 0); l <= P.levels; ++l) {
     desc_of[l] = static_cast<int32_t>(B.descs.size());
-    B.descs.push_back(level_desc(P, l, bank, b0 - slot0));
+    B.descs.push_back(level_desc(P, l, bank, b0 - slot0, cfg));
   }
   const auto& vo = P.valid_off_h;
   for (size_t i = 0; i < P.base_items.size(); ++i) {
@@ -155,7 +180,7 @@ std::vector<M2LLaunch> build_schedule(const std::vector<Plan*>& plans, const Tun
     Plan& P = *plans[p];
     if (P.base_items.empty() || P.bank_budget != 0) continue;
     if (B.empty()) B.emplace_back();
-    add_source(B[0], P, 0, P.n_bank, resident_bank(P), 0, emitted[p]);
+    add_source(B[0], P, 0, P.n_bank, resident_bank(P), 0, cfg, emitted[p]);
   }
   // streamed banks: consecutive bank ids packed into launches of at most
   // ws_matrices matrices, and of about equal work (blocks using the
@@ -195,7 +220,7 @@ std::vector<M2LLaunch> build_schedule(const std::vector<Plan*>& plans, const Tun
       }
       const int64_t slot0 = ws_matrices - left;
       add_generation(B.back(), P, b, e);
-      add_source(B.back(), P, b, e, ws, slot0, emitted[p]);
+      add_source(B.back(), P, b, e, ws, slot0, cfg, emitted[p]);
       left -= e - b;
       if (e < P.n_bank) left = 0;  // full (matrices or work): next launch
       b = e;
@@ -340,14 +365,17 @@ void build_m2l_work(Plan& P, hipStream_t s) {
   P.valid_off_h.clear();
   P.sched.clear();
   P.sched_ready = false;
-  P.m2l_columns = 0;
+  P.level_pairs.clear();
+  P.level_tiles.clear();
   if (n_items == 0) {
     P.valid_off.alloc(1, &P.tally);
     FDM_HIP(hipStreamSynchronize(s));
     return;
   }
   std::vector<M2LDesc> descs(p + 1);
-  for (int l = 0; l <= p; ++l) descs[l] = level_desc(P, l, nullptr, 0);
+  TuneConfig plain;
+  plain.compact = 0;
+  for (int l = 0; l <= p; ++l) descs[l] = level_desc(P, l, nullptr, 0, plain);
   DevBuf<M2LDesc> d_descs;
   to_device(d_descs, descs, s, nullptr);
   DevBuf<M2LItem> d_items;
@@ -356,11 +384,12 @@ void build_m2l_work(Plan& P, hipStream_t s) {
   to_device(d_cand, cand, s, nullptr);
   to_device(d_cb, cand_begin_per_item, s, nullptr);
   to_device(d_cc, cand_count_per_item, s, nullptr);
-  DevBuf<unsigned long long> d_bpo(std::max<int64_t>(P.n_bank, 1));
+  DevBuf<unsigned long long> d_bpo(std::max<int64_t>(P.n_bank, 1)), d_tiles(p + 1);
   FDM_HIP(hipMemsetAsync(d_bpo.get(), 0, d_bpo.bytes(), s));
+  FDM_HIP(hipMemsetAsync(d_tiles.get(), 0, d_tiles.bytes(), s));
   launch_valid_offsets(d_items.get(), n_items, d_cb.get(), d_cc.get(), d_cand.get(),
                        d_descs.get(), P.tgt_list.get(), P.offtab.get(), 0, d_counts.get(),
-                       nullptr, nullptr, nullptr, s);
+                       nullptr, nullptr, nullptr, nullptr, s);
   std::vector<int32_t> counts = to_host(d_counts.get(), n_items, s);
   std::vector<int32_t> begin(n_items);
   int64_t total = 0;
@@ -373,8 +402,12 @@ void build_m2l_work(Plan& P, hipStream_t s) {
   P.valid_off.alloc(std::max<int64_t>(total, 1), &P.tally);
   launch_valid_offsets(d_items.get(), n_items, d_cb.get(), d_cc.get(), d_cand.get(),
                        d_descs.get(), P.tgt_list.get(), P.offtab.get(), 1, nullptr,
-                       d_begin.get(), P.valid_off.get(), d_bpo.get(), s);
+                       d_begin.get(), P.valid_off.get(), d_bpo.get(), d_tiles.get(), s);
   std::vector<unsigned long long> bpo = to_host(d_bpo.get(), P.n_bank, s);
+  const std::vector<unsigned long long> tiles = to_host(d_tiles.get(), p + 1, s);
+  P.level_tiles.assign(tiles.begin(), tiles.end());
+  P.level_pairs.assign(p + 1, 0);
+  for (int64_t i = 0; i < n_items; ++i) P.level_pairs[items[i].desc] += counts[i];
   P.bank_work.assign(bpo.begin(), bpo.end());
   P.valid_off_h = to_host(P.valid_off.get(), total, s);
   for (int64_t i = 0; i < n_items; ++i) {
@@ -385,7 +418,6 @@ void build_m2l_work(Plan& P, hipStream_t s) {
   // statistics and per-level offset use for export
   P.n_couplings = 0;
   P.n_stored = 0;
-  P.m2l_columns = total * nb;
   P.off_used.assign(p + 1, {});
   for (int l = 0; l <= p; ++l) {
     if (l < P.l_min) continue;

@@ -231,11 +231,13 @@ TuneConfig check_tune(const fdm_tune& t) {
   if (t.nb != 32 && t.nb != 64) fail(FDM_ERR_INVALID_ARG, "tune.nb must be 32 or 64");
   for (int v : {t.persistent, t.lpt, t.p2p_in_queue})
     if (v != 0 && v != 1) fail(FDM_ERR_INVALID_ARG, "tune flags must be 0 or 1");
+  if (t.compact < 0 || t.compact > 2) fail(FDM_ERR_INVALID_ARG, "tune.compact must be 0, 1 or 2");
   TuneConfig c;
   c.nb = t.nb;
   c.persistent = t.persistent;
   c.lpt = t.lpt;
   c.p2p_in_queue = t.p2p_in_queue;
+  c.compact = t.compact;
   return c;
 }
 
@@ -245,6 +247,7 @@ fdm_tune to_c(const TuneConfig& c) {
   t.persistent = c.persistent;
   t.lpt = c.lpt;
   t.p2p_in_queue = c.p2p_in_queue;
+  t.compact = c.compact;
   return t;
 }
 
@@ -481,7 +484,7 @@ int fdm_plan_stats(const fdm_plan* plan, fdm_stats* out) {
     st.n_bank_matrices = P.n_bank;
     st.near_pairs = P.near_pairs;
     st.near_entries = P.near_entries;
-    st.m2l_columns = P.m2l_columns;
+    st.m2l_columns = issued_columns(P, P.tune);
     st.device_bytes = P.tally;
     st.setup_ms = P.setup_ms;
     *out = st;

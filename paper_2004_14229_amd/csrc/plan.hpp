@@ -59,6 +59,7 @@ struct M2LDesc {
   // range of ids this address lies before the workspace (never read there)
   const void* bank;
   int32_t nd, level;
+  int32_t compact;  // FP32 items of this level use compacted columns
 };
 
 // Descriptor of one plan's near field in a queued launch.
@@ -99,6 +100,7 @@ struct TuneConfig {
   int persistent = 1;    // 1: persistent workgroups pulling from a device queue
   int lpt = 1;           // 1: heaviest items first; 0: (level, octant, direction, block)
   int p2p_in_queue = 0;  // near-field items in the coupling launch
+  int compact = 1;       // FP32 column compaction: 0 never, 1 sparse levels, 2 all
 };
 
 // One coupling launch: optional bank generation into a workspace, then the
@@ -155,6 +157,9 @@ struct Plan {
   DevBuf<uint8_t> bank_ws;
   std::vector<int32_t> bank_info;  // per bank id: level, ox, oy, oz, c
   std::vector<int64_t> bank_work;  // per bank id: admissible blocks using it
+  // per level: (item, offset) pairs of the work lists, and the 32-column
+  // tiles they take when compacted
+  std::vector<int64_t> level_pairs, level_tiles;
 
   // coupling work (per plan; a batch builds its own launches from it)
   TuneConfig tune;
@@ -177,7 +182,6 @@ struct Plan {
 
   // statistics
   int64_t n_couplings = 0, n_stored = 0, near_pairs = 0, near_entries = 0;
-  int64_t m2l_columns = 0;
   double setup_ms = 0;
   bool has_run = false;
 
@@ -250,13 +254,19 @@ void launch_valid_offsets(const M2LItem* items, int64_t n_items, const int32_t* 
                           const int32_t* cand_count, const int32_t* cand, const M2LDesc* descs,
                           const int32_t* tgt_list, const int4* offtab, int pass,
                           int32_t* counts, const int32_t* out_begin, int32_t* out,
-                          unsigned long long* blocks_per_off, hipStream_t s);
+                          unsigned long long* blocks_per_off,
+                          unsigned long long* tiles_per_level, hipStream_t s);
 int m2l_threads(int Kp);
 // Near-field items can share the coupling launch (FP32 / BF16, Kp <= 256);
 // otherwise the near field runs as its own launch whatever the tune says.
 inline bool p2p_queue_supported(int prec, int Kp) {
   return prec != FDM_PREC_FP64 && Kp <= 256;
 }
+// Compacted coupling items exist in the FP32 kernel with 64 targets per
+// item.
+inline bool compact_supported(int prec, int nb) { return prec == FDM_PREC_FP32 && nb == 64; }
+// Matrix-core columns of one coupling step under cfg (zero padding included).
+int64_t issued_columns(const Plan& P, const TuneConfig& cfg);
 int64_t m2l_resident_groups(int prec, int nb, int Kp, bool parts);
 // per-precision coupling launches (m2l_f64.hip, m2l_f32.hip, m2l_bf16.hip)
 void launch_items_f64(const M2LLaunch& L, int Kp, int nb, bool persistent, int32_t* head,

@@ -34,15 +34,20 @@ class FdmError(RuntimeError):
 
 
 class Tune(ctypes.Structure):
+    """fdm_tune: nb, persistent, lpt, p2p_in_queue, compact (0 never, 1
+    sparse levels, 2 every level)."""
     _fields_ = [("nb", ctypes.c_int32), ("persistent", ctypes.c_int32),
-                ("lpt", ctypes.c_int32), ("p2p_in_queue", ctypes.c_int32)]
+                ("lpt", ctypes.c_int32), ("p2p_in_queue", ctypes.c_int32),
+                ("compact", ctypes.c_int32)]
+    DEFAULTS = {"nb": 64, "persistent": 1, "lpt": 1, "p2p_in_queue": 0, "compact": 1}
 
     def as_dict(self) -> dict:
         return {name: getattr(self, name) for name, _ in self._fields_}
 
     @classmethod
     def from_dict(cls, d: dict) -> "Tune":
-        return cls(*(int(d[name]) for name, _ in cls._fields_))
+        """Fields missing from d take the library's defaults."""
+        return cls(*(int(d.get(name, cls.DEFAULTS[name])) for name, _ in cls._fields_))
 
 
 class Options(ctypes.Structure):
@@ -154,7 +159,7 @@ class Plan:
         pt, ps = _points(points_T), _points(points_S)
         box_arr = (ctypes.c_double * 6)(*[float(b) for b in box])
         opts = Options(PRECISION[precision], -2 if l_hf is None else int(l_hf),
-                       int(bank_budget), Tune.from_dict(tune) if tune else Tune(0, 0, 0, 0))
+                       int(bank_budget), Tune.from_dict(tune) if tune else Tune())
         h = ctypes.c_void_p()
         st = lib().fdm_build_tree_opts(
             _ptr(pt), pt.shape[0], _ptr(ps), ps.shape[0], float(kappa), box_arr,

@@ -51,18 +51,19 @@ def test_null_handles():
     assert L.fdm_plan_export(None, b"perm_T", None, 0, ctypes.byref(size)) == -1
 
 
-def _build_opts(nb=64, budget=0, prec=0, persistent=1):
+def _build_opts(nb=64, budget=0, prec=0, persistent=1, compact=1):
     L = F.lib()
     h = ctypes.c_void_p()
     box = (ctypes.c_double * 6)(0, 0, 0, 1, 1, 1)
-    opts = F.fdm.Options(prec, -2, budget, F.fdm.Tune(nb, persistent, 1, 0))
+    opts = F.fdm.Options(prec, -2, budget, F.fdm.Tune(nb, persistent, 1, 0, compact))
     st = L.fdm_build_tree_opts(None, 0, None, 0, 1.0, box, 3, 4, ctypes.byref(opts), None,
                                ctypes.byref(h))
     return st, h, L.fdm_last_error().decode()
 
 
 @pytest.mark.parametrize("kw", [dict(nb=48), dict(nb=0, budget=-1), dict(budget=1),
-                                dict(persistent=2), dict(prec=5)])
+                                dict(persistent=2), dict(prec=5), dict(compact=3),
+                                dict(compact=-1)])
 def test_invalid_options_are_rejected(kw):
     st, h, msg = _build_opts(**kw)
     assert st == -1 and h.value is None and msg
@@ -70,7 +71,7 @@ def test_invalid_options_are_rejected(kw):
 
 def test_null_handles_are_rejected():
     L = F.lib()
-    t = F.fdm.Tune(64, 1, 1, 0)
+    t = F.fdm.Tune(64, 1, 1, 0, 1)
     assert L.fdm_plan_set_tune(None, ctypes.byref(t), None) == -1
     assert L.fdm_plan_get_tune(None, ctypes.byref(t)) == -1
     out = ctypes.c_void_p()

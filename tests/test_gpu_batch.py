@@ -19,8 +19,10 @@ pytestmark = pytest.mark.gpu
 TOL_FP64 = 1e-12
 TOL_FP32 = 1e-6
 
-TUNES = [dict(nb=nb, persistent=p, lpt=l, p2p_in_queue=q)
+TUNES = [dict(nb=nb, persistent=p, lpt=l, p2p_in_queue=q, compact=0)
          for nb in (64, 32) for p in (1, 0) for l in (1, 0) for q in (0, 1)]
+# compacted FP32 columns on every level, for each nb = 64 launch shape
+TUNES += [dict(t, compact=2) for t in TUNES if t["nb"] == 64]
 
 
 _oracle_cache = {}
@@ -80,11 +82,54 @@ def test_streamed_bank_matches_oracle(precision, tol):
     n = st["n_bank_matrices"]
     assert n > 20
     for budget in (mat, 7 * mat, (n // 3) * mat):
-        for t in (TUNES[0], TUNES[-1]):
+        for t in (TUNES[0], TUNES[15], TUNES[-1]):
             y, st2 = plan_y(P, precision, bank_budget=budget, tune=t)
             assert rel(y, yo) <= tol, (budget, t)
             assert st2["n_couplings"] == st["n_couplings"]
     assert rel(y_res, yo) <= tol
+
+
+@pytest.mark.parametrize("seed,nt,ns,kappa,levels,m,clustered", [
+    (311, 700, 650, 45.0, 4, 3, False), (312, 3000, 2600, 60.0, 5, 3, True),
+    (313, 1500, 1400, 30.0, 4, 5, False), (314, 90, 2000, 20.0, 4, 4, False)])
+def test_compacted_columns_match_plain(seed, nt, ns, kappa, levels, m, clustered):
+    """Mixed FP32 with compacted coupling columns (on every level, and on
+    the levels the automatic rule picks) against the oracle and against the
+    plain FP32 items.  Compaction only drops zero columns: every target's
+    per-offset sums, FP32 totals and flush points are unchanged, so the
+    results agree with the plain items bit for bit."""
+    if clustered:
+        P = W.clustered_problem(seed, nt, ns, kappa, levels, m)
+    else:
+        P = W.random_problem(seed, nt, ns, kappa, levels, m)
+    yo = oracle_y(P)
+    base = dict(nb=64, persistent=1, lpt=1, p2p_in_queue=0)
+    y0, st0 = plan_y(P, "fp32", tune=dict(base, compact=0))
+    y1, st1 = plan_y(P, "fp32", tune=dict(base, compact=1))
+    y2, st2 = plan_y(P, "fp32", tune=dict(base, compact=2))
+    for y in (y0, y1, y2):
+        assert rel(y, yo) <= TOL_FP32
+    assert np.array_equal(y0, y2) and np.array_equal(y0, y1)
+    assert st2["m2l_columns"] <= st1["m2l_columns"] <= st0["m2l_columns"]
+    assert st1["n_couplings"] == st0["n_couplings"]
+
+
+def test_compacted_columns_streamed_and_grid():
+    """Compacted items split over streamed-bank launches (first part
+    stores, later parts add), in grid and persistent launches."""
+    P = W.random_problem(315, 1200, 1100, 50.0, 4, 4)
+    yo = oracle_y(P)
+    K = (P.m + 1) ** 3
+    Kp = (K + 31) // 32 * 32
+    mat = Kp * Kp * 8
+    y_ref, _ = plan_y(P, "fp32", tune=dict(nb=64, compact=0))
+    for pers in (1, 0):
+        for budget in (0, 3 * mat):
+            y, _ = plan_y(P, "fp32", bank_budget=budget,
+                          tune=dict(nb=64, persistent=pers, compact=2))
+            assert rel(y, yo) <= TOL_FP32, (pers, budget)
+            if budget == 0:
+                assert np.array_equal(y, y_ref), pers
 
 
 def test_streamed_bank_uniform2k_fp32():

@@ -155,3 +155,14 @@ def random_problem(seed: int, n_T: int, n_S: int, kappa: float, levels: int,
     ps = hi - (hi - lo) * rng.random((n_S, 3))
     v = complex_normal(rng, n_S)
     return Problem(f"rand{seed}", pt, ps, v, float(kappa), tuple(box), levels, m)
+
+
+def clustered_problem(seed: int, n_T: int, n_S: int, kappa: float, levels: int,
+                      m: int) -> Problem:
+    """Small clustered problem in the unit cube (tests): Gaussian blobs, so
+    that the leaf levels hold many empty boxes."""
+    rng = np.random.default_rng(seed)
+    pt = clustered_points(rng, n_T)
+    ps = clustered_points(rng, n_S)
+    v = complex_normal(rng, n_S)
+    return Problem(f"clus{seed}", pt, ps, v, float(kappa), UNIT_BOX, levels, m)
