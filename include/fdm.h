@@ -106,16 +106,16 @@ int fdm_build_tree_ex(const double* points_T, int64_t n_T,
  *  p2p_in_queue  1: the near-field work (blocks of target points) is queued
  *                behind the coupling items of the same launch; 0: separate
  *                launch.
- *  compact       column compaction of the mixed FP32 coupling items (nb
- *                64): per offset only the target boxes whose source box is
- *                non-empty take matrix-core columns.
+ *  compact       column compaction of the mixed FP32 and BF16 split
+ *                coupling items (nb 64): per offset only the target boxes
+ *                whose source box is non-empty take matrix-core columns.
  *                0: never; 1: on levels where it saves at least a fifth of
  *                the columns (sparse leaf levels); 2: on every level.  No
- *                effect in the other precisions.
+ *                effect in plain FP64.
  * Results do not depend on the launch shape except through nb, which
  * changes the grouping of the FP32 partial sums (the FP64 path is summed in
- * the same order for both nb), and compaction, which may change the FP32
- * rounding of the products (same partial sums, same flush points).  A zero
+ * the same order for both nb); compaction skips zero columns only and
+ * leaves every partial sum and flush point as it is.  A zero
  * fdm_options.tune.nb selects the defaults {64, 1, 1, 0, 1}.
  */
 typedef struct {

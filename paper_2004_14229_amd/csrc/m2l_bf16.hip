@@ -6,7 +6,7 @@ namespace fdm {
 
 namespace {
 
-FDM_M2L_KERNEL(k_m2l_bf16x3, BF16Shared, item_bf16, true)
+FDM_M2L_KERNEL(k_m2l_bf16x3, BF16Shared, item_bf16k, true)
 FDM_M2L_LAUNCHERS(k_m2l_bf16x3, launch_items_bf16, resident_bf16, false)
 
 }  // namespace

@@ -514,16 +514,16 @@ __device__ __forceinline__ void item_f32(F32Shared<NB>& sh, const M2LItem& it,
   }
 }
 
-// ------------------------------------------- FP32, compacted columns --
+// ------------------------------------- compacted columns: the helpers --
 // At sparse levels most target slots of a block see an empty source box
 // for a given offset, and their zero columns cost the matrix cores as much
-// as the others.  A compacted item (NB = 64) takes, per offset, only the
-// non-empty source columns, 32 at a time (one MFMA column tile per pass;
-// a second pass, which reads the coupling matrix again, only for offsets
-// with more than 32), and adds each pass's 32x32 per-offset sums into the
-// FP32 totals of the target slots with a lane permutation.  Per-offset
-// sums, totals and flush points are those of the plain FP32 item; only
-// zero columns are skipped.
+// as the others.  A compacted item (FP32 or BF16 split products, NB = 64)
+// takes, per offset, only the non-empty source columns, 32 at a time (one
+// MFMA column tile per pass; a second pass, which reads the coupling matrix
+// again, only for offsets with more than 32), and adds each pass's 32x32
+// per-offset sums into the FP32 totals of the target slots with a lane
+// permutation.  Per-offset sums, totals and flush points are those of the
+// plain item; only zero columns are skipped.
 
 // Moment columns of one k slab for compacted entries base .. base+31.
 __device__ __forceinline__ float4 load_cols_compact(const TargetTile<64>& S, int colbuf,
@@ -579,112 +579,6 @@ __device__ __forceinline__ void scatter_add(f16v (&tor)[2], f16v (&toi)[2], cons
       }
     }
   }
-}
-
-// Compacted FP32 item.  One pipeline step = one (offset, pass, k slab); an
-// offset's pass count is known once its columns are compacted, which
-// happens one offset ahead (double-buffered column lists).
-__device__ __forceinline__ void item_f32_compact(F32Shared<64>& sh, const M2LItem& it,
-                                                 const M2LDesc& D, int Kp) {
-  using Tr = F32Traits;
-  const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
-  const bool rows_here = 32 * wave < Kp;
-  load_targets(sh.S, it, D);
-  __syncthreads();
-  double2* out = static_cast<double2*>(D.out);
-  f16v tor[2], toi[2];
-  zero(tor);
-  zero(toi);
-  const int nv = it.vo_count;
-  if (nv == 0) {  // no source box: the result is zero
-    if (rows_here && it.first)
-      flush_rows32<64>(tor, toi, sh.S, out, D.nd, it.c, Kp, wave, lane, true);
-    return;
-  }
-  const float* mom = static_cast<const float*>(D.mom);
-  const float* bank = static_cast<const float*>(D.bank);
-  const int64_t per = int64_t(Kp) * Kp;
-  const int ns = Kp / Tr::KS;  // k slabs per pass (>= 2)
-  auto passes = [&](int b) {
-    const int n = __builtin_amdgcn_readfirstlane(sh.S.nval[b]);
-    return std::max(1, (n + 31) / 32);
-  };
-  int4 od_cur = offset_of(D, it.vo_begin);
-  int4 od_next = od_cur;
-  source_columns_compact(sh.S, 0, D, od_cur, it.c, Kp);
-  __syncthreads();
-  int np = passes(0);
-  {
-    const float4 v0 = load_cols_compact(sh.S, 0, 0, mom, 0);
-    if (threadIdx.x < 256) store_cols<Tr, 64>(sh, 0, v0);
-  }
-  __syncthreads();
-  bool first = it.first != 0;
-  f16v acr, aci;
-  int v = 0, p = 0, s = 0, cur = 0;
-  for (;;) {
-    if (s == 0 && p == 0 && v + 1 < nv) {  // compact the next offset's columns
-      od_next = offset_of(D, it.vo_begin + v + 1);
-      source_columns_compact(sh.S, (v + 1) & 1, D, od_next, it.c, Kp);
-    }
-    int v2 = v, p2 = p, s2 = s + 1;
-    if (s2 == ns) {
-      s2 = 0;
-      if (++p2 == np) {
-        p2 = 0;
-        ++v2;
-      }
-    }
-    const bool more = v2 < nv;
-    float4 nxt{};
-    if (more) nxt = load_cols_compact(sh.S, v2 & 1, 32 * p2, mom, s2 * Tr::KS);
-    if (rows_here) {
-      if (s == 0) {
-#pragma unroll
-        for (int i = 0; i < 16; ++i) {
-          acr[i] = 0.f;
-          aci[i] = 0.f;
-        }
-      }
-      float a[2][8];
-      load_a32(a, bank + od_cur.w * 2 * per, per, s * Tr::KS, Kp, wave, lane);
-      __builtin_amdgcn_sched_barrier(0);
-      mfma32_tile(acr, aci, a, sh, cur, lane);
-      if (s == ns - 1) {
-        scatter_add(tor, toi, acr, aci, sh.S, v & 1, 32 * p, lane);
-        if (v2 != v && ((v + 1) % kFlush == 0 || !more)) {
-          flush_rows32<64>(tor, toi, sh.S, out, D.nd, it.c, Kp, wave, lane, first);
-          first = false;
-          zero(tor);
-          zero(toi);
-        }
-      }
-    }
-    if (more && threadIdx.x < 256) store_cols<Tr, 64>(sh, cur ^ 1, nxt);
-    __syncthreads();
-    if (!more) break;
-    if (v2 != v) {
-      od_cur = od_next;
-      np = passes(v2 & 1);
-    }
-    v = v2;
-    p = p2;
-    s = s2;
-    cur ^= 1;
-  }
-}
-
-// FP32 item: compacted where the level asks for it (NB = 64).
-template <int NB, bool ADD>
-__device__ __forceinline__ void item_f32k(F32Shared<NB>& sh, const M2LItem& it,
-                                          const M2LDesc& D, int Kp) {
-  if constexpr (NB == 64) {
-    if (D.compact) {
-      item_f32_compact(sh, it, D, Kp);
-      return;
-    }
-  }
-  item_f32<NB, ADD>(sh, it, D, Kp);
 }
 
 // ------------------------------------------------- BF16 split precision --
@@ -745,8 +639,8 @@ __device__ __forceinline__ bf8v neg_bf8(bf8v x) {
 // fragment order, B operands from LDS.  Two passes keep few B operands
 // live: first the A lo parts against the B hi parts, then the A hi parts
 // against both B parts.
-template <int NB>
-__device__ __forceinline__ void mfma_bf16x3(f16v (&ar)[NB / 32], f16v (&ai)[NB / 32],
+template <int NB, int NTU = NB / 32>  // NTU: column tiles used (staged columns 0 .. 32 NTU)
+__device__ __forceinline__ void mfma_bf16x3(f16v (&ar)[NTU], f16v (&ai)[NTU],
                                             const uint16_t* __restrict__ A, int64_t per,
                                             const BF16Shared<NB>& sh, int buf, int s, int Kp,
                                             int wave, int lane) {
@@ -760,7 +654,7 @@ __device__ __forceinline__ void mfma_bf16x3(f16v (&ar)[NB / 32], f16v (&ai)[NB /
   __builtin_amdgcn_sched_barrier(0);
   {
 #pragma unroll
-    for (int cs = 0; cs < NB / 32; ++cs) {
+    for (int cs = 0; cs < NTU; ++cs) {
       const int col = 32 * cs + lane % 32;
       const bf8v brh = lds_bf8(&sh.B[buf][0][col][kq]);
       const bf8v bih = lds_bf8(&sh.B[buf][2][col][kq]);
@@ -772,7 +666,7 @@ __device__ __forceinline__ void mfma_bf16x3(f16v (&ar)[NB / 32], f16v (&ai)[NB /
     }
   }
 #pragma unroll
-  for (int cs = 0; cs < NB / 32; ++cs) {
+  for (int cs = 0; cs < NTU; ++cs) {
     const int col = 32 * cs + lane % 32;
     const bf8v brh = lds_bf8(&sh.B[buf][0][col][kq]);
     const bf8v brl = lds_bf8(&sh.B[buf][1][col][kq]);
@@ -862,6 +756,136 @@ __device__ __forceinline__ void item_bf16(BF16Shared<NB>& sh, const M2LItem& it,
     if (more) store_cols_bf16<NB>(sh, cur ^ 1, nxt);
     __syncthreads();
   }
+}
+
+// ------------------------------------------------ compacted columns --
+// Compacted item (FP32 or BF16 split products, NB = 64).  One pipeline
+// step = one (offset, pass, k slab); an offset's pass count is known once
+// its columns are compacted, which happens one offset ahead
+// (double-buffered column lists).  Staging and products are those of the
+// precision's plain item, on column tile 0 only.
+template <bool BF16, class SH>
+__device__ __forceinline__ void item_compact(SH& sh, const M2LItem& it, const M2LDesc& D,
+                                             int Kp) {
+  constexpr int KS = 16;  // k per slab in both precisions
+  static_assert(F32Traits::KS == KS && kBKS == KS, "one slab size");
+  const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+  const bool rows_here = 32 * wave < Kp;
+  load_targets(sh.S, it, D);
+  __syncthreads();
+  double2* out = static_cast<double2*>(D.out);
+  f16v tor[2], toi[2];
+  zero(tor);
+  zero(toi);
+  const int nv = it.vo_count;
+  if (nv == 0) {  // no source box: the result is zero
+    if (rows_here && it.first)
+      flush_rows32<64>(tor, toi, sh.S, out, D.nd, it.c, Kp, wave, lane, true);
+    return;
+  }
+  const float* mom = static_cast<const float*>(D.mom);
+  const int64_t per = int64_t(Kp) * Kp;
+  const int ns = Kp / KS;  // k slabs per pass (>= 2)
+  auto passes = [&](int b) {
+    const int n = __builtin_amdgcn_readfirstlane(sh.S.nval[b]);
+    return std::max(1, (n + 31) / 32);
+  };
+  auto stage = [&](int buf, float4 val) {  // columns 0 .. 31 of a slab
+    if (threadIdx.x < 256) {
+      if constexpr (BF16)
+        store_cols_bf16<64>(sh, buf, val);
+      else
+        store_cols<F32Traits, 64>(sh, buf, val);
+    }
+  };
+  int4 od_cur = offset_of(D, it.vo_begin);
+  int4 od_next = od_cur;
+  source_columns_compact(sh.S, 0, D, od_cur, it.c, Kp);
+  __syncthreads();
+  int np = passes(0);
+  stage(0, load_cols_compact(sh.S, 0, 0, mom, 0));
+  __syncthreads();
+  bool first = it.first != 0;
+  f16v acr[1], aci[1];
+  int v = 0, p = 0, s = 0, cur = 0;
+  for (;;) {
+    if (s == 0 && p == 0 && v + 1 < nv) {  // compact the next offset's columns
+      od_next = offset_of(D, it.vo_begin + v + 1);
+      source_columns_compact(sh.S, (v + 1) & 1, D, od_next, it.c, Kp);
+    }
+    int v2 = v, p2 = p, s2 = s + 1;
+    if (s2 == ns) {
+      s2 = 0;
+      if (++p2 == np) {
+        p2 = 0;
+        ++v2;
+      }
+    }
+    const bool more = v2 < nv;
+    float4 nxt{};
+    if (more) nxt = load_cols_compact(sh.S, v2 & 1, 32 * p2, mom, s2 * KS);
+    if (rows_here) {
+      if (s == 0) {
+        zero(acr);
+        zero(aci);
+      }
+      if constexpr (BF16) {
+        const uint16_t* bank = static_cast<const uint16_t*>(D.bank);
+        mfma_bf16x3<64, 1>(acr, aci, bank + od_cur.w * 4 * per, per, sh, cur, s, Kp, wave,
+                           lane);
+      } else {
+        const float* bank = static_cast<const float*>(D.bank);
+        float a[2][8];
+        load_a32(a, bank + od_cur.w * 2 * per, per, s * KS, Kp, wave, lane);
+        __builtin_amdgcn_sched_barrier(0);
+        mfma32_tile(acr[0], aci[0], a, sh, cur, lane);
+      }
+      if (s == ns - 1) {
+        scatter_add(tor, toi, acr[0], aci[0], sh.S, v & 1, 32 * p, lane);
+        if (v2 != v && ((v + 1) % kFlush == 0 || !more)) {
+          flush_rows32<64>(tor, toi, sh.S, out, D.nd, it.c, Kp, wave, lane, first);
+          first = false;
+          zero(tor);
+          zero(toi);
+        }
+      }
+    }
+    if (more) stage(cur ^ 1, nxt);
+    __syncthreads();
+    if (!more) break;
+    if (v2 != v) {
+      od_cur = od_next;
+      np = passes(v2 & 1);
+    }
+    v = v2;
+    p = p2;
+    s = s2;
+    cur ^= 1;
+  }
+}
+
+// FP32 and BF16 items: compacted where the level asks for it (NB = 64).
+template <int NB, bool ADD>
+__device__ __forceinline__ void item_f32k(F32Shared<NB>& sh, const M2LItem& it,
+                                          const M2LDesc& D, int Kp) {
+  if constexpr (NB == 64) {
+    if (D.compact) {
+      item_compact<false>(sh, it, D, Kp);
+      return;
+    }
+  }
+  item_f32<NB, ADD>(sh, it, D, Kp);
+}
+template <int NB, bool ADD>
+__device__ __forceinline__ void item_bf16k(BF16Shared<NB>& sh, const M2LItem& it,
+                                           const M2LDesc& D, int Kp) {
+  if constexpr (NB == 64) {
+    if (D.compact) {
+      item_compact<true>(sh, it, D, Kp);
+      return;
+    }
+  }
+  item_bf16<NB, ADD>(sh, it, D, Kp);
 }
 
 // ------------------------------------------------------------ launches --

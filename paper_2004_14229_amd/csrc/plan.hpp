@@ -262,9 +262,11 @@ int m2l_threads(int Kp);
 inline bool p2p_queue_supported(int prec, int Kp) {
   return prec != FDM_PREC_FP64 && Kp <= 256;
 }
-// Compacted coupling items exist in the FP32 kernel with 64 targets per
-// item.
-inline bool compact_supported(int prec, int nb) { return prec == FDM_PREC_FP32 && nb == 64; }
+// Compacted coupling items exist in the FP32 and BF16 split kernels with 64
+// targets per item.
+inline bool compact_supported(int prec, int nb) {
+  return (prec == FDM_PREC_FP32 || prec == FDM_PREC_BF16X3) && nb == 64;
+}
 // Matrix-core columns of one coupling step under cfg (zero padding included).
 int64_t issued_columns(const Plan& P, const TuneConfig& cfg);
 int64_t m2l_resident_groups(int prec, int nb, int Kp, bool parts);

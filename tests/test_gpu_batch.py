@@ -89,45 +89,48 @@ def test_streamed_bank_matches_oracle(precision, tol):
     assert rel(y_res, yo) <= tol
 
 
+@pytest.mark.parametrize("precision,tol", [("fp32", TOL_FP32), ("bf16x3", 2e-5)])
 @pytest.mark.parametrize("seed,nt,ns,kappa,levels,m,clustered", [
     (311, 700, 650, 45.0, 4, 3, False), (312, 3000, 2600, 60.0, 5, 3, True),
     (313, 1500, 1400, 30.0, 4, 5, False), (314, 90, 2000, 20.0, 4, 4, False)])
-def test_compacted_columns_match_plain(seed, nt, ns, kappa, levels, m, clustered):
-    """Mixed FP32 with compacted coupling columns (on every level, and on
-    the levels the automatic rule picks) against the oracle and against the
-    plain FP32 items.  Compaction only drops zero columns: every target's
-    per-offset sums, FP32 totals and flush points are unchanged, so the
-    results agree with the plain items bit for bit."""
+def test_compacted_columns_match_plain(seed, nt, ns, kappa, levels, m, clustered,
+                                       precision, tol):
+    """Mixed FP32 and BF16 split products with compacted coupling columns
+    (on every level, and on the levels the automatic rule picks) against
+    the oracle and against the plain items.  Compaction only drops zero
+    columns: every target's per-offset sums, FP32 totals and flush points
+    are unchanged, so the results agree with the plain items bit for bit."""
     if clustered:
         P = W.clustered_problem(seed, nt, ns, kappa, levels, m)
     else:
         P = W.random_problem(seed, nt, ns, kappa, levels, m)
     yo = oracle_y(P)
     base = dict(nb=64, persistent=1, lpt=1, p2p_in_queue=0)
-    y0, st0 = plan_y(P, "fp32", tune=dict(base, compact=0))
-    y1, st1 = plan_y(P, "fp32", tune=dict(base, compact=1))
-    y2, st2 = plan_y(P, "fp32", tune=dict(base, compact=2))
+    y0, st0 = plan_y(P, precision, tune=dict(base, compact=0))
+    y1, st1 = plan_y(P, precision, tune=dict(base, compact=1))
+    y2, st2 = plan_y(P, precision, tune=dict(base, compact=2))
     for y in (y0, y1, y2):
-        assert rel(y, yo) <= TOL_FP32
+        assert rel(y, yo) <= tol
     assert np.array_equal(y0, y2) and np.array_equal(y0, y1)
     assert st2["m2l_columns"] <= st1["m2l_columns"] <= st0["m2l_columns"]
     assert st1["n_couplings"] == st0["n_couplings"]
 
 
-def test_compacted_columns_streamed_and_grid():
+@pytest.mark.parametrize("precision,tol", [("fp32", TOL_FP32), ("bf16x3", 2e-5)])
+def test_compacted_columns_streamed_and_grid(precision, tol):
     """Compacted items split over streamed-bank launches (first part
     stores, later parts add), in grid and persistent launches."""
     P = W.random_problem(315, 1200, 1100, 50.0, 4, 4)
     yo = oracle_y(P)
     K = (P.m + 1) ** 3
     Kp = (K + 31) // 32 * 32
-    mat = Kp * Kp * 8
-    y_ref, _ = plan_y(P, "fp32", tune=dict(nb=64, compact=0))
+    mat = Kp * Kp * 8  # FP32: 2 planes x 4 bytes; BF16: 4 planes x 2 bytes
+    y_ref, _ = plan_y(P, precision, tune=dict(nb=64, compact=0))
     for pers in (1, 0):
         for budget in (0, 3 * mat):
-            y, _ = plan_y(P, "fp32", bank_budget=budget,
+            y, _ = plan_y(P, precision, bank_budget=budget,
                           tune=dict(nb=64, persistent=pers, compact=2))
-            assert rel(y, yo) <= TOL_FP32, (pers, budget)
+            assert rel(y, yo) <= tol, (pers, budget)
             if budget == 0:
                 assert np.array_equal(y, y_ref), pers
 
