@@ -97,15 +97,14 @@ __global__ void __launch_bounds__(256) k_bank(const int32_t* __restrict__ info,
 // Candidate offsets of an item whose source box is non-empty for at least
 // one target of the block: count (pass 0) or write (pass 1) them.  One wave
 // per item (<= 64 targets); pass 1 also counts the admissible blocks per
-// offset and, per level, the 32-column tiles of the compacted form.
+// offset and, per item, the 32-column tiles of the compacted form.
 __global__ void __launch_bounds__(64) k_valid_offsets(
     const M2LItem* __restrict__ items, int64_t n_items, const int32_t* __restrict__ cand_begin,
     const int32_t* __restrict__ cand_count, const int32_t* __restrict__ cand,
     const M2LDesc* __restrict__ descs, const int32_t* __restrict__ tgt_list,
     const int4* __restrict__ offtab, int pass, int32_t* __restrict__ counts,
     const int32_t* __restrict__ out_begin, int32_t* __restrict__ out,
-    unsigned long long* __restrict__ blocks_per_off,
-    unsigned long long* __restrict__ tiles_per_level) {
+    unsigned long long* __restrict__ blocks_per_off, int32_t* __restrict__ tiles) {
   const int lane = threadIdx.x;
   for (int64_t ii = blockIdx.x; ii < n_items; ii += gridDim.x) {
     const M2LItem it = items[ii];
@@ -116,7 +115,7 @@ __global__ void __launch_bounds__(64) k_valid_offsets(
     if (t >= 0) demorton3(D.keyT[t], D.level, ix, iy, iz);
     const int32_t* cl = cand + cand_begin[ii];
     const int nc = cand_count[ii];
-    int n = 0;
+    int n = 0, nt = 0;
     for (int q = 0; q < nc; ++q) {
       const int4 od = offtab[cl[q]];
       bool ok = false;
@@ -129,14 +128,14 @@ __global__ void __launch_bounds__(64) k_valid_offsets(
       if (mask) {
         if (pass == 1 && lane == 0) {
           out[out_begin[ii] + n] = cl[q];
-          const int nsrc = __popcll(mask);
-          atomicAdd(&blocks_per_off[cl[q]], (unsigned long long)nsrc);
-          atomicAdd(&tiles_per_level[D.level], (unsigned long long)((nsrc + 31) / 32));
+          atomicAdd(&blocks_per_off[cl[q]], (unsigned long long)__popcll(mask));
         }
+        nt += (__popcll(mask) + 31) / 32;
         ++n;
       }
     }
     if (pass == 0 && lane == 0) counts[ii] = n;
+    if (pass == 1 && lane == 0) tiles[ii] = nt;
   }
 }
 
@@ -184,13 +183,13 @@ void launch_valid_offsets(const M2LItem* items, int64_t n_items, const int32_t* 
                           const int32_t* cand_count, const int32_t* cand, const M2LDesc* descs,
                           const int32_t* tgt_list, const int4* offtab, int pass,
                           int32_t* counts, const int32_t* out_begin, int32_t* out,
-                          unsigned long long* blocks_per_off,
-                          unsigned long long* tiles_per_level, hipStream_t s) {
+                          unsigned long long* blocks_per_off, int32_t* tiles,
+                          hipStream_t s) {
   if (n_items == 0) return;
   const unsigned G = static_cast<unsigned>(std::min<int64_t>(n_items, 1 << 16));
   k_valid_offsets<<<G, 64, 0, s>>>(items, n_items, cand_begin, cand_count, cand, descs,
                                    tgt_list, offtab, pass, counts, out_begin, out,
-                                   blocks_per_off, tiles_per_level);
+                                   blocks_per_off, tiles);
   FDM_LAUNCH("k_valid_offsets");
 }
 

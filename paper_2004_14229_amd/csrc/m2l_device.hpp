@@ -864,12 +864,12 @@ __device__ __forceinline__ void item_compact(SH& sh, const M2LItem& it, const M2
   }
 }
 
-// FP32 and BF16 items: compacted where the level asks for it (NB = 64).
+// FP32 and BF16 items: compacted where the item asks for it (NB = 64).
 template <int NB, bool ADD>
 __device__ __forceinline__ void item_f32k(F32Shared<NB>& sh, const M2LItem& it,
                                           const M2LDesc& D, int Kp) {
   if constexpr (NB == 64) {
-    if (D.compact) {
+    if (it.compact) {
       item_compact<false>(sh, it, D, Kp);
       return;
     }
@@ -880,7 +880,7 @@ template <int NB, bool ADD>
 __device__ __forceinline__ void item_bf16k(BF16Shared<NB>& sh, const M2LItem& it,
                                            const M2LDesc& D, int Kp) {
   if constexpr (NB == 64) {
-    if (D.compact) {
+    if (it.compact) {
       item_compact<true>(sh, it, D, Kp);
       return;
     }

@@ -22,32 +22,30 @@ BankLevel bank_level(const Plan& P, int l) {
   return BankLevel{P.L[l].dirvec.get(), P.L[l].h, P.kappa, l, P.L[l].nd};
 }
 
-// Whether level l's FP32 items take compacted columns under `cfg`: mode 1
-// when the compacted tiles (32 columns each) save at least a fifth of the
-// plain items' columns (nb per offset).
-bool level_compact(const Plan& P, int l, const TuneConfig& cfg) {
-  if (!cfg.compact || !compact_supported(P.prec, cfg.nb) || P.tune.nb != cfg.nb)
-    return false;
+// Whether base item i runs with compacted columns under `cfg`: mode 1 when
+// its compacted tiles (32 columns each) save at least a fifth of the plain
+// item's columns (nb per offset) -- items at sparse levels and at the
+// domain boundary.
+bool item_compact(const Plan& P, size_t i, const TuneConfig& cfg) {
+  if (!cfg.compact || !compact_supported(P.prec, cfg.nb) || P.tune.nb != cfg.nb) return false;
   if (cfg.compact == 2) return true;
-  if (l >= static_cast<int>(P.level_pairs.size())) return false;
-  return 5 * 32 * P.level_tiles[l] <= 4 * int64_t(cfg.nb) * P.level_pairs[l];
+  return 5 * 32 * int64_t(P.item_tiles[i]) <= 4 * int64_t(cfg.nb) * P.base_items[i].vo_count;
 }
 
 }  // namespace
 
 int64_t issued_columns(const Plan& P, const TuneConfig& cfg) {
   int64_t n = 0;
-  for (size_t l = 0; l < P.level_pairs.size(); ++l)
-    n += level_compact(P, static_cast<int>(l), cfg) ? 32 * P.level_tiles[l]
-                                                     : int64_t(P.tune.nb) * P.level_pairs[l];
+  for (size_t i = 0; i < P.base_items.size(); ++i)
+    n += item_compact(P, i, cfg) ? 32 * int64_t(P.item_tiles[i])
+                                 : int64_t(P.tune.nb) * P.base_items[i].vo_count;
   return n;
 }
 
 namespace {
 
 // `bank` holds bank id bank_id0 as its first matrix.
-M2LDesc level_desc(const Plan& P, int l, const void* bank, int64_t bank_id0,
-                   const TuneConfig& cfg) {
+M2LDesc level_desc(const Plan& P, int l, const void* bank, int64_t bank_id0) {
   const LevelData& Ld = P.L[l];
   M2LDesc d{};
   d.gridS = P.S.grid[l].get();
@@ -63,7 +61,6 @@ M2LDesc level_desc(const Plan& P, int l, const void* bank, int64_t bank_id0,
                                          static_cast<uintptr_t>(bank_id0 * mb));
   d.nd = Ld.nd;
   d.level = l;
-  d.compact = level_compact(P, l, cfg) ? 1 : 0;
   return d;
 }
 
@@ -76,6 +73,7 @@ const void* resident_bank(const Plan& P) {
 // Host image of one launch while a schedule is assembled.
 struct LaunchBuilder {
   std::vector<M2LItem> items, p2p_items;
+  std::vector<double> weight;  // per coupling item: MFMA column tiles it issues
   std::vector<M2LDesc> descs;
   std::vector<P2PDesc> p2p;
   std::vector<int32_t> gen_info;
@@ -91,13 +89,14 @@ void add_source(LaunchBuilder& B, const Plan& P, int64_t b0, int64_t b1, const v
   std::vector<int32_t> desc_of(P.levels + 1, -1);
   for (int l = std::max(P.l_min, 0); l <= P.levels; ++l) {
     desc_of[l] = static_cast<int32_t>(B.descs.size());
-    B.descs.push_back(level_desc(P, l, bank, b0 - slot0, cfg));
+    B.descs.push_back(level_desc(P, l, bank, b0 - slot0));
   }
   const auto& vo = P.valid_off_h;
   for (size_t i = 0; i < P.base_items.size(); ++i) {
     const M2LItem& it = P.base_items[i];
     M2LItem o = it;
     o.desc = desc_of[it.desc];
+    o.compact = item_compact(P, i, cfg) ? 1 : 0;
     if (it.vo_count == 0) {  // no source box: stored as zero once
       if (emitted[i]) continue;
       o.first = 1;
@@ -112,6 +111,11 @@ void add_source(LaunchBuilder& B, const Plan& P, int64_t b0, int64_t b1, const v
     }
     emitted[i] = 1;
     B.items.push_back(o);
+    // plain: nb / 32 tiles per offset; compacted: the item's tiles, shared
+    // over its parts in proportion to their offsets
+    B.weight.push_back(o.compact ? double(P.item_tiles[i]) * o.vo_count /
+                                       std::max(it.vo_count, 1)
+                                 : double(o.vo_count) * cfg.nb / 32);
   }
 }
 
@@ -145,10 +149,15 @@ void add_near_field(LaunchBuilder& B, Plan& P, int chunk) {
 
 M2LLaunch upload(LaunchBuilder& B, const TuneConfig& cfg, int prec, int Kp, void* ws,
                  hipStream_t s) {
-  if (cfg.lpt)  // heaviest items first (longest-processing-time order)
-    std::stable_sort(B.items.begin(), B.items.end(), [](const M2LItem& a, const M2LItem& b) {
-      return a.vo_count > b.vo_count;
-    });
+  if (cfg.lpt) {  // heaviest items first (longest-processing-time order)
+    std::vector<size_t> order(B.items.size());
+    for (size_t i = 0; i < order.size(); ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(),
+                     [&](size_t a, size_t b) { return B.weight[a] > B.weight[b]; });
+    std::vector<M2LItem> sorted(order.size());
+    for (size_t i = 0; i < order.size(); ++i) sorted[i] = B.items[order[i]];
+    B.items.swap(sorted);
+  }
   M2LLaunch L;
   L.n_items = static_cast<int64_t>(B.items.size() + B.p2p_items.size());
   L.n_p2p_items = static_cast<int64_t>(B.p2p_items.size());
@@ -365,17 +374,14 @@ void build_m2l_work(Plan& P, hipStream_t s) {
   P.valid_off_h.clear();
   P.sched.clear();
   P.sched_ready = false;
-  P.level_pairs.clear();
-  P.level_tiles.clear();
+  P.item_tiles.clear();
   if (n_items == 0) {
     P.valid_off.alloc(1, &P.tally);
     FDM_HIP(hipStreamSynchronize(s));
     return;
   }
   std::vector<M2LDesc> descs(p + 1);
-  TuneConfig plain;
-  plain.compact = 0;
-  for (int l = 0; l <= p; ++l) descs[l] = level_desc(P, l, nullptr, 0, plain);
+  for (int l = 0; l <= p; ++l) descs[l] = level_desc(P, l, nullptr, 0);
   DevBuf<M2LDesc> d_descs;
   to_device(d_descs, descs, s, nullptr);
   DevBuf<M2LItem> d_items;
@@ -384,9 +390,9 @@ void build_m2l_work(Plan& P, hipStream_t s) {
   to_device(d_cand, cand, s, nullptr);
   to_device(d_cb, cand_begin_per_item, s, nullptr);
   to_device(d_cc, cand_count_per_item, s, nullptr);
-  DevBuf<unsigned long long> d_bpo(std::max<int64_t>(P.n_bank, 1)), d_tiles(p + 1);
+  DevBuf<unsigned long long> d_bpo(std::max<int64_t>(P.n_bank, 1));
+  DevBuf<int32_t> d_tiles(n_items);
   FDM_HIP(hipMemsetAsync(d_bpo.get(), 0, d_bpo.bytes(), s));
-  FDM_HIP(hipMemsetAsync(d_tiles.get(), 0, d_tiles.bytes(), s));
   launch_valid_offsets(d_items.get(), n_items, d_cb.get(), d_cc.get(), d_cand.get(),
                        d_descs.get(), P.tgt_list.get(), P.offtab.get(), 0, d_counts.get(),
                        nullptr, nullptr, nullptr, nullptr, s);
@@ -404,10 +410,7 @@ void build_m2l_work(Plan& P, hipStream_t s) {
                        d_descs.get(), P.tgt_list.get(), P.offtab.get(), 1, nullptr,
                        d_begin.get(), P.valid_off.get(), d_bpo.get(), d_tiles.get(), s);
   std::vector<unsigned long long> bpo = to_host(d_bpo.get(), P.n_bank, s);
-  const std::vector<unsigned long long> tiles = to_host(d_tiles.get(), p + 1, s);
-  P.level_tiles.assign(tiles.begin(), tiles.end());
-  P.level_pairs.assign(p + 1, 0);
-  for (int64_t i = 0; i < n_items; ++i) P.level_pairs[items[i].desc] += counts[i];
+  P.item_tiles = to_host(d_tiles.get(), n_items, s);
   P.bank_work.assign(bpo.begin(), bpo.end());
   P.valid_off_h = to_host(P.valid_off.get(), total, s);
   for (int64_t i = 0; i < n_items; ++i) {

@@ -59,7 +59,6 @@ struct M2LDesc {
   // range of ids this address lies before the workspace (never read there)
   const void* bank;
   int32_t nd, level;
-  int32_t compact;  // FP32 items of this level use compacted columns
 };
 
 // Descriptor of one plan's near field in a queued launch.
@@ -80,10 +79,11 @@ struct P2PDesc {
 // tgt_list[tgt_begin .. +ntgt), direction c, offsets valid_off[vo_begin ..
 // +vo_count); `first` = 1 for the first part of a (target block, c), whose
 // result is stored, 0 for later parts (streamed banks), which add to it.
-// desc < 0: near-field item of P2P descriptor -desc-1 for target points
-// tgt_begin .. +ntgt (tree order).
+// `compact` = 1: the coupling item runs with compacted columns (FP32 and
+// BF16 kernels, 64 targets per item).  desc < 0: near-field item of P2P
+// descriptor -desc-1 for target points tgt_begin .. +ntgt (tree order).
 struct M2LItem {
-  int32_t desc, c, tgt_begin, ntgt, vo_begin, vo_count, first, pad;
+  int32_t desc, c, tgt_begin, ntgt, vo_begin, vo_count, first, compact;
 };
 
 // One matrix to generate into a streamed bank: level descriptor index,
@@ -157,9 +157,8 @@ struct Plan {
   DevBuf<uint8_t> bank_ws;
   std::vector<int32_t> bank_info;  // per bank id: level, ox, oy, oz, c
   std::vector<int64_t> bank_work;  // per bank id: admissible blocks using it
-  // per level: (item, offset) pairs of the work lists, and the 32-column
-  // tiles they take when compacted
-  std::vector<int64_t> level_pairs, level_tiles;
+  // per base item: the 32-column tiles its offsets take when compacted
+  std::vector<int32_t> item_tiles;
 
   // coupling work (per plan; a batch builds its own launches from it)
   TuneConfig tune;
@@ -254,8 +253,8 @@ void launch_valid_offsets(const M2LItem* items, int64_t n_items, const int32_t* 
                           const int32_t* cand_count, const int32_t* cand, const M2LDesc* descs,
                           const int32_t* tgt_list, const int4* offtab, int pass,
                           int32_t* counts, const int32_t* out_begin, int32_t* out,
-                          unsigned long long* blocks_per_off,
-                          unsigned long long* tiles_per_level, hipStream_t s);
+                          unsigned long long* blocks_per_off, int32_t* tiles,
+                          hipStream_t s);
 int m2l_threads(int Kp);
 // Near-field items can share the coupling launch (FP32 / BF16, Kp <= 256);
 // otherwise the near field runs as its own launch whatever the tune says.
