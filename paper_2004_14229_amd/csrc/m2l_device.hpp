@@ -339,7 +339,9 @@ __device__ __forceinline__ void item_f64(F64Shared<NB>& sh, const M2LItem& it,
     const double* mom = static_cast<const double*>(D.mom);
     const double* bank = static_cast<const double*>(D.bank);
     const int64_t per = int64_t(Kp) * Kp;
-    const int ns = Kp / Tr::KS;  // k slabs per offset (>= 2)
+    // k slabs per offset: those holding any of the K nodes (slabs of only
+    // zero padding are skipped), at least 2 for the pipeline
+    const int ns = std::max(2, (D.K + Tr::KS - 1) / Tr::KS);
     const int total = nv * ns;
     int4 od_cur = offset_of(D, it.vo_begin);
     int4 od_next = od_cur;

@@ -61,6 +61,7 @@ M2LDesc level_desc(const Plan& P, int l, const void* bank, int64_t bank_id0) {
                                          static_cast<uintptr_t>(bank_id0 * mb));
   d.nd = Ld.nd;
   d.level = l;
+  d.K = P.ip.K;
   return d;
 }
 

@@ -59,6 +59,7 @@ struct M2LDesc {
   // range of ids this address lies before the workspace (never read there)
   const void* bank;
   int32_t nd, level;
+  int32_t K;  // interpolation nodes per box, (m+1)^3 <= Kp: rows / k beyond are padding
 };
 
 // Descriptor of one plan's near field in a queued launch.
