@@ -85,6 +85,44 @@ def time_plan(plan, v, y, steps, warmup, tag=""):
     return wall, phases
 
 
+def plan_shape(plan, levels: int, l_min: int) -> dict:
+    """Boxes per level of both trees and directions per level (plan export)."""
+    nbS = [int(plan.export(f"keys_S{l}").shape[0]) for l in range(levels + 1)]
+    nbT = [int(plan.export(f"keys_T{l}").shape[0]) for l in range(levels + 1)]
+    nd = [int(plan.export(f"dirs_{l}").shape[0]) if l >= l_min else 1 for l in range(levels + 1)]
+    return {"nbS": nbS, "nbT": nbT, "nd": nd, "levels": levels, "l_min": l_min}
+
+
+def hbm_phases(shape: dict, phase_ms: dict, K: int, nT: int, nS: int, mixed: bool) -> dict:
+    """Compulsory HBM bytes of the transfer phases (each array read or written
+    once; 16-byte complex FP64 vectors of Kp entries per (box, direction),
+    plus the 8-byte FP32 copy of the moments in the mixed precisions) and the
+    rate they imply at the measured phase times, against 8 TB/s."""
+    Kp = (K + 31) // 32 * 32
+    p, lm = shape["levels"], shape["l_min"]
+    nbS, nbT, nd = shape["nbS"], shape["nbT"], shape["nd"]
+    vec = Kp * 16
+    mom_w = vec + (Kp * 8 if mixed else 0)
+    b = {}
+    # permute in + S2M: v read and written, points and tree-order v read, leaf moments written
+    b["s2m"] = 16 * nS * 2 + (24 + 16) * nS + nbS[p] * nd[p] * mom_w if lm <= p else 0
+    # M2M: child moments read, parent moments written
+    b["m2m"] = sum(nbS[l + 1] * nd[l + 1] * vec + nbS[l] * nd[l] * mom_w for l in range(lm, p))
+    # L2L: parent locals read, child locals read and written (completed in place)
+    b["l2l"] = sum(nbT[l] * nd[l] * vec + nbT[l + 1] * nd[l + 1] * 2 * vec for l in range(lm, p))
+    # L2T: leaf locals and points read, y read and written
+    b["l2t"] = (nbT[p] * nd[p] * vec if lm <= p else 0) + 24 * nT + 32 * nT
+    # near field: target and source points, tree-order v read, y written
+    b["near"] = 24 * nT + 40 * nS + 16 * nT
+    out = {}
+    for k, v in b.items():
+        ms = phase_ms.get(k, 0.0)
+        rate = v / (ms * 1e-3) / 1e9 if ms > 0.01 else None  # empty phase: no rate
+        out[k] = {"bytes": v, "ms": ms, "GB/s": rate,
+                  "frac_of_8TB/s": (rate / 8000.0) if rate else None}
+    return out
+
+
 def kernel_source_sha(kernel: str) -> str:
     """SHA-256 of the sources that define a coupling kernel (shared device
     code + its precision's file)."""
@@ -272,6 +310,7 @@ def main():
     stats = plan.stats()
     print(f"[bench] {args.precision} plan built in {setup_s:.1f} s: N_C={stats['n_couplings']} "
           f"N_SC={stats['n_stored_couplings']}", file=sys.stderr, flush=True)
+    shape = plan_shape(plan, P.levels, stats["l_min"])
     wall, phases = time_plan(plan, v, y, args.steps, args.warmup, args.precision)
     y_mixed = y.cpu().numpy()
     plan.close()
@@ -303,6 +342,8 @@ def main():
                        "traffic": traffic_for(M2L_KERNEL[args.precision], args.workload, flops),
                        "flops_per_launch": flops, "avg_launch_ms": m2l_ms}
     out["phase_ms"] = {k: float(np.mean([p[k] for p in phases])) for k in phases[0]}
+    out["hbm_phases"] = hbm_phases(shape, out["phase_ms"], (P.m + 1) ** 3, P.points_T.shape[0],
+                                   P.points_S.shape[0], args.precision != "fp64")
     out["setup_s"] = setup_s
     out["plan"] = {k: stats[k] for k in ("n_couplings", "n_stored_couplings", "m2l_columns",
                                          "near_entries", "device_bytes", "l_hf", "l_min")}
