@@ -6,9 +6,14 @@
 // The near-field blocks of a leaf are the same-level boxes at the leaf
 // level's inadmissible offsets (independent of the target octant: an
 // inadmissible pair always has an inadmissible, hence refined, parent).
-// One thread per target point in tree order, so neighbouring threads share
-// a leaf and read the same source boxes (served from L2).  The near field is
-// stored into y (it runs before the far field, which is added).
+// Small leaves (a few points each): one thread per target point in tree
+// order, so neighbouring threads share a leaf and read the same source boxes
+// (served from L2).  Large leaves (on average >= kLeafTile / 8 points): one
+// workgroup per target leaf, each near source box staged through LDS in
+// tiles that every thread of the leaf then reads (broadcast, no bank
+// conflicts); both sum over the same offsets and sources in the same order,
+// so they give the same bits.  The near field is stored into y (it runs
+// before the far field, which is added).
 #include "nearfield.hpp"
 
 namespace fdm {
@@ -20,6 +25,58 @@ __global__ void __launch_bounds__(256) k_p2p(P2PDesc d, int64_t nT) {
   const int64_t j = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
   if (j >= nT) return;
   reinterpret_cast<double2*>(d.y)[j] = near_value(d, j);
+}
+
+// Workgroup per target leaf (grid-stride), its points kLeafTile at a time.
+constexpr int kLeafTile = 256;
+__global__ void __launch_bounds__(kLeafTile) k_p2p_leaf(P2PDesc d,
+                                                        const int32_t* __restrict__ startT,
+                                                        const int32_t* __restrict__ countT,
+                                                        int64_t n_leaf) {
+  __shared__ double sx[kLeafTile], sy[kLeafTile], sz[kLeafTile];
+  __shared__ double2 sv[kLeafTile];
+  const double2* v = reinterpret_cast<const double2*>(d.v);
+  const int lim = 1 << d.level;
+  for (int64_t b = blockIdx.x; b < n_leaf; b += gridDim.x) {
+    int ix, iy, iz;
+    demorton3(d.keyT[b], d.level, ix, iy, iz);
+    const int t0 = startT[b], tn = countT[b];
+    for (int tb = 0; tb < tn; tb += kLeafTile) {
+      const int j = t0 + tb + threadIdx.x;
+      const bool act = tb + static_cast<int>(threadIdx.x) < tn;
+      double px = 0.0, py = 0.0, pz = 0.0;
+      if (act) {
+        px = d.xt[j];
+        py = d.yt[j];
+        pz = d.zt[j];
+      }
+      double ar = 0.0, ai = 0.0;
+      for (int o = 0; o < d.n_off; ++o) {
+        const int sxb = ix - d.near_off[3 * o], syb = iy - d.near_off[3 * o + 1],
+                  szb = iz - d.near_off[3 * o + 2];
+        if (sxb < 0 || syb < 0 || szb < 0 || sxb >= lim || syb >= lim || szb >= lim) continue;
+        const int32_t sb = d.gridS[morton3(sxb, syb, szb, d.level)];
+        if (sb < 0) continue;
+        const int k0 = d.startS[sb], kn = d.countS[sb];
+        for (int kb = 0; kb < kn; kb += kLeafTile) {
+          __syncthreads();  // the previous tile has been read
+          const int k = kb + static_cast<int>(threadIdx.x);
+          if (k < kn) {
+            sx[threadIdx.x] = d.xs[k0 + k];
+            sy[threadIdx.x] = d.ys[k0 + k];
+            sz[threadIdx.x] = d.zs[k0 + k];
+            sv[threadIdx.x] = v[k0 + k];
+          }
+          __syncthreads();
+          const int nk = kn - kb < kLeafTile ? kn - kb : kLeafTile;
+          if (act)
+            for (int q = 0; q < nk; ++q)
+              kernel_add(px, py, pz, sx[q], sy[q], sz[q], sv[q], d.kappa, ar, ai);
+        }
+      }
+      if (act) reinterpret_cast<double2*>(d.y)[j] = make_double2(ar, ai);
+    }
+  }
 }
 
 // Dense product: thread per target, source tiles staged in LDS.
@@ -83,6 +140,15 @@ P2PDesc p2p_desc(const Plan& P) {
 
 void launch_p2p(Plan& P, hipStream_t s) {
   if (P.nT == 0 || P.nS == 0) return;
+  const int p = P.levels;
+  const int64_t n_leaf = P.T.nb[p];
+  if (n_leaf > 0 && P.nT >= int64_t(kLeafTile / 8) * n_leaf) {  // large leaves
+    const unsigned grid = static_cast<unsigned>(std::min<int64_t>(n_leaf, 1 << 20));
+    k_p2p_leaf<<<grid, kLeafTile, 0, s>>>(p2p_desc(P), P.T.start[p].get(), P.T.count[p].get(),
+                                          n_leaf);
+    FDM_LAUNCH("k_p2p_leaf");
+    return;
+  }
   const int B = 256;
   k_p2p<<<static_cast<unsigned>((P.nT + B - 1) / B), B, 0, s>>>(p2p_desc(P), P.nT);
   FDM_LAUNCH("k_p2p");

@@ -108,6 +108,20 @@ def test_fp64_paper_grid_k5():
     assert rel(y, yo) <= TOL_FP64
 
 
+@pytest.mark.parametrize("seed,levels", [(331, 2), (332, 3)])
+def test_fp64_large_uneven_leaves(seed, levels):
+    """Clustered points on a shallow tree: leaves of very different sizes,
+    many above 256 points, so the near field runs one workgroup per target
+    leaf with source tiles staged in LDS (several target chunks and source
+    tiles per leaf)."""
+    P = W.clustered_problem(seed, 6000, 5000, 15.0, levels, 3)
+    y, gp = gpu_matvec(P)
+    counts = gp.export(f"count_T{levels}")
+    assert counts.mean() >= 32 and counts.max() > 256
+    yo = oracle.matvec(oracle_plan(P), P.v)
+    assert rel(y, yo) <= TOL_FP64
+
+
 def test_moments_and_locals_match_oracle():
     """Per-phase parity: the GPU's centre-relative moments / locals equal the
     oracle's absolute-phase ones times exp(+i kappa <m_box, c>)."""
