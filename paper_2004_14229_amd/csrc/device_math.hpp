@@ -8,6 +8,10 @@ namespace fdm {
 
 constexpr int kMaxK = kMaxM1 * kMaxM1 * kMaxM1;  // 729
 constexpr int kPerLane = (kMaxK + 63) / 64;      // coefficients per lane
+// Transfer kernels (M2M, L2L): one 256-thread workgroup per (box, direction)
+// and the coefficients each thread holds.
+constexpr int kXT = 256;
+constexpr int kPerXT = (kMaxK + kXT - 1) / kXT;
 
 __device__ __forceinline__ double2 cmul(double2 a, double2 b) {
   return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);

@@ -26,9 +26,9 @@ __device__ __forceinline__ double2 load_c<float2>(const float2* p, int64_t i) {
   return make_double2(v.x, v.y);
 }
 
-// One workgroup (64 threads) per (child box t' on level l+1, direction c').
+// One workgroup (kXT threads) per (child box t' on level l+1, direction c').
 template <class GT>
-__global__ void __launch_bounds__(64) k_l2l(
+__global__ void __launch_bounds__(kXT) k_l2l(
     const double2* __restrict__ ploc, int nd, const int32_t* __restrict__ pgrid,
     const uint32_t* __restrict__ key1, int64_t nb1, int level, double h1,
     const double* __restrict__ dirvec, const double* __restrict__ dirvec1, int nd1,
@@ -49,11 +49,11 @@ __global__ void __launch_bounds__(64) k_l2l(
     const int32_t par = pgrid[k1 >> 3];
     const int q = k1 & 7;
     const int bq[3] = {(q >> 2) & 1, (q >> 1) & 1, q & 1};
-    double2 acc[kPerLane];
+    double2 acc[kPerXT];
     const int64_t obase = (b * nd1 + cp) * int64_t(Kp);
 #pragma unroll
-    for (int i = 0; i < kPerLane; ++i) {
-      const int k = lane + 64 * i;
+    for (int i = 0; i < kPerXT; ++i) {
+      const int k = lane + kXT * i;
       acc[i] = k < K ? load_c(g_m2l, obase + k) : make_double2(0.0, 0.0);
     }
     for (int c = c_begin; c < c_end; ++c) {
@@ -68,12 +68,12 @@ __global__ void __launch_bounds__(64) k_l2l(
         ph[d][nu] = make_double2(cs, sn);
       }
       const double2* src = ploc + (int64_t(par) * nd + c) * Kp;
-      for (int k = lane; k < K; k += 64) buf[0][k] = src[k];
+      for (int k = lane; k < K; k += kXT) buf[0][k] = src[k];
       __syncthreads();
-      apply_transfer(buf, ip, bq, false, lane, 64);  // buf[1] = E_{t'} g
+      apply_transfer(buf, ip, bq, false, lane, kXT);  // buf[1] = E_{t'} g
 #pragma unroll
-      for (int i = 0; i < kPerLane; ++i) {
-        const int k = lane + 64 * i;
+      for (int i = 0; i < kPerXT; ++i) {
+        const int k = lane + kXT * i;
         if (k < K) {
           const int n3 = k % m1, n2 = (k / m1) % m1, n1 = k / (m1 * m1);
           const double2 f = cmul(cmul(ph[0][n1], ph[1][n2]), ph[2][n3]);
@@ -84,10 +84,10 @@ __global__ void __launch_bounds__(64) k_l2l(
       }
     }
 #pragma unroll
-    for (int i = 0; i < kPerLane + 1; ++i) {
-      const int k = lane + 64 * i;
-      if (k < Kp) loc1[obase + k] = (k < K && i < kPerLane) ? acc[i < kPerLane ? i : 0]
-                                                           : make_double2(0.0, 0.0);
+    for (int i = 0; i < kPerXT + 1; ++i) {
+      const int k = lane + kXT * i;
+      if (k < Kp) loc1[obase + k] = (k < K && i < kPerXT) ? acc[i < kPerXT ? i : 0]
+                                                         : make_double2(0.0, 0.0);
     }
   }
 }
@@ -173,7 +173,7 @@ void launch_l2l(Plan& P, int level, hipStream_t s) {
   const int64_t nb1 = P.T.nb[level + 1];
   if (nb1 == 0) return;
   dim3 grid(static_cast<unsigned>(std::min<int64_t>(nb1, 1 << 20)), L1.nd);
-  k_l2l<double2><<<grid, 64, 0, s>>>(
+  k_l2l<double2><<<grid, kXT, 0, s>>>(
       reinterpret_cast<const double2*>(Lc.loc64.get()), Lc.nd, P.T.grid[level].get(),
       P.T.key[level + 1].get(), nb1, level, L1.h, Lc.dirvec.get(), L1.dirvec.get(),
       L1.nd, P.l_hf, P.kappa, P.ip, reinterpret_cast<const double2*>(L1.loc64.get()),

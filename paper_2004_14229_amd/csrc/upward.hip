@@ -21,17 +21,19 @@ namespace fdm {
 namespace {
 
 // Write one coefficient vector (K values, zero padding up to Kp) in FP64 and,
-// if requested, as the FP32 operand copy.
-__device__ __forceinline__ void store_coeffs(const double2 (&acc)[kPerLane],
+// if requested, as the FP32 operand copy; thread `lane` of T holds
+// coefficients lane + T i.
+template <int T, int NPER>
+__device__ __forceinline__ void store_coeffs(const double2 (&acc)[NPER],
                                              double2* __restrict__ out64,
                                              float2* __restrict__ out32,
                                              int64_t base, int K, int Kp, int lane) {
 #pragma unroll
-  for (int i = 0; i < (kMaxK + 63) / 64 + 1; ++i) {
-    const int k = lane + 64 * i;
+  for (int i = 0; i < (kMaxK + T - 1) / T + 1; ++i) {
+    const int k = lane + T * i;
     if (k < Kp) {
-      const double2 val = (k < K && i < kPerLane) ? acc[i < kPerLane ? i : 0]
-                                                  : make_double2(0.0, 0.0);
+      const double2 val = (k < K && i < NPER) ? acc[i < NPER ? i : 0]
+                                              : make_double2(0.0, 0.0);
       out64[base + k] = val;
       if (out32) out32[base + k] = make_float2(float(val.x), float(val.y));
     }
@@ -119,12 +121,13 @@ __global__ void __launch_bounds__(64) k_s2m(
         }
       }
     }
-    store_coeffs(acc, mom, mom32, (b * nd + c) * int64_t(Kp), K, Kp, lane);
+    store_coeffs<64>(acc, mom, mom32, (b * nd + c) * int64_t(Kp), K, Kp, lane);
   }
 }
 
-// One workgroup (64 threads) per (parent box, direction).
-__global__ void __launch_bounds__(64) k_m2m(
+// One workgroup (kXT threads) per (parent box, direction); the children in
+// turn, each transformed by the whole workgroup.
+__global__ void __launch_bounds__(kXT) k_m2m(
     const double2* __restrict__ child_mom, int nd1, const int32_t* __restrict__ grid1,
     const uint32_t* __restrict__ key, int64_t nb, int level, double h1,
     const double* __restrict__ dirvec, const double* __restrict__ dirvec1, int nd,
@@ -139,8 +142,8 @@ __global__ void __launch_bounds__(64) k_m2m(
   const double cv[3] = {dirvec[3 * c], dirvec[3 * c + 1], dirvec[3 * c + 2]};
   const double cv1[3] = {dirvec1[3 * cp], dirvec1[3 * cp + 1], dirvec1[3 * cp + 2]};
   for (int64_t b = blockIdx.x; b < nb; b += gridDim.x) {
-    double2 acc[kPerLane];
-    for (int i = 0; i < kPerLane; ++i) acc[i] = make_double2(0.0, 0.0);
+    double2 acc[kPerXT];
+    for (int i = 0; i < kPerXT; ++i) acc[i] = make_double2(0.0, 0.0);
     const uint32_t pkey = key[b];
     for (int q = 0; q < 8; ++q) {
       const int32_t ch = grid1[(pkey << 3) | q];
@@ -158,24 +161,24 @@ __global__ void __launch_bounds__(64) k_m2m(
       }
       __syncthreads();
       const double2* src = child_mom + (int64_t(ch) * nd1 + cp) * Kp;
-      for (int k = lane; k < K; k += 64) {
+      for (int k = lane; k < K; k += kXT) {
         const int n3 = k % m1, n2 = (k / m1) % m1, n1 = k / (m1 * m1);
         double2 f = cmul(cmul(ph[0][n1], ph[1][n2]), ph[2][n3]);
         buf[0][k] = cmul(f, src[k]);
       }
       __syncthreads();
       // E_{s'}^T as three 1D passes: out[k] = sum_j E1[b][j][k] in[j]
-      apply_transfer(buf, ip, bq, true, lane, 64);  // result in buf[1]
+      apply_transfer(buf, ip, bq, true, lane, kXT);  // result in buf[1]
 #pragma unroll
-      for (int i = 0; i < kPerLane; ++i) {
-        const int k = lane + 64 * i;
+      for (int i = 0; i < kPerXT; ++i) {
+        const int k = lane + kXT * i;
         if (k < K) {
           acc[i].x += buf[1][k].x;
           acc[i].y += buf[1][k].y;
         }
       }
     }
-    store_coeffs(acc, mom, mom32, (b * nd + c) * int64_t(Kp), K, Kp, lane);
+    store_coeffs<kXT>(acc, mom, mom32, (b * nd + c) * int64_t(Kp), K, Kp, lane);
   }
 }
 
@@ -234,7 +237,7 @@ void launch_m2m(Plan& P, int level, hipStream_t s) {
   const int64_t nb = P.S.nb[level];
   if (nb == 0) return;
   dim3 grid(static_cast<unsigned>(std::min<int64_t>(nb, 1 << 20)), Lc.nd);
-  k_m2m<<<grid, 64, 0, s>>>(reinterpret_cast<const double2*>(L1.mom64.get()), L1.nd,
+  k_m2m<<<grid, kXT, 0, s>>>(reinterpret_cast<const double2*>(L1.mom64.get()), L1.nd,
                             P.S.grid[level + 1].get(), P.S.key[level].get(), nb, level,
                             L1.h, Lc.dirvec.get(), L1.dirvec.get(), Lc.nd, P.l_hf,
                             P.kappa, P.ip, reinterpret_cast<double2*>(Lc.mom64.get()),
