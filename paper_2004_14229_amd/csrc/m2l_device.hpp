@@ -94,7 +94,7 @@ __device__ __forceinline__ void gstore16(void* p, double2 v) {
 // col[b][j] is the first moment element of target j's source column for the
 // offset held in buffer b (or -1: empty or outside the grid).
 //
-// Compacted offsets (FP32 items with NB = 64 at sparse levels): the first
+// Compacted offsets (FP32 / BF16 items with NB = 64 that ask for it): the first
 // nval[b] entries of col[b] are the non-empty source columns only, and
 // inv[b][j] is the entry of target slot j (-1: empty source).
 template <int NB>

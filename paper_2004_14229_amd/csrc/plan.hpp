@@ -101,7 +101,7 @@ struct TuneConfig {
   int persistent = 1;    // 1: persistent workgroups pulling from a device queue
   int lpt = 1;           // 1: heaviest items first; 0: (level, octant, direction, block)
   int p2p_in_queue = 0;  // near-field items in the coupling launch
-  int compact = 1;       // FP32 column compaction: 0 never, 1 sparse levels, 2 all
+  int compact = 1;       // column compaction: 0 never, 1 sparse items, 2 every item
 };
 
 // One coupling launch: optional bank generation into a workspace, then the

@@ -35,7 +35,7 @@ class FdmError(RuntimeError):
 
 class Tune(ctypes.Structure):
     """fdm_tune: nb, persistent, lpt, p2p_in_queue, compact (0 never, 1
-    sparse levels, 2 every level)."""
+    items that save a fifth of their columns, 2 every item)."""
     _fields_ = [("nb", ctypes.c_int32), ("persistent", ctypes.c_int32),
                 ("lpt", ctypes.c_int32), ("p2p_in_queue", ctypes.c_int32),
                 ("compact", ctypes.c_int32)]
