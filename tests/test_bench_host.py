@@ -1,0 +1,35 @@
+"""Host-side accounting of bench.py (no GPU): the compulsory HBM bytes of
+the transfer phases, counted by hand for a small two-level tree."""
+import importlib.util
+import os
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def bench():
+    spec = importlib.util.spec_from_file_location("bench_mod", os.path.join(ROOT, "bench.py"))
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    return mod
+
+
+def test_hbm_phase_bytes_by_hand(bench):
+    # levels 0..2, couplings from level 1; K = 27 -> Kp = 32
+    shape = {"nbS": [1, 4, 10], "nbT": [1, 3, 7], "nd": [1, 2, 1], "levels": 2, "l_min": 1}
+    nT, nS, K = 50, 40, 27
+    ms = {"s2m": 1.0, "m2m": 2.0, "l2l": 4.0, "l2t": 0.5, "near": 0.001}
+    r = bench.hbm_phases(shape, ms, K, nT, nS, mixed=True)
+    vec, mom_w = 32 * 16, 32 * 16 + 32 * 8
+    assert r["s2m"]["bytes"] == 16 * nS * 2 + 40 * nS + 10 * 1 * mom_w
+    assert r["m2m"]["bytes"] == 10 * 1 * vec + 4 * 2 * mom_w  # level 2 -> 1 only
+    assert r["l2l"]["bytes"] == 3 * 2 * vec + 7 * 1 * 2 * vec
+    assert r["l2t"]["bytes"] == 7 * vec + 24 * nT + 32 * nT
+    assert r["near"]["bytes"] == 24 * nT + 40 * nS + 16 * nT
+    assert r["m2m"]["GB/s"] == pytest.approx(r["m2m"]["bytes"] / 2e-3 / 1e9)
+    assert r["near"]["GB/s"] is None  # a phase below 10 us gets no rate
+    plain = bench.hbm_phases(shape, ms, K, nT, nS, mixed=False)
+    assert plain["m2m"]["bytes"] == 10 * vec + 4 * 2 * vec
+
