@@ -18,6 +18,8 @@ Layout, following the paper:
 * ``dense``         Sect. 1 -- the dense product, for reference
 * ``emulate``       reduced-precision emulation of the M2L step, used to fix
                     the tolerance of the mixed-precision GPU path
+* ``lowrank``       Sect. 2.7 -- coupling matrices compressed by adaptive
+                    cross approximation (matvec option ``m2l="aca:<eps>"``)
 
 Readings of points the paper leaves open (node formula, child and face
 ordering, tie-breaks, tree depth, high-frequency level rule) are listed in the
@@ -37,6 +39,7 @@ from .interpolation import (chebyshev_nodes, lagrange_1d, multi_indices,
                             coupling_matrix, helmholtz)
 from .fdmvm import Plan, build, matvec, sample_rows, structure
 from .dense import dense_matvec, dense_rows
+from .lowrank import aca, aca_dense
 
 __all__ = [
     "BoxTree", "build_box_tree", "ETA2", "admissible", "block_tree",

@@ -31,7 +31,7 @@ from dataclasses import dataclass, field
 
 import numpy as np
 
-from . import emulate
+from . import emulate, lowrank
 from .tree import BoxTree, build_box_tree
 from .partition import ETA2, BlockTree, block_tree
 from .directions import DirectionSets, active_directions, high_frequency_level
@@ -120,8 +120,12 @@ def apply_coupling(m, h, o, kappa, c, M, m2l="fp64"):
     """One group of the coupling step: every admissible block of one level
     and offset ``o`` shares ``A_{c,t x s}`` (Sect. 2.7); rows of ``M`` are the
     blocks' source moments, the result rows their contributions to the
-    target locals."""
+    target locals.  ``m2l = "aca:<eps>"`` applies the matrix compressed by
+    adaptive cross approximation to tolerance eps (Sect. 2.7), A ~ U W^*."""
     A = coupling_matrix(m, h, o, kappa, c)
+    if m2l.startswith("aca:"):
+        U, W = lowrank.aca_dense(A, float(m2l[4:]))
+        return (M @ W.conj()) @ U.T
     return emulate.product(A, M, m2l)
 
 
@@ -152,7 +156,9 @@ def matvec(plan: Plan, v, chunk_points: int = 65536, keep: bool = False,
     """Alg. 4: ``g ~= A v`` in the user's target order (complex128).
 
     ``m2l`` other than ``"fp64"`` emulates a reduced-precision coupling step
-    (see ``oracle.emulate``); the default is the plain FP64 algorithm.
+    (see ``oracle.emulate``) or, as ``"aca:<eps>"``, applies the coupling
+    matrices compressed by ACA (``oracle.lowrank``); the default is the
+    plain FP64 algorithm.
     """
     t0 = time.perf_counter()
     TT, TS, BT, dirs = plan.TT, plan.TS, plan.BT, plan.dirs
