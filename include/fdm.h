@@ -346,6 +346,35 @@ int fdm_batch_autotune(fdm_batch* batch, const void* const* v, void* const* y,
 /* Free a batch (not its plans).  NULL is accepted. */
 int fdm_batch_destroy(fdm_batch* batch);
 
+/*
+ * fdm_aca -- low-rank compression A ~ U W^H of one complex matrix by
+ * partially pivoted adaptive cross approximation, the compression the paper
+ * applies to its coupling matrices (Sect. 2.7).  Cross k takes the residual
+ * of one row of A, scales it by its entry of largest modulus (the pivot
+ * column), takes the residual of that column, and moves on to the unused row
+ * where that column is largest; a row whose residual vanishes is skipped for
+ * the first unused row.  It stops once |u_k| |v_k| <= eps |sum_l u_l v_l^T|_F
+ * (the Frobenius norm kept up to date from inner products), at max_rank
+ * crosses, or when no unused row is left.  Only the pivot rows and columns
+ * of A are read.
+ * Host code: runs on the calling thread, touches no device and no stream.
+ *  A        host complex128 (re, im interleaved), n_rows x n_cols, row-major.
+ *  eps      relative tolerance, >= 0 (0: stop only at max_rank or when the
+ *           residual of every row has vanished).
+ *  max_rank 1..min(n_rows, n_cols).
+ *  U        host complex128, n_rows x max_rank, row-major: column l holds u_l
+ *           for l < *rank; the other columns are zeroed.
+ *  W        host complex128, n_cols x max_rank, row-major: column l holds
+ *           conj(v_l), so that A ~ U W^H.  Same zeroing.
+ *  rank     host int, set to the number of crosses taken (0 for A = 0).
+ * U and W are owned by the caller and may not overlap A or each other.
+ * FDM_ERR_INVALID_ARG for NULL pointers, n_rows or n_cols < 1, a max_rank
+ * outside the range, a negative or non-finite eps, or non-finite entries in
+ * a row or column it reads.
+ */
+int fdm_aca(const double* A, int n_rows, int n_cols, double eps, int max_rank,
+            double* U, double* W, int* rank);
+
 /* Thread-local message of the last error ("" if none). */
 const char* fdm_last_error(void);
 

@@ -5,8 +5,8 @@ directional matrix-vector product of Of & Watschinger (uniform box cluster
 trees, directional Chebyshev interpolation, Alg. 4) in hand-written HIP; this
 package is its thin Python binding.
 """
-from .fdm import (Batch, Plan, FdmError, dense_matvec, lib, header_functions, PRECISION,
+from .fdm import (Batch, Plan, FdmError, aca, dense_matvec, lib, header_functions, PRECISION,
                   STATUS, LIB_PATH)
 
-__all__ = ["Batch", "Plan", "FdmError", "dense_matvec", "lib", "header_functions",
+__all__ = ["Batch", "Plan", "FdmError", "aca", "dense_matvec", "lib", "header_functions",
            "PRECISION", "STATUS", "LIB_PATH"]

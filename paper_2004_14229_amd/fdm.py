@@ -111,6 +111,7 @@ def lib() -> ctypes.CDLL:
     L.fdm_batch_autotune.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(vp), ci, ci, vp,
                                      ctypes.POINTER(Tune), ctypes.POINTER(dbl)]
     L.fdm_batch_destroy.argtypes = [vp]
+    L.fdm_aca.argtypes = [vp, ci, ci, dbl, ci, vp, vp, ctypes.POINTER(ci)]
     L.fdm_last_error.restype = ctypes.c_char_p
     L.fdm_version.restype = ctypes.c_char_p
     for f in ("fdm_build_tree", "fdm_build_tree_ex", "fdm_build_tree_opts", "fdm_plan_matvec",
@@ -120,7 +121,7 @@ def lib() -> ctypes.CDLL:
               "fdm_plan_prepare", "fdm_plan_coupling_launches", "fdm_plan_wait_launch",
               "fdm_plan_autotune", "fdm_batch_create", "fdm_batch_matvec",
               "fdm_batch_set_graph", "fdm_batch_get_tune", "fdm_batch_set_tune",
-              "fdm_batch_autotune", "fdm_batch_destroy"):
+              "fdm_batch_autotune", "fdm_batch_destroy", "fdm_aca"):
         getattr(L, f).restype = ci
     _lib = L
     return L
@@ -287,6 +288,23 @@ def dense_matvec(points_T, points_S, kappa: float, v, out=None, stream=None):
     _check(lib().fdm_dense_matvec(_ptr(pt), pt.shape[0], _ptr(ps), ps.shape[0], float(kappa),
                                   _ptr(v), _ptr(out), _stream_handle(stream)))
     return out
+
+
+def aca(A, eps: float, max_rank: int | None = None):
+    """Low-rank ``A ~ U @ W.conj().T`` of a host complex matrix by partially
+    pivoted ACA (wraps ``fdm_aca``; host code, no device).  Returns numpy
+    arrays U (n_rows, k) and W (n_cols, k)."""
+    A = np.ascontiguousarray(A, dtype=np.complex128)
+    if A.ndim != 2:
+        raise TypeError("A must be a 2-d array")
+    n, m = A.shape
+    R = min(n, m) if max_rank is None else int(max_rank)
+    U = np.zeros((n, max(R, 1)), np.complex128)
+    W = np.zeros((m, max(R, 1)), np.complex128)
+    k = ctypes.c_int()
+    _check(lib().fdm_aca(A.ctypes.data, n, m, float(eps), R, U.ctypes.data, W.ctypes.data,
+                         ctypes.byref(k)))
+    return U[:, :k.value].copy(), W[:, :k.value].copy()
 
 
 class Batch:
