@@ -49,7 +49,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only copy 1 GiB device to device (calibrates HBM byte counters)")
-    ap.add_argument("--cpu-groups", type=int, default=10)
+    ap.add_argument("--cpu-groups", type=int, default=40)
     return ap.parse_args()
 
 
