@@ -193,6 +193,27 @@ def test_table1_from_points(k):
     assert np.bincount(plan.BT.near_t[-1]).max() <= 27
 
 
+@pytest.mark.parametrize("k", [5, 6])
+def test_stored_couplings_pair_by_transposition(k):
+    """Every stored coupling (level, o) has its partner (level, -o) stored,
+    used by as many blocks, with the antipodal direction, so that
+    A_{-o} = A_o^T (the coupling matrix transposes when o and c change sign)
+    and half of the bank determines the rest."""
+    P = W.config(f"paper_k{k}")
+    plan = oracle.build(P.points_T, P.points_S, P.kappa, P.box, P.levels, P.m)
+    s = oracle.structure(plan)
+    for l in range(P.levels + 1):
+        off, cnt = s[f"off{l}"], s[f"offcnt{l}"]
+        if not off.shape[0]:
+            continue
+        index = {tuple(o): i for i, o in enumerate(off)}
+        partner = np.array([index[tuple(-o)] for o in off])
+        assert np.array_equal(cnt[partner], cnt)
+        vec = plan.dirs.vectors(l)
+        d = s[f"offdir{l}"]
+        assert np.array_equal(vec[d[partner]], -vec[d] + 0.0), l
+
+
 # ------------------------------------------------------- Alg. 3, dir maps --
 def test_direction_counts_and_top_faces():
     D = DirectionSets(3, 5)
