@@ -170,8 +170,9 @@ class Plan:
         self.n_T, self.n_S = pt.shape[0], ps.shape[0]
         self.precision = precision
 
-    def matvec(self, v, out=None, stream=None):
-        """``y = A~ v`` (complex128, or complex64 in and out)."""
+    def _vectors(self, v, out):
+        """Checks v (n_S) and out (n_T) before any pointer reaches the
+        library, which cannot see sizes."""
         import torch
         if not isinstance(v, torch.Tensor) or not v.is_cuda:
             raise TypeError("v must be a CUDA tensor")
@@ -180,8 +181,15 @@ class Plan:
         v = v.contiguous()
         if out is None:
             out = torch.empty(self.n_T, dtype=v.dtype, device=v.device)
-        elif out.dtype != v.dtype or out.shape != (self.n_T,) or not out.is_contiguous():
-            raise TypeError("out must be a contiguous vector of length n_T, same dtype as v")
+        elif (not isinstance(out, torch.Tensor) or not out.is_cuda or out.dtype != v.dtype
+              or out.shape != (self.n_T,) or not out.is_contiguous()):
+            raise TypeError("out must be a contiguous CUDA vector of length n_T, same dtype as v")
+        return v, out
+
+    def matvec(self, v, out=None, stream=None):
+        """``y = A~ v`` (complex128, or complex64 in and out)."""
+        import torch
+        v, out = self._vectors(v, out)
         fn = lib().fdm_plan_matvec if v.dtype == torch.complex128 else lib().fdm_plan_matvec_c64
         _check(fn(self._h, _ptr(v), _ptr(out), _stream_handle(stream)))
         return out
@@ -220,9 +228,9 @@ class Plan:
         """Time the coupling step under each launch shape and keep the
         fastest; also computes ``out = A~ v``.  Returns (best, times_ms, out)."""
         import torch
-        v = v.contiguous()
-        if out is None:
-            out = torch.empty(self.n_T, dtype=v.dtype, device=v.device)
+        v, out = self._vectors(v, out)
+        if max_candidates < 1:
+            raise ValueError("max_candidates must be at least 1")
         best = Tune()
         ms = (ctypes.c_double * max_candidates)()
         _check(lib().fdm_plan_autotune(self._h, _ptr(v), _ptr(out),
@@ -280,11 +288,15 @@ def dense_matvec(points_T, points_S, kappa: float, v, out=None, stream=None):
     """Dense ``y = A v`` by direct FP64 summation on the GPU."""
     import torch
     pt, ps = _points(points_T), _points(points_S)
-    if v.dtype != torch.complex128 or v.shape != (ps.shape[0],):
-        raise TypeError("v must be complex128 of length n_S")
+    if not isinstance(v, torch.Tensor) or not v.is_cuda or v.dtype != torch.complex128 \
+            or v.shape != (ps.shape[0],):
+        raise TypeError("v must be a complex128 CUDA vector of length n_S")
     v = v.contiguous()
     if out is None:
         out = torch.empty(pt.shape[0], dtype=torch.complex128, device=v.device)
+    elif (not isinstance(out, torch.Tensor) or not out.is_cuda or out.dtype != torch.complex128
+          or out.shape != (pt.shape[0],) or not out.is_contiguous()):
+        raise TypeError("out must be a contiguous complex128 CUDA vector of length n_T")
     _check(lib().fdm_dense_matvec(_ptr(pt), pt.shape[0], _ptr(ps), ps.shape[0], float(kappa),
                                   _ptr(v), _ptr(out), _stream_handle(stream)))
     return out
@@ -334,9 +346,12 @@ class Batch:
                 raise TypeError("each v must be a CUDA vector of its plan's n_S, one dtype")
         if outs is None:
             outs = [torch.empty(p.n_T, dtype=dtype, device=vs[0].device) for p in self.plans]
+        if len(outs) != len(self.plans):
+            raise ValueError("one out per plan")
         for y, p in zip(outs, self.plans):
-            if y.dtype != dtype or y.shape != (p.n_T,) or not y.is_contiguous():
-                raise TypeError("each out must be a contiguous vector of its plan's n_T")
+            if (not isinstance(y, torch.Tensor) or not y.is_cuda or y.dtype != dtype
+                    or y.shape != (p.n_T,) or not y.is_contiguous()):
+                raise TypeError("each out must be a contiguous CUDA vector of its plan's n_T")
         n = len(self.plans)
         va = (ctypes.c_void_p * n)(*[v.data_ptr() if v.numel() else None for v in vs])
         ya = (ctypes.c_void_p * n)(*[y.data_ptr() if y.numel() else None for y in outs])
@@ -365,6 +380,8 @@ class Batch:
         shape and keep the fastest; also computes outs.  Returns
         (best, times_ms, outs)."""
         vs, outs, va, ya, c64 = self._vectors(vs, outs)
+        if max_candidates < 1:
+            raise ValueError("max_candidates must be at least 1")
         best = Tune()
         ms = (ctypes.c_double * max_candidates)()
         _check(lib().fdm_batch_autotune(self._h, va, ya, c64, int(max_candidates),
