@@ -33,3 +33,21 @@ def test_hbm_phase_bytes_by_hand(bench):
     plain = bench.hbm_phases(shape, ms, K, nT, nS, mixed=False)
     assert plain["m2m"]["bytes"] == 10 * vec + 4 * 2 * vec
 
+
+
+def test_traffic_only_for_the_measured_kernel_source(bench, tmp_path, monkeypatch):
+    """The counter record gives `traffic` only while its SHA-256 matches the
+    kernel's current sources; a stale or missing record gives null."""
+    csrc = tmp_path / "paper_2004_14229_amd" / "csrc"
+    csrc.mkdir(parents=True)
+    (tmp_path / "profiles").mkdir()
+    (csrc / "m2l_device.hpp").write_text("// shared\n")
+    (csrc / "m2l_f32.hip").write_text("// fp32\n")
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    assert bench.traffic_for("k_m2l_f32", "w", 1.0) is None  # no record
+    rec = tmp_path / "profiles" / "k_m2l_f32_w_counters.json"
+    sha = bench.kernel_source_sha("k_m2l_f32")
+    rec.write_text('{"source_sha256": "%s", "hbm_bytes_per_launch": 123.5}' % sha)
+    assert bench.traffic_for("k_m2l_f32", "w", 1.0) == 123.5
+    (csrc / "m2l_device.hpp").write_text("// shared, edited\n")
+    assert bench.traffic_for("k_m2l_f32", "w", 1.0) is None
