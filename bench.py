@@ -175,6 +175,7 @@ def cpu_baseline(P, stats, groups: int, seed: int = 7):
     cand = cand[oracle.admissible(P.kappa, h, cand)]
     par = -((-cand) // 2)  # ceil(o / 2): parent offset for target octant 0
     cand = cand[~oracle.admissible(P.kappa, TT.side(level - 1), par)]
+    groups = min(groups, cand.shape[0])
     pick = cand[rng.choice(cand.shape[0], groups, replace=False)]
     src_index = {tuple(c): i for i, c in enumerate(TS.coords[level])}
     t_mat, t_all, n_blocks = [], [], 0

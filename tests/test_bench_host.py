@@ -51,3 +51,15 @@ def test_traffic_only_for_the_measured_kernel_source(bench, tmp_path, monkeypatc
     assert bench.traffic_for("k_m2l_f32", "w", 1.0) == 123.5
     (csrc / "m2l_device.hpp").write_text("// shared, edited\n")
     assert bench.traffic_for("k_m2l_f32", "w", 1.0) is None
+
+
+def test_cpu_baseline_on_a_small_workload(bench):
+    """The oracle leg of the benchmark runs on a sample and scales it to the
+    stated block and matrix counts (here those of a small workload)."""
+    import workloads as W
+    P = W.config("uniform2k")
+    stats = {"n_stored_couplings": 1000, "n_couplings": 50000}
+    r = bench.cpu_baseline(P, stats, 1000)  # more groups than exist: all of them
+    assert r["kind"] == "oracle" and r["unit"] == "matvecs/s"
+    assert r["value"] > 0 and r["cores"] >= 1
+    assert "offset groups" in r["sample"]
