@@ -15,6 +15,12 @@ output.  Modes (operands = coupling matrix and moments of one M2L product):
 * ``bf16x6``    operands split into BF16 hi + mid + lo parts (24 significant
                 bits), the six products of order <= 2 (hh, hm, mh, hl, mm,
                 lh) summed in FP32, sum over offsets in FP64.
+
+Pinned by: BF16 rounding equal to torch's float32 -> bfloat16 conversion
+(round to nearest even) and on hand-made ties; the error bounds of the two-
+and three-part splits; products on operands built from exact BF16 parts,
+where the three-product split equals the exact product minus the lo*lo
+terms bit for bit; and the error band of each mode on random operands.
 """
 from __future__ import annotations
 
