@@ -119,3 +119,21 @@ def test_accumulation_type():
         assert E.accumulate_dtype(mode) == np.complex128
     with pytest.raises(ValueError):
         E.product(np.ones((2, 2)), np.ones((2, 2)), "fp16")
+
+
+def test_emulated_matvec_errors_follow_the_arithmetic():
+    """Alg. 4 with the coupling step emulated in each mode: FP32 products
+    stay near FP32 rounding (and summing the offsets in FP64 is no worse),
+    the three-product BF16 split is an order of magnitude above, the
+    six-product split back at FP32 level."""
+    import oracle
+    import workloads as W
+    P = W.random_problem(52, 400, 380, 30.0, 3, 4)
+    plan = oracle.build(P.points_T, P.points_S, P.kappa, P.box, P.levels, P.m)
+    y = oracle.matvec(plan, P.v)
+    err = {mode: np.linalg.norm(oracle.matvec(plan, P.v, m2l=mode) - y) / np.linalg.norm(y)
+           for mode in ("fp32", "fp32acc64", "bf16x3", "bf16x6")}
+    assert 1e-8 <= err["fp32"] <= 1e-6, err
+    assert err["fp32acc64"] <= err["fp32"], err
+    assert 5e-7 <= err["bf16x3"] <= 1e-5 and err["bf16x3"] >= 5 * err["fp32"], err
+    assert err["bf16x6"] <= err["fp32"], err
