@@ -211,3 +211,28 @@ def test_paper_k6_error_matches_printed_value():
     yd = oracle.dense_rows(P.points_T, P.points_S, P.v, P.kappa, rows)
     err = _rel(y, yd)
     assert 2e-4 / 3 < err < 2e-4 * 1.5
+
+
+def test_dense_rows_brute_force_with_coinciding_point():
+    """The dense product (Sect. 1) against a scalar double loop with
+    math.cos / math.sin, including a target equal to a source (zero term)
+    and a chunk size that leaves a ragged last chunk."""
+    import math
+    rng = np.random.default_rng(9)
+    X = rng.uniform(-1, 1, (7, 3))
+    Y = rng.uniform(-1, 1, (9, 3))
+    Y[4] = X[2]
+    v = rng.standard_normal(9) + 1j * rng.standard_normal(9)
+    kappa = 6.5
+    want = []
+    for x in X:
+        s = 0j
+        for yk, vk in zip(Y, v):
+            r = math.sqrt(sum((a - b) ** 2 for a, b in zip(x, yk)))
+            if r > 0:
+                s += complex(math.cos(kappa * r), math.sin(kappa * r)) / (4 * math.pi * r) * vk
+        want.append(s)
+    want = np.array(want)
+    for chunk in (2, 256):
+        got = oracle.dense_rows(X, Y, v, kappa, np.arange(7), chunk=chunk)
+        assert np.allclose(got, want, rtol=1e-13, atol=0)
