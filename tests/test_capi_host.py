@@ -35,6 +35,7 @@ def _build(**kw):
     (dict(n_T=-5), -1), (dict(l_hf=5, levels=3), -1),
     (dict(box=(0, 0, 0, 1, 1, 2)), -3), (dict(box=(0, 0, 0, 0, 1, 1)), -1),
     (dict(m=7), -3), (dict(prec=3), -1), (dict(prec=-1), -1),
+    (dict(n_T=2 ** 30), -3), (dict(n_S=2 ** 30), -3), (dict(n_S=-1), -1),
 ])
 def test_invalid_arguments_are_rejected(kw, status):
     st, h, msg = _build(**kw)
