@@ -236,3 +236,17 @@ def test_dense_rows_brute_force_with_coinciding_point():
     for chunk in (2, 256):
         got = oracle.dense_rows(X, Y, v, kappa, np.arange(7), chunk=chunk)
         assert np.allclose(got, want, rtol=1e-13, atol=0)
+
+
+@pytest.mark.parametrize("name", ["uniform100k", "uniform1m"])
+def test_stored_rows_approximate_the_dense_product(name):
+    """The stored oracle rows of the full-size workloads (written by
+    tests/golden/make_golden.py) against the dense sum (Sect. 1) at the same
+    rows: within the method's approximation error for these m and kappa,
+    and not equal to it (they are the fast method's values)."""
+    import os
+    g = np.load(os.path.join(os.path.dirname(__file__), "golden", f"{name}_rows.npz"))
+    P = W.config(name)
+    yd = oracle.dense_rows(P.points_T, P.points_S, P.v, P.kappa, g["rows"])
+    err = np.linalg.norm(g["y"] - yd) / np.linalg.norm(yd)
+    assert 1e-6 < err < 1e-3, err
