@@ -250,3 +250,16 @@ def test_stored_rows_approximate_the_dense_product(name):
     yd = oracle.dense_rows(P.points_T, P.points_S, P.v, P.kappa, g["rows"])
     err = np.linalg.norm(g["y"] - yd) / np.linalg.norm(yd)
     assert 1e-6 < err < 1e-3, err
+
+
+def test_stored_batch_rows_approximate_the_dense_product():
+    """As above for the four stored problems of the batched workload (two
+    uniform, two clustered)."""
+    import os
+    g = np.load(os.path.join(os.path.dirname(__file__), "golden", "batch_rows.npz"))
+    probs = W.batch_problems()
+    for i in (2, 4, 35, 46):
+        P = probs[i]
+        yd = oracle.dense_rows(P.points_T, P.points_S, P.v, P.kappa, g[f"rows{i}"])
+        err = np.linalg.norm(g[f"y{i}"] - yd) / np.linalg.norm(yd)
+        assert 1e-6 < err < 2e-3, (i, err)
