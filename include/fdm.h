@@ -71,9 +71,15 @@ typedef enum {
  *            box (lo, hi] shared by both trees.  Must be a cube (else
  *            FDM_ERR_UNSUPPORTED).  Every point must satisfy lo < x <= hi
  *            per axis (else FDM_ERR_POINT_OUTSIDE_BOX).
- *  levels    tree depth below the root, 0..9; every non-empty box above
- *            this level is split (leaves all sit on this level).
- *  m         Chebyshev degree per axis, 1..8: (m+1)^3 nodes per box.
+ *  levels    tree depth below the root, 0..9 (the per-level key -> box
+ *            grids hold 8^levels entries); every non-empty box above this
+ *            level is split (leaves all sit on this level).  levels outside
+ *            0..9 give FDM_ERR_INVALID_ARG.
+ *  m         Chebyshev degree per axis: (m+1)^3 nodes per box.  m outside
+ *            1..8 gives FDM_ERR_INVALID_ARG; m = 7 and 8 give
+ *            FDM_ERR_UNSUPPORTED, because the coupling kernels give one
+ *            wave to each 32 of the (m+1)^3 nodes padded to a multiple of 32
+ *            and hold at most 384 of them (m <= 6).
  *  precision an fdm_precision.
  *  stream    HIP stream for the device work; the call synchronises it
  *            before returning (box counts size the plan).

@@ -138,6 +138,45 @@ def _stream_handle(stream):
     return ctypes.c_void_p(s.cuda_stream)
 
 
+class _OnStream:
+    """Runs a library call on ``stream`` (None: the current stream).
+
+    With a stream other than the current one: the stream first waits for
+    the work already queued on the current stream (so inputs written there
+    are complete), tensors made inside the block are allocated on the given
+    stream, and every tensor passed to ``keep`` is marked as used by that
+    stream, so that torch's caching allocator does not hand its memory to
+    other work before the library's kernels are done with it."""
+
+    def __init__(self, stream):
+        self.stream, self._ctx = None, None
+        if stream is not None:
+            import torch
+            cur = torch.cuda.current_stream()
+            if stream != cur:
+                self.stream = stream
+                stream.wait_stream(cur)
+                self._ctx = torch.cuda.stream(stream)
+
+    def __enter__(self):
+        if self._ctx is not None:
+            self._ctx.__enter__()
+        return self
+
+    def __exit__(self, *exc):
+        if self._ctx is not None:
+            self._ctx.__exit__(*exc)
+
+    def handle(self):
+        return _stream_handle(self.stream)
+
+    def keep(self, *tensors):
+        if self.stream is not None:
+            for t in tensors:
+                if t is not None and t.numel():
+                    t.record_stream(self.stream)
+
+
 def _ptr(t) -> ctypes.c_void_p:
     return ctypes.c_void_p(t.data_ptr() if t is not None and t.numel() else 0)
 
@@ -157,14 +196,16 @@ class Plan:
     def __init__(self, points_T, points_S, kappa: float, box, levels: int, m: int,
                  precision: str = "fp64", l_hf: int | None = None, stream=None,
                  bank_budget: int = 0, tune: dict | None = None):
-        pt, ps = _points(points_T), _points(points_S)
         box_arr = (ctypes.c_double * 6)(*[float(b) for b in box])
         opts = Options(PRECISION[precision], -2 if l_hf is None else int(l_hf),
                        int(bank_budget), Tune.from_dict(tune) if tune else Tune())
         h = ctypes.c_void_p()
-        st = lib().fdm_build_tree_opts(
-            _ptr(pt), pt.shape[0], _ptr(ps), ps.shape[0], float(kappa), box_arr,
-            int(levels), int(m), ctypes.byref(opts), _stream_handle(stream), ctypes.byref(h))
+        # the library synchronises the stream before returning
+        with _OnStream(stream) as on:
+            pt, ps = _points(points_T), _points(points_S)
+            st = lib().fdm_build_tree_opts(
+                _ptr(pt), pt.shape[0], _ptr(ps), ps.shape[0], float(kappa), box_arr,
+                int(levels), int(m), ctypes.byref(opts), on.handle(), ctypes.byref(h))
         _check(st)
         self._h = h
         self.n_T, self.n_S = pt.shape[0], ps.shape[0]
@@ -189,9 +230,11 @@ class Plan:
     def matvec(self, v, out=None, stream=None):
         """``y = A~ v`` (complex128, or complex64 in and out)."""
         import torch
-        v, out = self._vectors(v, out)
-        fn = lib().fdm_plan_matvec if v.dtype == torch.complex128 else lib().fdm_plan_matvec_c64
-        _check(fn(self._h, _ptr(v), _ptr(out), _stream_handle(stream)))
+        with _OnStream(stream) as on:
+            v, out = self._vectors(v, out)
+            fn = lib().fdm_plan_matvec if v.dtype == torch.complex128 else lib().fdm_plan_matvec_c64
+            _check(fn(self._h, _ptr(v), _ptr(out), on.handle()))
+            on.keep(v, out)
         return out
 
     def stats(self) -> dict:
@@ -228,14 +271,16 @@ class Plan:
         """Time the coupling step under each launch shape and keep the
         fastest; also computes ``out = A~ v``.  Returns (best, times_ms, out)."""
         import torch
-        v, out = self._vectors(v, out)
         if max_candidates < 1:
             raise ValueError("max_candidates must be at least 1")
-        best = Tune()
-        ms = (ctypes.c_double * max_candidates)()
-        _check(lib().fdm_plan_autotune(self._h, _ptr(v), _ptr(out),
-                                       int(v.dtype == torch.complex64), int(max_candidates),
-                                       _stream_handle(stream), ctypes.byref(best), ms))
+        with _OnStream(stream) as on:
+            v, out = self._vectors(v, out)
+            best = Tune()
+            ms = (ctypes.c_double * max_candidates)()
+            _check(lib().fdm_plan_autotune(self._h, _ptr(v), _ptr(out),
+                                           int(v.dtype == torch.complex64), int(max_candidates),
+                                           on.handle(), ctypes.byref(best), ms))
+            on.keep(v, out)
         return best.as_dict(), list(ms), out
 
     def prepare(self, stream=None) -> None:
@@ -287,18 +332,22 @@ class Plan:
 def dense_matvec(points_T, points_S, kappa: float, v, out=None, stream=None):
     """Dense ``y = A v`` by direct FP64 summation on the GPU."""
     import torch
-    pt, ps = _points(points_T), _points(points_S)
-    if not isinstance(v, torch.Tensor) or not v.is_cuda or v.dtype != torch.complex128 \
-            or v.shape != (ps.shape[0],):
+    if not isinstance(v, torch.Tensor) or not v.is_cuda or v.dtype != torch.complex128:
         raise TypeError("v must be a complex128 CUDA vector of length n_S")
-    v = v.contiguous()
-    if out is None:
-        out = torch.empty(pt.shape[0], dtype=torch.complex128, device=v.device)
-    elif (not isinstance(out, torch.Tensor) or not out.is_cuda or out.dtype != torch.complex128
-          or out.shape != (pt.shape[0],) or not out.is_contiguous()):
-        raise TypeError("out must be a contiguous complex128 CUDA vector of length n_T")
-    _check(lib().fdm_dense_matvec(_ptr(pt), pt.shape[0], _ptr(ps), ps.shape[0], float(kappa),
-                                  _ptr(v), _ptr(out), _stream_handle(stream)))
+    with _OnStream(stream) as on:
+        pt, ps = _points(points_T), _points(points_S)
+        if v.shape != (ps.shape[0],):
+            raise TypeError("v must be a complex128 CUDA vector of length n_S")
+        v = v.contiguous()
+        if out is None:
+            out = torch.empty(pt.shape[0], dtype=torch.complex128, device=v.device)
+        elif (not isinstance(out, torch.Tensor) or not out.is_cuda
+              or out.dtype != torch.complex128 or out.shape != (pt.shape[0],)
+              or not out.is_contiguous()):
+            raise TypeError("out must be a contiguous complex128 CUDA vector of length n_T")
+        _check(lib().fdm_dense_matvec(_ptr(pt), pt.shape[0], _ptr(ps), ps.shape[0],
+                                      float(kappa), _ptr(v), _ptr(out), on.handle()))
+        on.keep(pt, ps, v, out)
     return out
 
 
@@ -359,8 +408,10 @@ class Batch:
 
     def matvec(self, vs, outs=None, stream=None):
         """``outs[i] = A~_i vs[i]`` for every plan; returns outs."""
-        vs, outs, va, ya, c64 = self._vectors(vs, outs)
-        _check(lib().fdm_batch_matvec(self._h, va, ya, c64, _stream_handle(stream)))
+        with _OnStream(stream) as on:
+            vs, outs, va, ya, c64 = self._vectors(vs, outs)
+            _check(lib().fdm_batch_matvec(self._h, va, ya, c64, on.handle()))
+            on.keep(*vs, *outs)
         return outs
 
     def set_graph(self, enable: bool) -> None:
@@ -379,13 +430,15 @@ class Batch:
         """Time the batch's coupling launches under each candidate launch
         shape and keep the fastest; also computes outs.  Returns
         (best, times_ms, outs)."""
-        vs, outs, va, ya, c64 = self._vectors(vs, outs)
         if max_candidates < 1:
             raise ValueError("max_candidates must be at least 1")
-        best = Tune()
-        ms = (ctypes.c_double * max_candidates)()
-        _check(lib().fdm_batch_autotune(self._h, va, ya, c64, int(max_candidates),
-                                        _stream_handle(stream), ctypes.byref(best), ms))
+        with _OnStream(stream) as on:
+            vs, outs, va, ya, c64 = self._vectors(vs, outs)
+            best = Tune()
+            ms = (ctypes.c_double * max_candidates)()
+            _check(lib().fdm_batch_autotune(self._h, va, ya, c64, int(max_candidates),
+                                            on.handle(), ctypes.byref(best), ms))
+            on.keep(*vs, *outs)
         return best.as_dict(), list(ms), outs
 
     def close(self) -> None:
