@@ -24,8 +24,10 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "matvecs/s at N=1e6 mixed vs FP64 plain; rel l2 err vs FP64 oracle"
-PEAK_TFLOPS = {"fp32": 157.3, "fp64": 78.6, "bf16x3": 2500.0}
-M2L_KERNEL = {"fp32": "k_m2l_f32", "fp64": "k_m2l_f64", "bf16x3": "k_m2l_bf16x3"}
+PEAK_TFLOPS = {"fp32": 157.3, "fp64": 78.6, "bf16x3": 2500.0, "bf16x6": 2500.0}
+M2L_KERNEL = {"fp32": "k_m2l_f32", "fp64": "k_m2l_f64", "bf16x3": "k_m2l_bf16x3",
+              "bf16x6": "k_m2l_bf16x6"}
+SPLIT_PRODUCTS = {"bf16x3": 3, "bf16x6": 6}  # BF16 products issued per real product
 
 
 def parse():
@@ -34,11 +36,11 @@ def parse():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="uniform1m")
-    ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64", "bf16x3"])
+    ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64", "bf16x3", "bf16x6"])
     ap.add_argument("--plain-steps", type=int, default=1,
                     help="timed steps of the plain FP64 plan (0 = skip)")
     ap.add_argument("--bf16-steps", type=int, default=1,
-                    help="timed steps of the BF16 split (bf16x3) plan (0 = skip)")
+                    help="timed steps of each BF16 split plan (bf16x3, bf16x6; 0 = skip)")
     ap.add_argument("--batch-steps", type=int, default=2,
                     help="timed batched matvecs of the 64-problem workload (0 = skip)")
     ap.add_argument("--bank-budget-gb", type=float, default=0.0,
@@ -46,10 +48,14 @@ def parse():
                          "workspace of this many GB (for banks that do not fit)")
     ap.add_argument("--compact", type=int, default=1, choices=[0, 1, 2],
                     help="FP32 column compaction: 0 never, 1 sparse levels, 2 every level")
+    ap.add_argument("--nb", type=int, default=None, choices=[32, 64],
+                    help="target boxes per coupling work item of the timed plan "
+                         "(default: the library's for the precision)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only copy 1 GiB device to device (calibrates HBM byte counters)")
-    ap.add_argument("--cpu-groups", type=int, default=40)
+    ap.add_argument("--cpu-sub", type=int, default=4,
+                    help="CPU baseline sample: the sub-cube of side 1/cpu-sub of the box")
     return ap.parse_args()
 
 
@@ -128,7 +134,7 @@ def kernel_source_sha(kernel: str) -> str:
     code + its precision's file)."""
     csrc = os.path.join(ROOT, "paper_2004_14229_amd", "csrc")
     part = {"k_m2l_f32": "m2l_f32.hip", "k_m2l_f64": "m2l_f64.hip",
-            "k_m2l_bf16x3": "m2l_bf16.hip"}[kernel]
+            "k_m2l_bf16x3": "m2l_bf16.hip", "k_m2l_bf16x6": "m2l_bf16x6.hip"}[kernel]
     h = hashlib.sha256()
     for f in ("m2l_device.hpp", part):
         h.update(open(os.path.join(csrc, f), "rb").read())
@@ -147,67 +153,87 @@ def traffic_for(kernel: str, workload: str, launch_flops: float):
     return rec.get("hbm_bytes_per_launch")
 
 
-def cpu_baseline(P, stats, groups: int, seed: int = 7):
-    """The oracle's coupling step (its Alg. 4 M2L: one coupling matrix per
-    level and offset applied to all blocks of that offset), timed on a seeded
-    sample of (level, offset) groups with their full block lists, then scaled
-    to a whole matvec as N_SC * (matrix time) + N_C * (time per block)."""
+def cpu_baseline(P, stats, shape, sub_div: int = 4):
+    """The oracle's whole Alg. 4 (S2M, M2M, M2L, L2L, L2T, near field, in the
+    oracle's own code) timed on a bounded sample of the workload: the points
+    of the workload inside the sub-cube (0, 1/sub_div]^3 with their charges,
+    the same kappa, m and leaf size (levels - log2(sub_div)), so that every
+    box size of the workload's coupling levels occurs with the same
+    direction counts.  Each phase's time is scaled to the whole workload by
+    its own work count (points for S2M and L2T, box-directions for M2M and
+    L2L, stored matrices and admissible blocks for M2L, point pairs for the
+    near field): measured on the sample, extrapolated per phase."""
     import oracle
-    from oracle.fdmvm import apply_coupling
     from oracle.interpolation import coupling_matrix
     try:
         from threadpoolctl import threadpool_info
         cores = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
     except Exception:  # pragma: no cover
         cores = os.cpu_count()
-    rng = np.random.default_rng(seed)
-    TT = oracle.build_box_tree(P.points_T, P.box, P.levels)
-    TS = oracle.build_box_tree(P.points_S, P.box, P.levels)
+    lo = np.asarray(P.box[:3])
     side = P.box[3] - P.box[0]
-    l_hf = oracle.high_frequency_level(P.kappa, side, P.levels)
-    dirs = oracle.DirectionSets(l_hf, P.levels)
-    level = P.levels - 1  # the level with the most blocks at this workload
-    h = TT.side(level)
-    # admissible offsets of the level whose parent offset is inadmissible
-    R = 2 ** level - 1
-    r = np.arange(-R, R + 1)
-    cand = np.stack(np.meshgrid(r, r, r, indexing="ij"), -1).reshape(-1, 3)
-    cand = cand[oracle.admissible(P.kappa, h, cand)]
-    par = -((-cand) // 2)  # ceil(o / 2): parent offset for target octant 0
-    cand = cand[~oracle.admissible(P.kappa, TT.side(level - 1), par)]
-    groups = min(groups, cand.shape[0])
-    pick = cand[rng.choice(cand.shape[0], groups, replace=False)]
-    src_index = {tuple(c): i for i, c in enumerate(TS.coords[level])}
-    t_mat, t_all, n_blocks = [], [], 0
-    K = (P.m + 1) ** 3
-    start = time.perf_counter()
-    for o in pick:
-        tc = TT.coords[level]
-        octant0 = np.all(tc % 2 == 0, axis=1)  # targets whose parent pair was refined
-        srcs = [src_index.get(tuple(x)) for x in (tc[octant0] - o)]
-        n = sum(1 for s in srcs if s is not None)
-        c = dirs.vectors(level)[int(dirs.dir_index(level, o))]
-        M = rng.standard_normal((n, K)) + 1j * rng.standard_normal((n, K))
-        t0 = time.perf_counter()
-        coupling_matrix(P.m, h, o, P.kappa, c)
-        t1 = time.perf_counter()
-        apply_coupling(P.m, h, o, P.kappa, c, M)
-        t2 = time.perf_counter()
-        t_mat.append(t1 - t0)
-        t_all.append(t2 - t1)
-        n_blocks += n
-    sample_s = time.perf_counter() - start
-    per_matrix = float(np.mean(t_mat))
-    # apply_coupling forms the matrix again: its time, measured apart, is
-    # taken off (never below zero, which timer noise allows on tiny samples)
-    per_block = max(sum(t_all) - sum(t_mat), 0.0) / max(n_blocks, 1)
-    t_full = stats["n_stored_couplings"] * per_matrix + stats["n_couplings"] * per_block
-    return {"value": 1.0 / t_full, "unit": "matvecs/s", "cores": int(cores), "kind": "oracle",
-            "sample": (f"oracle coupling step (the >99% of Alg. 4's arithmetic here) on "
-                       f"{groups} seeded level-{level} offset groups, {n_blocks} blocks, "
-                       f"{sample_s:.1f} s; scaled to N_SC={stats['n_stored_couplings']} "
-                       f"matrices + N_C={stats['n_couplings']} blocks = {t_full:.0f} s "
-                       f"per matvec (S2M/M2M/L2L/L2T/near field not counted)")}
+    sub_side = side / sub_div
+    hi = lo + sub_side
+    inT = np.all((P.points_T > lo) & (P.points_T <= hi), axis=1)
+    inS = np.all((P.points_S > lo) & (P.points_S <= hi), axis=1)
+    levels = P.levels - int(round(np.log2(sub_div)))
+    box = tuple(lo) + tuple(hi)
+    t0 = time.perf_counter()
+    plan = oracle.build(P.points_T[inT], P.points_S[inS], P.kappa, box, levels, P.m)
+    build_s = time.perf_counter() - t0
+    oracle.matvec(plan, P.v[inS])
+    tm = dict(plan.timings)
+    st = oracle.structure(plan)
+    nc_sub = sum(int(st[f"nc{l}"][0]) for l in range(levels + 1))
+    nsc_sub = sum(int(st[f"off{l}"].shape[0]) for l in range(levels + 1))
+    # time of one coupling matrix (its K^2 kernel evaluations), apart from the products
+    l_hf = plan.l_hf
+    lv = max(l for l in range(levels + 1) if int(st[f"nc{l}"][0]) > 0)
+    offs = st[f"off{lv}"][:8]
+    dirs = oracle.DirectionSets(l_hf, levels)
+    t1 = time.perf_counter()
+    for o in offs:
+        coupling_matrix(P.m, plan.side(lv), o, P.kappa,
+                        dirs.vectors(lv)[int(dirs.dir_index(lv, o))])
+    per_matrix = (time.perf_counter() - t1) / max(len(offs), 1)
+    per_block = max(tm["m2l"] - nsc_sub * per_matrix, 0.0) / max(nc_sub, 1)
+    # work counts: sample (oracle plan) and whole workload (GPU plan)
+    off = P.levels - levels
+    nbS_sub = [int(plan.TS.keys[l].shape[0]) for l in range(levels + 1)]
+    nbT_sub = [int(plan.TT.keys[l].shape[0]) for l in range(levels + 1)]
+    nd_full = shape["nd"]
+    lm = shape["l_min"]
+
+    def boxdirs(nb, lvl_of, first, last):
+        return sum(nb[l] * nd_full[lvl_of(l)] for l in range(first, last))
+
+    sub = {"s2m": int(inS.sum()), "l2t": int(inT.sum()),
+           "m2m": boxdirs(nbS_sub, lambda l: l + off, max(lm - off, 0), levels),
+           "l2l": boxdirs(nbT_sub, lambda l: l + off, max(lm - off, 0), levels),
+           "near": int(st["near_entries"][0])}
+    full = {"s2m": int(P.points_S.shape[0]), "l2t": int(P.points_T.shape[0]),
+            "m2m": boxdirs(shape["nbS"], lambda l: l, lm, P.levels),
+            "l2l": boxdirs(shape["nbT"], lambda l: l, lm, P.levels),
+            "near": int(stats["near_entries"])}
+    phases = {}
+    for k in ("s2m", "m2m", "l2l", "l2t", "near"):
+        phases[k] = {"sample_s": tm[k], "sample_units": sub[k], "full_units": full[k],
+                     "extrapolated_s": tm[k] * full[k] / max(sub[k], 1)}
+    m2l_full = stats["n_stored_couplings"] * per_matrix + stats["n_couplings"] * per_block
+    phases["m2l"] = {"sample_s": tm["m2l"], "sample_blocks": nc_sub, "sample_matrices": nsc_sub,
+                     "s_per_matrix": per_matrix, "s_per_block": per_block,
+                     "full_blocks": int(stats["n_couplings"]),
+                     "full_matrices": int(stats["n_stored_couplings"]),
+                     "extrapolated_s": m2l_full}
+    total = sum(ph["extrapolated_s"] for ph in phases.values())
+    return {"value": 1.0 / total, "unit": "matvecs/s", "cores": int(cores), "kind": "oracle",
+            "sample": (f"oracle Alg. 4 run whole on the workload's points in the sub-cube "
+                       f"(0,{sub_side:g}]^3 ({int(inT.sum())} targets, {int(inS.sum())} "
+                       f"sources, {levels} levels: the same kappa, m and box sizes), "
+                       f"{tm['total']:.1f} s measured (+{build_s:.1f} s set-up); each phase "
+                       f"scaled by its work count to the whole workload: {total:.0f} s per "
+                       f"matvec"),
+            "measured_s": tm["total"], "extrapolated_s_per_matvec": total, "phases": phases}
 
 
 def batched(steps: int, compact: int = 1) -> dict:
@@ -307,7 +333,8 @@ def main():
     t0 = time.perf_counter()
     budget = int(args.bank_budget_gb * 1e9)
     plan = F.Plan(pt, ps, P.kappa, P.box, P.levels, P.m, precision=args.precision,
-                  bank_budget=budget, tune={"compact": args.compact})
+                  bank_budget=budget,
+                  tune={"compact": args.compact, **({"nb": args.nb} if args.nb else {})})
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t0
     stats = plan.stats()
@@ -330,13 +357,16 @@ def main():
            "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
            "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
            "vs_baseline": None,
-           "dtype": {"fp32": "f32", "fp64": "f64", "bf16x3": "bf16"}[args.precision],
+           "dtype": {"fp32": "f32", "fp64": "f64", "bf16x3": "bf16", "bf16x6": "bf16"}[
+               args.precision],
            "data": "synthetic",
            "config": {"workload": describe(P),
                       "precision": {
                           "fp32": "FP32 coupling products on MFMA, FP64 phases, transfers, "
                                   "near field and sums into y",
                           "bf16x3": "BF16 hi/lo split coupling products (3 per real "
+                                    "product) on MFMA with FP32 sums, FP64 elsewhere",
+                          "bf16x6": "BF16 hi/mid/lo split coupling products (6 per real "
                                     "product) on MFMA with FP32 sums, FP64 elsewhere",
                           "fp64": "FP64 throughout"}[args.precision]}}
     out["roofline"] = {"bound": "mfma", "kernel": M2L_KERNEL[args.precision],
@@ -348,7 +378,8 @@ def main():
     out["hbm_phases"] = hbm_phases(shape, out["phase_ms"], (P.m + 1) ** 3, P.points_T.shape[0],
                                    P.points_S.shape[0], args.precision != "fp64")
     out["setup_s"] = setup_s
-    out["plan"] = {k: stats[k] for k in ("n_couplings", "n_stored_couplings", "m2l_columns",
+    out["plan"] = {k: stats[k] for k in ("n_couplings", "n_stored_couplings", "n_bank_matrices",
+                                         "m2l_columns",
                                          "near_entries", "device_bytes", "l_hf", "l_min")}
     out["plan"]["bank"] = (f"generated per matvec into a {args.bank_budget_gb:g} GB workspace"
                            if budget else "resident")
@@ -380,32 +411,35 @@ def main():
                 np.linalg.norm(y_plain[rows] - yo) / np.linalg.norm(yo))
         print(f"[bench] fp64 plain: {pms:.1f} ms/matvec", file=sys.stderr, flush=True)
 
-    if args.bf16_steps > 0 and args.precision != "bf16x3":
-        bf = F.Plan(pt, ps, P.kappa, P.box, P.levels, P.m, precision="bf16x3",
+    for split in ("bf16x3", "bf16x6"):
+        if args.bf16_steps <= 0 or args.precision == split:
+            continue
+        bf = F.Plan(pt, ps, P.kappa, P.box, P.levels, P.m, precision=split,
                     bank_budget=budget)
-        bwall, bph = time_plan(bf, v, y, args.bf16_steps, min(args.warmup, 1), "bf16x3")
+        bwall, bph = time_plan(bf, v, y, args.bf16_steps, min(args.warmup, 1), split)
         y_bf = y.cpu().numpy()
         bf.close()
         del bf
         bms = 1000.0 * bwall / args.bf16_steps
         bm2l = float(np.mean([p["m2l"] for p in bph]))
         alg = flops / (bm2l * 1e-3) / 1e12
-        out["bf16x3"] = {"value": 1000.0 / bms, "ms_per_step": bms, "steps": args.bf16_steps,
-                         "m2l_ms": bm2l, "m2l_tflops_algorithmic": alg,
-                         "m2l_tflops_issued": 3.0 * alg,
-                         "frac_of_bf16_peak_issued": 3.0 * alg / PEAK_TFLOPS["bf16x3"],
-                         "speedup_vs_mixed": ms_per_step / bms}
+        npr = SPLIT_PRODUCTS[split]
+        out[split] = {"value": 1000.0 / bms, "ms_per_step": bms, "steps": args.bf16_steps,
+                      "m2l_ms": bm2l, "m2l_tflops_algorithmic": alg,
+                      "m2l_tflops_issued": npr * alg,
+                      "frac_of_bf16_peak_issued": npr * alg / PEAK_TFLOPS[split],
+                      "speedup_vs_mixed": ms_per_step / bms}
         if os.path.exists(golden):
             g = np.load(golden)
-            out["bf16x3"]["rel_l2_err_vs_oracle"] = float(
+            out[split]["rel_l2_err_vs_oracle"] = float(
                 np.linalg.norm(y_bf[rows] - yo) / np.linalg.norm(yo))
-            if "y_bf16x3" in g.files:
-                out["bf16x3"]["emulated_rel_l2_err"] = float(
-                    np.linalg.norm(g["y_bf16x3"] - yo) / np.linalg.norm(yo))
+            if f"y_{split}" in g.files:
+                out[split]["emulated_rel_l2_err"] = float(
+                    np.linalg.norm(g[f"y_{split}"] - yo) / np.linalg.norm(yo))
         if y_plain is not None:
-            out["bf16x3"]["rel_l2_err_vs_plain_gpu"] = float(
+            out[split]["rel_l2_err_vs_plain_gpu"] = float(
                 np.linalg.norm(y_bf - y_plain) / np.linalg.norm(y_plain))
-        print(f"[bench] bf16x3: {bms:.1f} ms/matvec, M2L {bm2l:.1f} ms", file=sys.stderr,
+        print(f"[bench] {split}: {bms:.1f} ms/matvec, M2L {bm2l:.1f} ms", file=sys.stderr,
               flush=True)
 
     if args.batch_steps > 0:
@@ -414,7 +448,7 @@ def main():
         out["batched"] = batched(args.batch_steps, args.compact)
 
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(P, stats, args.cpu_groups)
+        out["cpu_baseline"] = cpu_baseline(P, stats, shape, args.cpu_sub)
     print(json.dumps(out), flush=True)
 
 

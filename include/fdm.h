@@ -43,7 +43,9 @@ typedef struct fdm_plan fdm_plan;
 typedef enum {
   FDM_PREC_FP64 = 0,   /* plain: FP64 matrix-core products, FP64 sums      */
   FDM_PREC_FP32 = 1,   /* mixed: FP32 operands and matrix-core accumulation */
-  FDM_PREC_BF16X3 = 2  /* mixed: BF16 hi/lo split, 3 products, FP32 sums   */
+  FDM_PREC_BF16X3 = 2, /* mixed: BF16 hi/lo split, 3 products, FP32 sums   */
+  FDM_PREC_BF16X6 = 3  /* mixed: BF16 hi/mid/lo split of FP64 operands, the
+                          6 part products of order <= 2, FP32 sums        */
 } fdm_precision;
 
 typedef enum {
@@ -122,7 +124,10 @@ int fdm_build_tree_ex(const double* points_T, int64_t n_T,
  * changes the grouping of the FP32 partial sums (the FP64 path is summed in
  * the same order for both nb); compaction skips zero columns only and
  * leaves every partial sum and flush point as it is.  A zero
- * fdm_options.tune.nb selects the defaults {64, 1, 1, 0, 1}.
+ * fdm_options.tune.nb selects the defaults {64, 1, 1, 0, 1}, or {32, 1, 1, 0,
+ * 1} for FDM_PREC_BF16X6, whose 64-target items need more registers than a
+ * workgroup of 11 or 12 waves leaves them (their spills make them slower
+ * than 32-target items; compaction needs 64-target items and is then off).
  */
 typedef struct {
   int32_t nb;
@@ -147,12 +152,21 @@ typedef struct {
  *                     in a batch (which brings its own workspace).
  *  tune               initial launch shape (NULL-equivalent: nb = 0 picks
  *                     the defaults {64, 1, 1, 0, 1}).
+ *  full_bank          0: a resident FP64 or FP32 bank stores one matrix per
+ *                     pair of offsets (o, -o) and applies the matrix of -o
+ *                     as the transpose of that of o (A_{-o} = A_o^T: the
+ *                     coupling function is symmetric and the direction map
+ *                     odd), halving the bank; 1: one matrix per offset.
+ *                     Streamed and BF16 split banks always hold one matrix
+ *                     per offset.  Results agree to rounding (the k sums of
+ *                     transposed matrices run in another order).
  */
 typedef struct {
   int32_t precision;
   int32_t l_hf;
   int64_t bank_budget_bytes;
   fdm_tune tune;
+  int32_t full_bank;
 } fdm_options;
 
 /* fdm_build_tree with options (opts host, not NULL). */
@@ -238,7 +252,10 @@ typedef struct {
   int32_t l_hf, l_min;          /* l_min: coarsest level with a coupling */
   int64_t n_couplings;          /* N_C: admissible blocks                  */
   int64_t n_stored_couplings;   /* N_SC: distinct (level, offset) used     */
-  int64_t n_bank_matrices;      /* matrices held (>= N_SC)                 */
+  int64_t n_bank_matrices;      /* coupling matrices in the resident bank
+                                   (one per admissible offset, or one per
+                                   pair (o, -o), see full_bank), or, for a
+                                   streamed bank, generated per matvec     */
   int64_t near_pairs;           /* inadmissible leaf blocks                */
   int64_t near_entries;         /* sum of #t * #s over inadmissible blocks  */
   int64_t m2l_columns;          /* coupling products issued by the M2L

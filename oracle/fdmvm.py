@@ -151,27 +151,77 @@ def _chunks(counts, limit):
     return out
 
 
+def _widen(x: np.ndarray) -> np.ndarray:
+    """``x`` as complex128; zero rows are not copied (so that a large array
+    whose pages were never written stays unbacked)."""
+    if x.dtype == np.complex128:
+        return x
+    y = np.zeros(x.shape, dtype=np.complex128)
+    nz = np.flatnonzero(np.any(x != 0, axis=tuple(range(1, x.ndim))))
+    y[nz] = x[nz]
+    return y
+
+
+def _coupling_level(plan: Plan, level: int, mom_level, loc_level, m2l: str):
+    """Step 4 of Alg. 4 on one level: every admissible block (t, s) of the
+    level adds ``A_{c, t x s} v~_{s,c}`` to ``g~_{t,c}``, blocks grouped by
+    offset (Sect. 2.7), groups in ascending offset order."""
+    TT, TS, BT, dirs = plan.TT, plan.TS, plan.BT, plan.dirs
+    t, s = BT.adm_t[level], BT.adm_s[level]
+    if t.size == 0:
+        return
+    o = TT.coords[level][t] - TS.coords[level][s]
+    c = plan.cdir[level]
+    cv = dirs.vectors(level)
+    h = plan.side(level)
+    uo, inv = np.unique(o, axis=0, return_inverse=True)
+    inv = inv.reshape(-1)
+    order = np.argsort(inv, kind="stable")
+    bounds = np.concatenate(([0], np.cumsum(np.bincount(inv, minlength=uo.shape[0]))))
+    for gi in range(uo.shape[0]):
+        idx = order[bounds[gi]:bounds[gi + 1]]
+        cg = c[idx[0]]
+        loc_level[t[idx], cg] += apply_coupling(plan.m, h, uo[gi], plan.kappa, cv[cg],
+                                                mom_level[s[idx], cg], m2l)
+
+
 def matvec(plan: Plan, v, chunk_points: int = 65536, keep: bool = False,
-           m2l: str = "fp64") -> np.ndarray:
+           m2l="fp64", chunk_boxes: int = 8192):
     """Alg. 4: ``g ~= A v`` in the user's target order (complex128).
 
     ``m2l`` other than ``"fp64"`` emulates a reduced-precision coupling step
     (see ``oracle.emulate``) or, as ``"aca:<eps>"``, applies the coupling
     matrices compressed by ACA (``oracle.lowrank``); the default is the
-    plain FP64 algorithm.
+    plain FP64 algorithm.  A sequence of such modes returns one result per
+    mode, sharing the forward transformation (steps 1-3).
+
+    Memory: the coupling step of a level runs as soon as that level's
+    moments exist, and the moments of a level are dropped once its coupling
+    step and its parents' M2M have read them (``keep`` holds them all).
+    Each level's coupling step reads only its own moments and writes only
+    its own locals, which the backward transformation reads after every
+    coupling step has run, so this is the same arithmetic in the same order
+    as running all of step 3 before all of step 4.  M2M and L2L take the
+    boxes ``chunk_boxes`` parents at a time (per-parent sums unchanged).
     """
+    single = isinstance(m2l, str)
+    modes = [m2l] if single else list(m2l)
     t0 = time.perf_counter()
     TT, TS, BT, dirs = plan.TT, plan.TS, plan.BT, plan.dirs
     p, m, K, kappa = plan.levels, plan.m, plan.K, plan.kappa
     v = np.asarray(v, dtype=np.complex128).reshape(-1)
     if v.shape[0] != TS.n:
         raise ValueError("v has the wrong length")
-    g_tree = np.zeros(TT.n, dtype=np.complex128)
     if TT.n == 0 or TS.n == 0:
-        return np.zeros(TT.n, dtype=np.complex128) if plan.rows is None \
+        z = np.zeros(TT.n, dtype=np.complex128) if plan.rows is None \
             else np.zeros(plan.rows.shape[0], dtype=np.complex128)
+        return z if single else [z.copy() for _ in modes]
     vt = v[TS.perm]
     Eref = transfer_reference(m)
+    loc = {mode: [np.zeros((plan.DT[l] | plan.DhT[l]).shape + (K,),
+                           dtype=emulate.accumulate_dtype(mode)) for l in range(p + 1)]
+           for mode in modes}
+    t_m2l = 0.0
 
     # --- S2M (leaves of T_S) ----------------------------------------------
     mom = [None] * (p + 1)
@@ -192,141 +242,134 @@ def matvec(plan: Plan, v, chunk_points: int = 65536, keep: bool = False,
             mom[p][lv, c] = np.add.reduceat(contrib, seg, axis=0)
     plan.timings["s2m"] = time.perf_counter() - t0
 
-    # --- M2M (levels p-1 .. 0) ---------------------------------------------
+    # --- M2M (levels p-1 .. 0), each level's coupling step once its moments
+    # --- exist (step 4 per level; see the docstring) -------------------------
     t1 = time.perf_counter()
     for level in range(p - 1, -1, -1):
         need = plan.DS[level] | plan.DhS[level]
         mom[level] = np.zeros(need.shape + (K,), dtype=np.complex128)
-        if not need.any():
-            continue
-        par_dir = dirs.parent_index(level)
-        cv, cv1 = dirs.vectors(level), dirs.vectors(level + 1)
-        for c in range(need.shape[1]):
-            parents = np.flatnonzero(need[:, c])
-            if parents.size == 0:
-                continue
-            ch, owner = _segments(TS.child_start[level][parents],
-                                  TS.child_count[level][parents])
-            cp = par_dir[c]
-            Ed = directional_part(TS.lo[level + 1][ch], TS.hi[level + 1][ch],
-                                  m, kappa, cv[c], cv1[cp])
-            w = np.conj(Ed) * mom[level + 1][ch, cp]  # (E^d)^* v~_{s',c'}
-            octant = TS.keys[level + 1][ch] & 7
-            contrib = np.empty_like(w)
-            for q in range(8):
-                sel = octant == q
-                if sel.any():
-                    contrib[sel] = w[sel] @ Eref[q]  # rows of E_{s'}^T w
-            seg = np.concatenate(([0], np.cumsum(TS.child_count[level][parents])[:-1]))
-            mom[level][parents, c] = np.add.reduceat(contrib, seg, axis=0)
-    plan.timings["m2m"] = time.perf_counter() - t1
-
-    # --- M2L ----------------------------------------------------------------
+        if need.any():
+            par_dir = dirs.parent_index(level)
+            cv, cv1 = dirs.vectors(level), dirs.vectors(level + 1)
+            for c in range(need.shape[1]):
+                all_parents = np.flatnonzero(need[:, c])
+                cp = par_dir[c]
+                for a in range(0, all_parents.size, chunk_boxes):
+                    parents = all_parents[a:a + chunk_boxes]
+                    ch, owner = _segments(TS.child_start[level][parents],
+                                          TS.child_count[level][parents])
+                    Ed = directional_part(TS.lo[level + 1][ch], TS.hi[level + 1][ch],
+                                          m, kappa, cv[c], cv1[cp])
+                    w = np.conj(Ed) * mom[level + 1][ch, cp]  # (E^d)^* v~_{s',c'}
+                    octant = TS.keys[level + 1][ch] & 7
+                    contrib = np.empty_like(w)
+                    for q in range(8):
+                        sel = octant == q
+                        if sel.any():
+                            contrib[sel] = w[sel] @ Eref[q]  # rows of E_{s'}^T w
+                    seg = np.concatenate(([0], np.cumsum(TS.child_count[level][parents])[:-1]))
+                    mom[level][parents, c] = np.add.reduceat(contrib, seg, axis=0)
+        t2 = time.perf_counter()
+        for mode in modes:
+            _coupling_level(plan, level + 1, mom[level + 1], loc[mode][level + 1], mode)
+        t_m2l += time.perf_counter() - t2
+        if not keep:
+            mom[level + 1] = None
     t2 = time.perf_counter()
-    acc_dtype = emulate.accumulate_dtype(m2l)
-    loc = [np.zeros((plan.DT[l] | plan.DhT[l]).shape + (K,), dtype=acc_dtype)
-           for l in range(p + 1)]
-    for level in range(p + 1):
-        t, s = BT.adm_t[level], BT.adm_s[level]
-        if t.size == 0:
-            continue
-        o = TT.coords[level][t] - TS.coords[level][s]
-        c = plan.cdir[level]
-        cv = dirs.vectors(level)
-        h = plan.side(level)
-        uo, inv = np.unique(o, axis=0, return_inverse=True)
-        inv = inv.reshape(-1)
-        order = np.argsort(inv, kind="stable")
-        bounds = np.concatenate(([0], np.cumsum(np.bincount(inv, minlength=uo.shape[0]))))
-        for gi in range(uo.shape[0]):
-            idx = order[bounds[gi]:bounds[gi + 1]]
-            cg = c[idx[0]]
-            loc[level][t[idx], cg] += apply_coupling(m, h, uo[gi], kappa, cv[cg],
-                                                     mom[level][s[idx], cg], m2l)
-    loc = [x.astype(np.complex128) for x in loc]
-    plan.timings["m2l"] = time.perf_counter() - t2
+    for mode in modes:
+        _coupling_level(plan, 0, mom[0], loc[mode][0], mode)
+    t_m2l += time.perf_counter() - t2
+    if not keep:
+        mom[0] = None
+    plan.timings["m2l"] = t_m2l
+    plan.timings["m2m"] = time.perf_counter() - t1 - t_m2l
+    for mode in modes:
+        loc[mode] = [_widen(x) for x in loc[mode]]
 
-    # --- L2L (levels 0 .. p-1) ---------------------------------------------
-    t3 = time.perf_counter()
-    for level in range(p):
-        need = plan.DT[level] | plan.DhT[level]
-        if not need.any():
-            continue
-        par_dir = dirs.parent_index(level)
-        cv, cv1 = dirs.vectors(level), dirs.vectors(level + 1)
-        for c in range(need.shape[1]):
-            parents = np.flatnonzero(need[:, c])
-            if parents.size == 0:
-                continue
-            ch, owner = _segments(TT.child_start[level][parents],
-                                  TT.child_count[level][parents])
-            cp = par_dir[c]
-            gpar = loc[level][parents[owner], c]
-            octant = TT.keys[level + 1][ch] & 7
-            Eg = np.empty_like(gpar)
-            for q in range(8):
-                sel = octant == q
-                if sel.any():
-                    Eg[sel] = gpar[sel] @ Eref[q].T  # rows of E_{t'} g
-            Ed = directional_part(TT.lo[level + 1][ch], TT.hi[level + 1][ch],
-                                  m, kappa, cv[c], cv1[cp])
-            loc[level + 1][ch, cp] += Ed * Eg
-    plan.timings["l2l"] = time.perf_counter() - t3
-
-    # --- L2T (leaves of T_T) -----------------------------------------------
-    t4 = time.perf_counter()
     if plan.rows is not None:
         inv = np.empty(TT.n, dtype=np.int64)
         inv[TT.perm] = np.arange(TT.n)
         want = np.zeros(TT.n, dtype=bool)
         want[inv[plan.rows]] = True
-    need = plan.DT[p] | plan.DhT[p]
-    cvec = dirs.vectors(p)
-    for c in range(need.shape[1]):
-        leaves = np.flatnonzero(need[:, c])
-        for a, b in _chunks(TT.count[p][leaves], chunk_points):
-            lv = leaves[a:b]
-            slots, owner = _segments(TT.start[p][lv], TT.count[p][lv])
-            if plan.rows is not None:
-                sel = want[slots]
-                slots, owner = slots[sel], owner[sel]
-            x = TT.points[slots]
-            L = interpolation_rows(x, TT.lo[p][lv][owner], TT.hi[p][lv][owner], m)
-            ph = np.exp(1j * kappa * (x @ cvec[c]))
-            g_tree[slots] += ph * np.einsum("nk,nk->n", L, loc[p][lv[owner], c])
-    plan.timings["l2t"] = time.perf_counter() - t4
+    results = []
+    for mode in modes:
+        lm = loc[mode]
+        # --- L2L (levels 0 .. p-1) -----------------------------------------
+        t3 = time.perf_counter()
+        for level in range(p):
+            need = plan.DT[level] | plan.DhT[level]
+            if not need.any():
+                continue
+            par_dir = dirs.parent_index(level)
+            cv, cv1 = dirs.vectors(level), dirs.vectors(level + 1)
+            for c in range(need.shape[1]):
+                all_parents = np.flatnonzero(need[:, c])
+                cp = par_dir[c]
+                for a in range(0, all_parents.size, chunk_boxes):
+                    parents = all_parents[a:a + chunk_boxes]
+                    ch, owner = _segments(TT.child_start[level][parents],
+                                          TT.child_count[level][parents])
+                    gpar = lm[level][parents[owner], c]
+                    octant = TT.keys[level + 1][ch] & 7
+                    Eg = np.empty_like(gpar)
+                    for q in range(8):
+                        sel = octant == q
+                        if sel.any():
+                            Eg[sel] = gpar[sel] @ Eref[q].T  # rows of E_{t'} g
+                    Ed = directional_part(TT.lo[level + 1][ch], TT.hi[level + 1][ch],
+                                          m, kappa, cv[c], cv1[cp])
+                    lm[level + 1][ch, cp] += Ed * Eg
+        plan.timings["l2l"] = time.perf_counter() - t3
 
-    # --- near field -----------------------------------------------------------
-    t5 = time.perf_counter()
-    nt, ns = BT.near_t[p], BT.near_s[p]
-    if nt.size:
-        tslots, towner = _segments(TT.start[p][nt], TT.count[p][nt])
-        if plan.rows is not None:
-            sel = want[tslots]
-            tslots, towner = tslots[sel], towner[sel]
-        # every target slot meets every source slot of its pair's source box
-        srcs = ns[towner]
-        cnt = TS.count[p][srcs]
-        for a, b in _chunks(cnt, 4 * chunk_points):
-            ts = tslots[a:b]
-            sl, own = _segments(TS.start[p][srcs[a:b]], cnt[a:b])
-            tj = ts[own]
-            d = TT.points[tj] - TS.points[sl]
-            # f(x, y) = 0 exactly when the two points coincide (diagonal)
-            same = np.all(TT.points[tj] == TS.points[sl], axis=1)
-            r = np.sqrt(np.sum(d * d, axis=1))
-            r[same] = 0.0
-            np.add.at(g_tree, tj, helmholtz(r, kappa) * vt[sl])
-    plan.timings["near"] = time.perf_counter() - t5
+        # --- L2T (leaves of T_T) -------------------------------------------
+        t4 = time.perf_counter()
+        g_tree = np.zeros(TT.n, dtype=np.complex128)
+        need = plan.DT[p] | plan.DhT[p]
+        cvec = dirs.vectors(p)
+        for c in range(need.shape[1]):
+            leaves = np.flatnonzero(need[:, c])
+            for a, b in _chunks(TT.count[p][leaves], chunk_points):
+                lv = leaves[a:b]
+                slots, owner = _segments(TT.start[p][lv], TT.count[p][lv])
+                if plan.rows is not None:
+                    sel = want[slots]
+                    slots, owner = slots[sel], owner[sel]
+                x = TT.points[slots]
+                L = interpolation_rows(x, TT.lo[p][lv][owner], TT.hi[p][lv][owner], m)
+                ph = np.exp(1j * kappa * (x @ cvec[c]))
+                g_tree[slots] += ph * np.einsum("nk,nk->n", L, lm[p][lv[owner], c])
+        plan.timings["l2t"] = time.perf_counter() - t4
+
+        # --- near field -------------------------------------------------------
+        t5 = time.perf_counter()
+        nt, ns = BT.near_t[p], BT.near_s[p]
+        if nt.size:
+            tslots, towner = _segments(TT.start[p][nt], TT.count[p][nt])
+            if plan.rows is not None:
+                sel = want[tslots]
+                tslots, towner = tslots[sel], towner[sel]
+            # every target slot meets every source slot of its pair's source box
+            srcs = ns[towner]
+            cnt = TS.count[p][srcs]
+            for a, b in _chunks(cnt, 4 * chunk_points):
+                ts = tslots[a:b]
+                sl, own = _segments(TS.start[p][srcs[a:b]], cnt[a:b])
+                tj = ts[own]
+                d = TT.points[tj] - TS.points[sl]
+                # f(x, y) = 0 exactly when the two points coincide (diagonal)
+                same = np.all(TT.points[tj] == TS.points[sl], axis=1)
+                r = np.sqrt(np.sum(d * d, axis=1))
+                r[same] = 0.0
+                np.add.at(g_tree, tj, helmholtz(r, kappa) * vt[sl])
+        plan.timings["near"] = time.perf_counter() - t5
+
+        g = np.zeros(TT.n, dtype=np.complex128)
+        g[TT.perm] = g_tree
+        results.append(g[plan.rows] if plan.rows is not None else g)
     plan.timings["total"] = time.perf_counter() - t0
     if keep:  # intermediate moments and locals (absolute phase form)
-        plan.debug = {"mom": mom, "loc": loc}
-
-    g = np.zeros(TT.n, dtype=np.complex128)
-    g[TT.perm] = g_tree
-    if plan.rows is not None:
-        return g[plan.rows]
-    return g
+        plan.debug = {"mom": mom, "loc": loc[modes[0]]}
+    return results[0] if single else results
 
 
 def sample_rows(points_T, points_S, v, kappa, box, levels, m, rows,

@@ -37,17 +37,19 @@ namespace fdm {
 namespace {
 
 // Coupling matrices in the layout of the plan precision: FP64 or FP32 split
-// re/im planes, k-major; or, for the BF16 split precision, each FP32-rounded
-// part split into hi = bf16(x) and lo = bf16(x - hi), four planes in
-// fragment order.  One workgroup per matrix (grid-stride over matrices);
-// matrix i of the list is written at position i of `bank`.
-template <class T>
+// re/im planes, k-major (PLANES 2); for the BF16 split precisions, each
+// FP32-rounded part split into hi = bf16(x) and lo = bf16(x - hi), four
+// planes (PLANES 4), or each FP64 part into hi, mid, lo (see bf16_split3),
+// six planes (PLANES 6), in fragment order.  One workgroup per matrix
+// (grid-stride over matrices); matrix i of the list is written at position
+// i of `bank`.
+template <class T, int PLANES>
 __global__ void __launch_bounds__(256) k_bank(const int32_t* __restrict__ info,
                                               int64_t n_mat, const BankLevel* __restrict__ lv,
                                               Interp ip, T* __restrict__ bank) {
   const int Kp = ip.Kp, K = ip.K, m1 = ip.m1;
   const int per = Kp * Kp;
-  constexpr int planes = std::is_same<T, uint16_t>::value ? 4 : 2;
+  constexpr int planes = PLANES;
   for (int64_t id = blockIdx.x; id < n_mat; id += gridDim.x) {
     const int32_t* in = info + 5 * id;
     const BankLevel L = lv[in[0]];
@@ -75,7 +77,19 @@ __global__ void __launch_bounds__(256) k_bank(const int32_t* __restrict__ info,
         re = cs * w;
         im = sn * w;
       }
-      if constexpr (std::is_same<T, uint16_t>::value) {
+      if constexpr (PLANES == 6) {
+        // six planes (re hi, mid, lo, im hi, mid, lo) in MFMA operand order
+        const int f = frag_index(row, kk, Kp);
+        uint16_t h, m, l;
+        bf16_split3(re, h, m, l);
+        base[f] = h;
+        base[per + f] = m;
+        base[2 * per + f] = l;
+        bf16_split3(im, h, m, l);
+        base[3 * per + f] = h;
+        base[4 * per + f] = m;
+        base[5 * per + f] = l;
+      } else if constexpr (PLANES == 4) {
         // four planes (re hi, re lo, im hi, im lo) in MFMA operand order
         const int f = frag_index(row, kk, Kp);
         const float fr = static_cast<float>(re), fi = static_cast<float>(im);
@@ -146,6 +160,7 @@ int m2l_threads(int Kp) { return std::max(2 * Kp, 512); }  // one wave per 32 ro
 int64_t m2l_resident_groups(int prec, int nb, int Kp, bool parts) {
   if (prec == FDM_PREC_FP64) return resident_f64(nb, Kp, parts);
   if (prec == FDM_PREC_BF16X3) return resident_bf16(nb, Kp, parts);
+  if (prec == FDM_PREC_BF16X6) return resident_bf16x6(nb, Kp, parts);
   return resident_f32(nb, Kp, parts);
 }
 
@@ -158,6 +173,8 @@ void launch_m2l_items(const M2LLaunch& L, int prec, int Kp, const TuneConfig& cf
     launch_items_f64(L, Kp, cfg.nb, persistent, head, s);
   else if (prec == FDM_PREC_BF16X3)
     launch_items_bf16(L, Kp, cfg.nb, persistent, head, s);
+  else if (prec == FDM_PREC_BF16X6)
+    launch_items_bf16x6(L, Kp, cfg.nb, persistent, head, s);
   else
     launch_items_f32(L, Kp, cfg.nb, persistent, head, s);
 }
@@ -167,11 +184,13 @@ void launch_bank_direct(const int32_t* info, int64_t n_mat, const BankLevel* lv,
   if (n_mat == 0) return;
   const unsigned grid = static_cast<unsigned>(std::min<int64_t>(n_mat, 1 << 16));
   if (prec == FDM_PREC_FP64)
-    k_bank<double><<<grid, 256, 0, s>>>(info, n_mat, lv, ip, static_cast<double*>(dst));
+    k_bank<double, 2><<<grid, 256, 0, s>>>(info, n_mat, lv, ip, static_cast<double*>(dst));
   else if (prec == FDM_PREC_BF16X3)
-    k_bank<uint16_t><<<grid, 256, 0, s>>>(info, n_mat, lv, ip, static_cast<uint16_t*>(dst));
+    k_bank<uint16_t, 4><<<grid, 256, 0, s>>>(info, n_mat, lv, ip, static_cast<uint16_t*>(dst));
+  else if (prec == FDM_PREC_BF16X6)
+    k_bank<uint16_t, 6><<<grid, 256, 0, s>>>(info, n_mat, lv, ip, static_cast<uint16_t*>(dst));
   else
-    k_bank<float><<<grid, 256, 0, s>>>(info, n_mat, lv, ip, static_cast<float*>(dst));
+    k_bank<float, 2><<<grid, 256, 0, s>>>(info, n_mat, lv, ip, static_cast<float*>(dst));
   FDM_LAUNCH("k_bank");
 }
 

@@ -13,6 +13,7 @@ int64_t bank_matrix_bytes(int prec, const Interp& ip) {
   const int64_t per = int64_t(ip.Kp) * ip.Kp;
   if (prec == FDM_PREC_FP64) return 2 * per * 8;
   if (prec == FDM_PREC_BF16X3) return 4 * per * 2;
+  if (prec == FDM_PREC_BF16X6) return 6 * per * 2;
   return 2 * per * 4;
 }
 
@@ -50,8 +51,9 @@ M2LDesc level_desc(const Plan& P, int l, const void* bank, int64_t bank_id0) {
   M2LDesc d{};
   d.gridS = P.S.grid[l].get();
   d.keyT = P.T.key[l].get();
-  d.mom = P.prec == FDM_PREC_FP64 ? static_cast<const void*>(Ld.mom64.get())
-                                  : static_cast<const void*>(Ld.mom32.get());
+  d.mom = P.prec == FDM_PREC_FP64    ? static_cast<const void*>(Ld.mom64.get())
+          : P.prec == FDM_PREC_BF16X6 ? static_cast<const void*>(Ld.mom16.get())
+                                      : static_cast<const void*>(Ld.mom32.get());
   d.out = Ld.loc64.get();  // FP64 coupling result, completed in place by L2L
   d.tgt_list = P.tgt_list.get();
   d.valid_off = P.valid_off.get();
@@ -67,7 +69,7 @@ M2LDesc level_desc(const Plan& P, int l, const void* bank, int64_t bank_id0) {
 
 const void* resident_bank(const Plan& P) {
   if (P.prec == FDM_PREC_FP64) return P.bank64.get();
-  if (P.prec == FDM_PREC_BF16X3) return P.bank16.get();
+  if (P.prec == FDM_PREC_BF16X3 || P.prec == FDM_PREC_BF16X6) return P.bank16.get();
   return P.bank32.get();
 }
 
@@ -282,6 +284,49 @@ void build_plan_schedule(Plan& P, hipStream_t s) {
   plan_launch_events(P);
 }
 
+namespace {
+
+// Direction index of -u for the direction u of index c on a level with nd
+// directions (Alg. 3 order: 4^k sub-faces per face, faces in -/+ pairs).
+int antipodal_direction(int c, int nd) {
+  if (nd == 1) return c;
+  const int per_face = nd / 6;
+  return ((c / per_face) ^ 1) * per_face + c % per_face;
+}
+
+// Whether every admissible offset of every coupling level has its partner
+// -o at the mirrored position of the sorted list (the admissible set is
+// symmetric and sorted lexicographically) with the antipodal direction:
+// then A_{-o} = A_o^T (the dir map is odd, readings of the face order).
+bool bank_pairs_mirror(const Plan& P) {
+  for (int l = std::max(P.l_min, 0); l <= P.levels; ++l) {
+    const LevelTable& T = P.tab[l];
+    const size_t n = T.adm.size();
+    if (n % 2) return false;
+    const int nd = direction_count(l, P.l_hf);
+    for (size_t i = 0; i < n; ++i) {
+      const Off& a = T.adm[i];
+      const Off& b = T.adm[n - 1 - i];
+      if (b.x != -a.x || b.y != -a.y || b.z != -a.z) return false;
+      if (T.dir[n - 1 - i] != antipodal_direction(T.dir[i], nd)) return false;
+    }
+  }
+  return true;
+}
+
+}  // namespace
+
+int32_t matrix_code(const Plan& P, int l, size_t i) {
+  const int64_t b = P.L[l].bank_base + static_cast<int64_t>(i);
+  if (!P.sym) return static_cast<int32_t>(b << 1);
+  // stored: the first half of each level's sorted list, in order
+  const int64_t n = static_cast<int64_t>(P.tab[l].adm.size());
+  const int64_t half_base = P.L[l].bank_base / 2;  // earlier levels hold n / 2 each
+  const int64_t j = static_cast<int64_t>(i);
+  return j < n / 2 ? static_cast<int32_t>((half_base + j) << 1)
+                   : static_cast<int32_t>(((half_base + n - 1 - j) << 1) | 1);
+}
+
 void launch_bank(Plan& P, hipStream_t s) {
   // bank id -> (level, offset, direction), for resident and streamed banks
   P.bank_info.clear();
@@ -292,26 +337,41 @@ void launch_bank(Plan& P, hipStream_t s) {
     for (size_t i = 0; i < T.adm.size(); ++i)
       P.bank_info.insert(P.bank_info.end(), {l, T.adm[i].x, T.adm[i].y, T.adm[i].z, T.dir[i]});
   }
+  P.sym = P.bank_budget == 0 && !P.full_bank &&
+          (P.prec == FDM_PREC_FP64 || P.prec == FDM_PREC_FP32) && bank_pairs_mirror(P);
+  P.n_bank_stored = 0;
   if (P.n_bank == 0 || P.bank_budget != 0) return;  // streamed: generated per matvec
   std::vector<BankLevel> bl(P.levels + 1);
   for (int l = 0; l <= P.levels; ++l) bl[l] = bank_level(P, l);
+  std::vector<int32_t> info;  // the stored matrices, in bank order
+  if (P.sym) {
+    for (int l = std::max(P.l_min, 0); l <= P.levels; ++l) {
+      const size_t n = P.tab[l].adm.size();
+      const int64_t b0 = P.L[l].bank_base;
+      info.insert(info.end(), P.bank_info.begin() + 5 * b0,
+                  P.bank_info.begin() + 5 * (b0 + static_cast<int64_t>(n / 2)));
+    }
+  } else {
+    info = P.bank_info;
+  }
+  P.n_bank_stored = static_cast<int64_t>(info.size() / 5);
   DevBuf<int32_t> d_info;
   DevBuf<BankLevel> d_bl;
-  to_device(d_info, P.bank_info, s, nullptr);
+  to_device(d_info, info, s, nullptr);
   to_device(d_bl, bl, s, nullptr);
-  const int64_t elems = P.n_bank * bank_matrix_bytes(P.prec, P.ip);
+  const int64_t elems = P.n_bank_stored * bank_matrix_bytes(P.prec, P.ip);
   void* dst = nullptr;
   if (P.prec == FDM_PREC_FP64) {
     P.bank64.alloc(elems / 8, &P.tally);
     dst = P.bank64.get();
-  } else if (P.prec == FDM_PREC_BF16X3) {
+  } else if (P.prec == FDM_PREC_BF16X3 || P.prec == FDM_PREC_BF16X6) {
     P.bank16.alloc(elems / 2, &P.tally);
     dst = P.bank16.get();
   } else {
     P.bank32.alloc(elems / 4, &P.tally);
     dst = P.bank32.get();
   }
-  launch_bank_direct(d_info.get(), P.n_bank, d_bl.get(), P.prec, P.ip, dst, s);
+  launch_bank_direct(d_info.get(), P.n_bank_stored, d_bl.get(), P.prec, P.ip, dst, s);
   FDM_HIP(hipStreamSynchronize(s));
 }
 
@@ -327,7 +387,7 @@ void build_m2l_work(Plan& P, hipStream_t s) {
     if (l < P.l_min) continue;
     for (size_t i = 0; i < T.adm.size(); ++i)
       offtab[Ld.bank_base + i] = make_int4(T.adm[i].x, T.adm[i].y, T.adm[i].z,
-                                           static_cast<int>(Ld.bank_base + i));
+                                           matrix_code(P, l, i));
   }
   for (int l = std::max(P.l_min, 0); l <= p; ++l) {
     const LevelTable& T = P.tab[l];

@@ -79,7 +79,10 @@ void plan_build(Plan& P, const double* pT, const double* pS, hipStream_t s) {
       const int64_t nt = P.T.nb[l] * int64_t(Ld.nd) * Kp;
       Ld.mom64.alloc(2 * ns, &P.tally);
       Ld.loc64.alloc(2 * nt, &P.tally);
-      if (mixed) Ld.mom32.alloc(2 * ns, &P.tally);
+      if (P.prec == FDM_PREC_BF16X6)
+        Ld.mom16.alloc(6 * ns, &P.tally);
+      else if (mixed)
+        Ld.mom32.alloc(2 * ns, &P.tally);
     }
   }
   // near-field offsets on the leaf level
@@ -279,12 +282,17 @@ int fdm_build_tree_opts(const double* points_T, int64_t n_T, const double* point
     if (!std::isfinite(kappa) || kappa < 0) fail(FDM_ERR_INVALID_ARG, "kappa must be finite and >= 0");
     if (levels < 0 || levels > 9) fail(FDM_ERR_INVALID_ARG, "levels must be in [0, 9]");
     if (m < 1 || m > 8) fail(FDM_ERR_INVALID_ARG, "m must be in [1, 8]");
-    if (precision < FDM_PREC_FP64 || precision > FDM_PREC_BF16X3)
+    if (precision < FDM_PREC_FP64 || precision > FDM_PREC_BF16X6)
       fail(FDM_ERR_INVALID_ARG, "unknown precision");
     if (l_hf < -2 || l_hf > levels) fail(FDM_ERR_INVALID_ARG, "l_hf out of range");
     if (opts->bank_budget_bytes < 0) fail(FDM_ERR_INVALID_ARG, "negative bank budget");
+    if (opts->full_bank != 0 && opts->full_bank != 1)
+      fail(FDM_ERR_INVALID_ARG, "full_bank must be 0 or 1");
     TuneConfig tune;
-    if (opts->tune.nb != 0) tune = check_tune(opts->tune);
+    if (opts->tune.nb != 0)
+      tune = check_tune(opts->tune);
+    else if (precision == FDM_PREC_BF16X6)
+      tune.nb = 32;  // its 64-target items run out of registers (see fdm.h)
     for (int d = 0; d < 3; ++d)
       if (!std::isfinite(box[d]) || !std::isfinite(box[d + 3]) || !(box[d + 3] > box[d]))
         fail(FDM_ERR_INVALID_ARG, "invalid box");
@@ -311,6 +319,7 @@ int fdm_build_tree_opts(const double* points_T, int64_t n_T, const double* point
       P.l_hf = l_hf;
       P.tune = tune;
       P.bank_budget = opts->bank_budget_bytes;
+      P.full_bank = opts->full_bank != 0;
       if (P.bank_budget > 0) {
         Interp ip{};
         ip.Kp = (K + 31) / 32 * 32;
@@ -481,7 +490,7 @@ int fdm_plan_stats(const fdm_plan* plan, fdm_stats* out) {
     st.l_min = P.l_min;
     st.n_couplings = P.n_couplings;
     st.n_stored_couplings = P.n_stored;
-    st.n_bank_matrices = P.n_bank;
+    st.n_bank_matrices = P.bank_budget == 0 ? P.n_bank_stored : P.n_bank;
     st.near_pairs = P.near_pairs;
     st.near_entries = P.near_entries;
     st.m2l_columns = issued_columns(P, P.tune);

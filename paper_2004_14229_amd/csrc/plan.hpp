@@ -54,7 +54,7 @@ struct M2LDesc {
   void* out;                 // FP64 result [nbT][nd][Kp] complex
   const int32_t* tgt_list;   // target boxes of the plan's items
   const int32_t* valid_off;  // bank ids of the plan's items' offsets
-  const int4* offtab;        // per bank id: offset x, y, z and bank id
+  const int4* offtab;        // per bank id: offset x, y, z, (matrix << 1) | transposed
   // bank id b is matrix b counted from `bank`; for a workspace holding a
   // range of ids this address lies before the workspace (never read there)
   const void* bank;
@@ -128,7 +128,10 @@ struct LevelData {
   DevBuf<int32_t> offs;   // adm offsets: x, y, z, bank id
   // moments / locals, complex, [nb][nd][Kp]
   DevBuf<double> mom64;   // FP64 moments (all precisions)
-  DevBuf<float> mom32;    // FP32 operand copy (mixed precisions)
+  DevBuf<float> mom32;    // FP32 operand copy (FP32, BF16X3)
+  // BF16X6 operand copy: per (box, direction) column and slab of 16 k, the
+  // six BF16 part planes (re hi, mid, lo, im hi, mid, lo) of 16 values
+  DevBuf<uint16_t> mom16;
   DevBuf<double> loc64;   // FP64 locals (coupling result + parent transfer)
 };
 
@@ -152,6 +155,11 @@ struct Plan {
   // bank_budget bytes during each matvec (streamed)
   int64_t n_bank = 0;
   int64_t bank_budget = 0;  // 0: resident
+  // resident FP64 / FP32 bank stored once per offset pair (o, -o): the
+  // matrix of -o is applied as the transpose of that of o (Sect. 2.7)
+  bool full_bank = false;   // option: store every matrix
+  bool sym = false;
+  int64_t n_bank_stored = 0;  // matrices in the resident bank
   DevBuf<double> bank64;
   DevBuf<float> bank32;
   DevBuf<uint16_t> bank16;
@@ -166,7 +174,9 @@ struct Plan {
   std::vector<M2LItem> base_items;  // desc = level, first = 1, in build order
   std::vector<int32_t> valid_off_h;
   DevBuf<int32_t> tgt_list, valid_off;
-  DevBuf<int4> offtab;  // per bank matrix: offset x, y, z and bank id
+  // per bank id: offset x, y, z and the matrix applied, (index << 1) | t:
+  // stored matrix `index` counted from the bank base, t = 1 transposed
+  DevBuf<int4> offtab;
   std::vector<M2LLaunch> sched;
   DevBuf<int32_t> heads;  // one queue head per launch
   bool sched_ready = false;
@@ -265,7 +275,8 @@ inline bool p2p_queue_supported(int prec, int Kp) {
 // Compacted coupling items exist in the FP32 and BF16 split kernels with 64
 // targets per item.
 inline bool compact_supported(int prec, int nb) {
-  return (prec == FDM_PREC_FP32 || prec == FDM_PREC_BF16X3) && nb == 64;
+  return (prec == FDM_PREC_FP32 || prec == FDM_PREC_BF16X3 || prec == FDM_PREC_BF16X6) &&
+         nb == 64;
 }
 // Matrix-core columns of one coupling step under cfg (zero padding included).
 int64_t issued_columns(const Plan& P, const TuneConfig& cfg);
@@ -277,9 +288,12 @@ void launch_items_f32(const M2LLaunch& L, int Kp, int nb, bool persistent, int32
                       hipStream_t s);
 void launch_items_bf16(const M2LLaunch& L, int Kp, int nb, bool persistent, int32_t* head,
                        hipStream_t s);
+void launch_items_bf16x6(const M2LLaunch& L, int Kp, int nb, bool persistent, int32_t* head,
+                         hipStream_t s);
 int64_t resident_f64(int nb, int Kp, bool parts);
 int64_t resident_f32(int nb, int Kp, bool parts);
 int64_t resident_bf16(int nb, int Kp, bool parts);
+int64_t resident_bf16x6(int nb, int Kp, bool parts);
 
 // launch-shape helpers of the C ABI (plan.hip)
 TuneConfig check_tune(const fdm_tune& t);

@@ -20,13 +20,30 @@ namespace fdm {
 
 namespace {
 
+// Three-part BF16 split of an FP64 value (hi = bf16(fp32(x)), then the same
+// of the remainders), as raw bits.
+__device__ __forceinline__ void split3_bits(double x, uint16_t& h, uint16_t& m, uint16_t& l) {
+  auto bits = [](float f) {
+    uint32_t u = __float_as_uint(f);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return static_cast<uint16_t>(u >> 16);
+  };
+  auto value = [](uint16_t b) { return double(__uint_as_float(uint32_t(b) << 16)); };
+  h = bits(static_cast<float>(x));
+  const double r1 = x - value(h);
+  m = bits(static_cast<float>(r1));
+  l = bits(static_cast<float>(r1 - value(m)));
+}
+
 // Write one coefficient vector (K values, zero padding up to Kp) in FP64 and,
-// if requested, as the FP32 operand copy; thread `lane` of T holds
-// coefficients lane + T i.
+// if requested, as the FP32 operand copy or as the split BF16 operand copy
+// (per slab of 16 coefficients, six planes of 16: re hi, mid, lo, im hi,
+// mid, lo); thread `lane` of T holds coefficients lane + T i.
 template <int T, int NPER>
 __device__ __forceinline__ void store_coeffs(const double2 (&acc)[NPER],
                                              double2* __restrict__ out64,
                                              float2* __restrict__ out32,
+                                             uint16_t* __restrict__ out16,
                                              int64_t base, int K, int Kp, int lane) {
 #pragma unroll
   for (int i = 0; i < (kMaxK + T - 1) / T + 1; ++i) {
@@ -36,6 +53,18 @@ __device__ __forceinline__ void store_coeffs(const double2 (&acc)[NPER],
                                               : make_double2(0.0, 0.0);
       out64[base + k] = val;
       if (out32) out32[base + k] = make_float2(float(val.x), float(val.y));
+      if (out16) {
+        uint16_t* d = out16 + 6 * base + 96 * (k / 16) + k % 16;
+        uint16_t h, m, l;
+        split3_bits(val.x, h, m, l);
+        d[0] = h;
+        d[16] = m;
+        d[32] = l;
+        split3_bits(val.y, h, m, l);
+        d[48] = h;
+        d[64] = m;
+        d[80] = l;
+      }
     }
   }
 }
@@ -81,7 +110,8 @@ __global__ void __launch_bounds__(64) k_s2m(
     const uint32_t* __restrict__ key, const int32_t* __restrict__ start,
     const int32_t* __restrict__ count, int64_t nb, int level, double lo0,
     double lo1, double lo2, double h, const double* __restrict__ dirvec, int nd,
-    double kappa, Interp ip, double2* __restrict__ mom, float2* __restrict__ mom32) {
+    double kappa, Interp ip, double2* __restrict__ mom, float2* __restrict__ mom32,
+    uint16_t* __restrict__ mom16) {
   __shared__ double lag[3][kMaxM1];
   const int lane = threadIdx.x;
   const int c = blockIdx.y;
@@ -121,7 +151,7 @@ __global__ void __launch_bounds__(64) k_s2m(
         }
       }
     }
-    store_coeffs<64>(acc, mom, mom32, (b * nd + c) * int64_t(Kp), K, Kp, lane);
+    store_coeffs<64>(acc, mom, mom32, mom16, (b * nd + c) * int64_t(Kp), K, Kp, lane);
   }
 }
 
@@ -132,7 +162,7 @@ __global__ void __launch_bounds__(kXT) k_m2m(
     const uint32_t* __restrict__ key, int64_t nb, int level, double h1,
     const double* __restrict__ dirvec, const double* __restrict__ dirvec1, int nd,
     int l_hf, double kappa, Interp ip, double2* __restrict__ mom,
-    float2* __restrict__ mom32) {
+    float2* __restrict__ mom32, uint16_t* __restrict__ mom16) {
   __shared__ double2 buf[2][kMaxK];
   __shared__ double2 ph[3][kMaxM1];
   const int lane = threadIdx.x;
@@ -178,7 +208,7 @@ __global__ void __launch_bounds__(kXT) k_m2m(
         }
       }
     }
-    store_coeffs<kXT>(acc, mom, mom32, (b * nd + c) * int64_t(Kp), K, Kp, lane);
+    store_coeffs<kXT>(acc, mom, mom32, mom16, (b * nd + c) * int64_t(Kp), K, Kp, lane);
   }
 }
 
@@ -227,7 +257,7 @@ void launch_s2m(Plan& P, hipStream_t s) {
                             P.S.key[p].get(), P.S.start[p].get(), P.S.count[p].get(), nb, p,
                             P.lo[0], P.lo[1], P.lo[2], Lp.h, Lp.dirvec.get(), Lp.nd,
                             P.kappa, P.ip, reinterpret_cast<double2*>(Lp.mom64.get()),
-                            reinterpret_cast<float2*>(Lp.mom32.get()));
+                            reinterpret_cast<float2*>(Lp.mom32.get()), Lp.mom16.get());
   FDM_LAUNCH("k_s2m");
 }
 
@@ -241,7 +271,7 @@ void launch_m2m(Plan& P, int level, hipStream_t s) {
                             P.S.grid[level + 1].get(), P.S.key[level].get(), nb, level,
                             L1.h, Lc.dirvec.get(), L1.dirvec.get(), Lc.nd, P.l_hf,
                             P.kappa, P.ip, reinterpret_cast<double2*>(Lc.mom64.get()),
-                            reinterpret_cast<float2*>(Lc.mom32.get()));
+                            reinterpret_cast<float2*>(Lc.mom32.get()), Lc.mom16.get());
   FDM_LAUNCH("k_m2m");
 }
 

@@ -22,7 +22,7 @@ FDM_OK = 0
 STATUS = {0: "FDM_OK", -1: "FDM_ERR_INVALID_ARG", -2: "FDM_ERR_POINT_OUTSIDE_BOX",
           -3: "FDM_ERR_UNSUPPORTED", -4: "FDM_ERR_OUT_OF_MEMORY", -5: "FDM_ERR_HIP",
           -6: "FDM_ERR_STATE"}
-PRECISION = {"fp64": 0, "fp32": 1, "bf16x3": 2}
+PRECISION = {"fp64": 0, "fp32": 1, "bf16x3": 2, "bf16x6": 3}
 
 _lib = None
 
@@ -45,14 +45,17 @@ class Tune(ctypes.Structure):
         return {name: getattr(self, name) for name, _ in self._fields_}
 
     @classmethod
-    def from_dict(cls, d: dict) -> "Tune":
-        """Fields missing from d take the library's defaults."""
-        return cls(*(int(d.get(name, cls.DEFAULTS[name])) for name, _ in cls._fields_))
+    def from_dict(cls, d: dict, precision: str = "fp64") -> "Tune":
+        """Fields missing from d take the library's defaults (32 targets per
+        item for the six-product BF16 split, 64 otherwise)."""
+        defaults = dict(cls.DEFAULTS, nb=32 if precision == "bf16x6" else 64)
+        return cls(*(int(d.get(name, defaults[name])) for name, _ in cls._fields_))
 
 
 class Options(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("l_hf", ctypes.c_int32),
-                ("bank_budget_bytes", ctypes.c_int64), ("tune", Tune)]
+                ("bank_budget_bytes", ctypes.c_int64), ("tune", Tune),
+                ("full_bank", ctypes.c_int32)]
 
 
 class Stats(ctypes.Structure):
@@ -195,10 +198,11 @@ class Plan:
 
     def __init__(self, points_T, points_S, kappa: float, box, levels: int, m: int,
                  precision: str = "fp64", l_hf: int | None = None, stream=None,
-                 bank_budget: int = 0, tune: dict | None = None):
+                 bank_budget: int = 0, tune: dict | None = None, full_bank: bool = False):
         box_arr = (ctypes.c_double * 6)(*[float(b) for b in box])
         opts = Options(PRECISION[precision], -2 if l_hf is None else int(l_hf),
-                       int(bank_budget), Tune.from_dict(tune) if tune else Tune())
+                       int(bank_budget), Tune.from_dict(tune, precision) if tune else Tune(),
+                       int(bool(full_bank)))
         h = ctypes.c_void_p()
         # the library synchronises the stream before returning
         with _OnStream(stream) as on:

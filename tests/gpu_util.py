@@ -32,3 +32,17 @@ def gpu_matvec(P, precision="fp64", plan=None):
 def rel(a, b):
     nb = np.linalg.norm(b)
     return np.linalg.norm(a - b) / (nb if nb else 1.0)
+
+
+def assert_close(a, b, tol, what=""):
+    """Relative l2 error at most tol, and every entry within tol times the
+    largest reference entry (a few wrong entries cannot hide in the norm)."""
+    a = np.asarray(a)
+    b = np.asarray(b)
+    err = rel(a, b)
+    assert err <= tol, f"{what} rel l2 {err:.3e} > {tol:.3e}"
+    scale = np.max(np.abs(b)) if b.size else 0.0
+    worst = np.max(np.abs(a - b)) if a.size else 0.0
+    assert worst <= tol * (scale if scale else 1.0), \
+        f"{what} max |diff| {worst:.3e} > {tol:.3e} * max |ref| {scale:.3e}"
+    return err

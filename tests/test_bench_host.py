@@ -53,13 +53,48 @@ def test_traffic_only_for_the_measured_kernel_source(bench, tmp_path, monkeypatc
     assert bench.traffic_for("k_m2l_f32", "w", 1.0) is None
 
 
-def test_cpu_baseline_on_a_small_workload(bench):
-    """The oracle leg of the benchmark runs on a sample and scales it to the
-    stated block and matrix counts (here those of a small workload)."""
+def _oracle_counts(P):
+    """Work counts of a whole problem from the oracle's own plan, in the
+    form bench.py takes them from the GPU plan."""
+    import oracle
+    plan = oracle.build(P.points_T, P.points_S, P.kappa, P.box, P.levels, P.m)
+    st = oracle.structure(plan)
+    nc = [int(st[f"nc{l}"][0]) for l in range(P.levels + 1)]
+    l_min = min([l for l in range(P.levels + 1) if nc[l]] or [P.levels + 1])
+    shape = {"nbS": [int(plan.TS.keys[l].shape[0]) for l in range(P.levels + 1)],
+             "nbT": [int(plan.TT.keys[l].shape[0]) for l in range(P.levels + 1)],
+             "nd": [int(plan.dirs.vectors(l).shape[0]) if l >= l_min else 1
+                    for l in range(P.levels + 1)],
+             "levels": P.levels, "l_min": l_min}
+    stats = {"n_couplings": sum(nc),
+             "n_stored_couplings": sum(int(st[f"off{l}"].shape[0]) for l in range(P.levels + 1)),
+             "near_entries": int(st["near_entries"][0])}
+    return shape, stats
+
+
+def test_cpu_baseline_whole_problem_is_not_scaled(bench):
+    """With the whole box as the sample, every phase's work count equals the
+    workload's, so each extrapolated phase time is the measured one."""
     import workloads as W
     P = W.config("uniform2k")
-    stats = {"n_stored_couplings": 1000, "n_couplings": 50000}
-    r = bench.cpu_baseline(P, stats, 1000)  # more groups than exist: all of them
-    assert r["kind"] == "oracle" and r["unit"] == "matvecs/s"
-    assert r["value"] > 0 and r["cores"] >= 1
-    assert "offset groups" in r["sample"]
+    shape, stats = _oracle_counts(P)
+    r = bench.cpu_baseline(P, stats, shape, sub_div=1)
+    assert r["kind"] == "oracle" and r["unit"] == "matvecs/s" and r["cores"] >= 1
+    for k, ph in r["phases"].items():
+        assert ph["extrapolated_s"] == pytest.approx(ph["sample_s"], rel=1e-9, abs=1e-12), k
+    assert r["extrapolated_s_per_matvec"] == pytest.approx(
+        sum(ph["sample_s"] for ph in r["phases"].values()))
+
+
+def test_cpu_baseline_sub_cube_sample(bench):
+    """The sample is the sub-cube (0, 1/2]^3 with one level less: its work
+    counts are a fraction of the workload's and scale up each phase."""
+    import workloads as W
+    P = W.config("uniform2k")
+    shape, stats = _oracle_counts(P)
+    r = bench.cpu_baseline(P, stats, shape, sub_div=2)
+    assert r["value"] > 0 and "sub-cube (0,0.5]^3" in r["sample"]
+    for k in ("s2m", "l2t", "near", "m2m", "l2l"):
+        ph = r["phases"][k]
+        assert 0 < ph["sample_units"] < ph["full_units"], k
+    assert r["phases"]["m2l"]["sample_blocks"] < stats["n_couplings"]

@@ -34,7 +34,7 @@ def _build(**kw):
     (dict(kappa=-1.0), -1), (dict(kappa=float("nan")), -1), (dict(prec=7), -1),
     (dict(n_T=-5), -1), (dict(l_hf=5, levels=3), -1),
     (dict(box=(0, 0, 0, 1, 1, 2)), -3), (dict(box=(0, 0, 0, 0, 1, 1)), -1),
-    (dict(m=7), -3), (dict(prec=3), -1), (dict(prec=-1), -1),
+    (dict(m=7), -3), (dict(prec=4), -1), (dict(prec=-1), -1),
     (dict(n_T=2 ** 30), -3), (dict(n_S=2 ** 30), -3), (dict(n_S=-1), -1),
 ])
 def test_invalid_arguments_are_rejected(kw, status):
@@ -52,11 +52,11 @@ def test_null_handles():
     assert L.fdm_plan_export(None, b"perm_T", None, 0, ctypes.byref(size)) == -1
 
 
-def _build_opts(nb=64, budget=0, prec=0, persistent=1, compact=1):
+def _build_opts(nb=64, budget=0, prec=0, persistent=1, compact=1, full_bank=0):
     L = F.lib()
     h = ctypes.c_void_p()
     box = (ctypes.c_double * 6)(0, 0, 0, 1, 1, 1)
-    opts = F.fdm.Options(prec, -2, budget, F.fdm.Tune(nb, persistent, 1, 0, compact))
+    opts = F.fdm.Options(prec, -2, budget, F.fdm.Tune(nb, persistent, 1, 0, compact), full_bank)
     st = L.fdm_build_tree_opts(None, 0, None, 0, 1.0, box, 3, 4, ctypes.byref(opts), None,
                                ctypes.byref(h))
     return st, h, L.fdm_last_error().decode()
@@ -64,7 +64,7 @@ def _build_opts(nb=64, budget=0, prec=0, persistent=1, compact=1):
 
 @pytest.mark.parametrize("kw", [dict(nb=48), dict(nb=0, budget=-1), dict(budget=1),
                                 dict(persistent=2), dict(prec=5), dict(compact=3),
-                                dict(compact=-1)])
+                                dict(compact=-1), dict(full_bank=2), dict(full_bank=-1)])
 def test_invalid_options_are_rejected(kw):
     st, h, msg = _build_opts(**kw)
     assert st == -1 and h.value is None and msg

@@ -12,7 +12,7 @@ import pytest
 
 import oracle
 import workloads as W
-from gpu_util import gpu_plan, rel, to_dev
+from gpu_util import assert_close, gpu_plan, rel, to_dev
 
 pytestmark = pytest.mark.gpu
 
@@ -37,13 +37,13 @@ def oracle_y(P):
     return _oracle_cache[key]
 
 
-def plan_y(P, precision="fp64", bank_budget=0, tune=None):
+def plan_y(P, precision="fp64", bank_budget=0, tune=None, full_bank=False):
     import torch
     import paper_2004_14229_amd as F
     pt = to_dev(P.points_T)
     ps = to_dev(P.points_S)
     with F.Plan(pt, ps, P.kappa, P.box, P.levels, P.m, precision=precision,
-                bank_budget=bank_budget, tune=tune) as plan:
+                bank_budget=bank_budget, tune=tune, full_bank=full_bank) as plan:
         y = plan.matvec(to_dev(P.v))
         torch.cuda.synchronize()
         return y.cpu().numpy(), plan.stats()
@@ -54,14 +54,14 @@ def small_batch(count=6, seed=41, m=5):
 
 
 @pytest.mark.parametrize("precision,tol", [("fp64", TOL_FP64), ("fp32", TOL_FP32),
-                                           ("bf16x3", 2e-5)])
+                                           ("bf16x3", 2e-5), ("bf16x6", TOL_FP32)])
 def test_every_launch_shape_matches_oracle(precision, tol):
     P = W.random_problem(301, 700, 650, 45.0, 4, 3)
     yo = oracle_y(P)
     ys = []
     for t in TUNES:
         y, _ = plan_y(P, precision, tune=t)
-        assert rel(y, yo) <= tol, t
+        assert_close(y, yo, tol, t)
         ys.append(y)
     if precision == "fp64":
         for y, t in zip(ys[1:], TUNES[1:]):
@@ -84,12 +84,33 @@ def test_streamed_bank_matches_oracle(precision, tol):
     for budget in (mat, 7 * mat, (n // 3) * mat):
         for t in (TUNES[0], TUNES[15], TUNES[-1]):
             y, st2 = plan_y(P, precision, bank_budget=budget, tune=t)
-            assert rel(y, yo) <= tol, (budget, t)
+            assert_close(y, yo, tol, (budget, t))
             assert st2["n_couplings"] == st["n_couplings"]
-    assert rel(y_res, yo) <= tol
+    assert_close(y_res, yo, tol)
 
 
-@pytest.mark.parametrize("precision,tol", [("fp32", TOL_FP32), ("bf16x3", 2e-5)])
+@pytest.mark.parametrize("precision,tol", [("fp64", TOL_FP64), ("fp32", TOL_FP32)])
+@pytest.mark.parametrize("m,levels", [(3, 4), (6, 3)])
+def test_symmetric_bank_matches_full_bank(precision, tol, m, levels):
+    """Resident banks holding one matrix per offset pair (o, -o), the matrix
+    of -o applied transposed (Sect. 2.7: A_{-o} = A_o^T), against banks
+    holding every matrix and against the oracle, in plain and compacted
+    launch shapes.  The bank halves; the results differ by rounding only
+    (transposed matrices are summed over k in another order)."""
+    P = W.random_problem(321 + m, 1500, 1400, 50.0, levels, m)
+    yo = oracle_y(P)
+    y_full, st_full = plan_y(P, precision, full_bank=True)
+    assert_close(y_full, yo, tol)
+    for t in (dict(nb=64, compact=0), dict(nb=64, compact=2), dict(nb=32, persistent=0)):
+        y_sym, st_sym = plan_y(P, precision, tune=t)
+        assert 2 * st_sym["n_bank_matrices"] == st_full["n_bank_matrices"]
+        assert st_sym["n_couplings"] == st_full["n_couplings"]
+        assert_close(y_sym, yo, tol, t)
+        assert_close(y_sym, y_full, tol, t)
+
+
+@pytest.mark.parametrize("precision,tol", [("fp32", TOL_FP32), ("bf16x3", 2e-5),
+                                           ("bf16x6", TOL_FP32)])
 @pytest.mark.parametrize("seed,nt,ns,kappa,levels,m,clustered", [
     (311, 700, 650, 45.0, 4, 3, False), (312, 3000, 2600, 60.0, 5, 3, True),
     (313, 1500, 1400, 30.0, 4, 5, False), (314, 90, 2000, 20.0, 4, 4, False)])
@@ -110,13 +131,14 @@ def test_compacted_columns_match_plain(seed, nt, ns, kappa, levels, m, clustered
     y1, st1 = plan_y(P, precision, tune=dict(base, compact=1))
     y2, st2 = plan_y(P, precision, tune=dict(base, compact=2))
     for y in (y0, y1, y2):
-        assert rel(y, yo) <= tol
+        assert_close(y, yo, tol)
     assert np.array_equal(y0, y2) and np.array_equal(y0, y1)
     assert st2["m2l_columns"] <= st1["m2l_columns"] <= st0["m2l_columns"]
     assert st1["n_couplings"] == st0["n_couplings"]
 
 
-@pytest.mark.parametrize("precision,tol", [("fp32", TOL_FP32), ("bf16x3", 2e-5)])
+@pytest.mark.parametrize("precision,tol", [("fp32", TOL_FP32), ("bf16x3", 2e-5),
+                                           ("bf16x6", TOL_FP32)])
 def test_compacted_columns_streamed_and_grid(precision, tol):
     """Compacted items split over streamed-bank launches (first part
     stores, later parts add), in grid and persistent launches."""
@@ -124,13 +146,14 @@ def test_compacted_columns_streamed_and_grid(precision, tol):
     yo = oracle_y(P)
     K = (P.m + 1) ** 3
     Kp = (K + 31) // 32 * 32
-    mat = Kp * Kp * 8  # FP32: 2 planes x 4 bytes; BF16: 4 planes x 2 bytes
+    # FP32: 2 planes x 4 bytes; BF16 split: 4 (x3) or 6 (x6) planes x 2 bytes
+    mat = Kp * Kp * (12 if precision == "bf16x6" else 8)
     y_ref, _ = plan_y(P, precision, tune=dict(nb=64, compact=0))
     for pers in (1, 0):
         for budget in (0, 3 * mat):
             y, _ = plan_y(P, precision, bank_budget=budget,
                           tune=dict(nb=64, persistent=pers, compact=2))
-            assert rel(y, yo) <= tol, (pers, budget)
+            assert_close(y, yo, tol, (pers, budget))
             if budget == 0:
                 assert np.array_equal(y, y_ref), pers
 
@@ -139,7 +162,7 @@ def test_streamed_bank_uniform2k_fp32():
     P = W.config("uniform2k")
     yo = oracle_y(P)
     y, st = plan_y(P, "fp32", bank_budget=50 * 128 * 128 * 8)
-    assert rel(y, yo) <= TOL_FP32
+    assert_close(y, yo, TOL_FP32)
 
 
 def _batch_vectors(probs, c64):
@@ -152,7 +175,7 @@ def _batch_check(probs, ys, tol, c64):
     for P, y in zip(probs, ys):
         yo = oracle_y(P)
         yy = y.cpu().numpy().astype(np.complex128)
-        assert rel(yy, yo) <= tol + (1e-7 if c64 else 0.0), P.name
+        assert_close(yy, yo, tol + (1e-7 if c64 else 0.0), P.name)
 
 
 @pytest.mark.parametrize("precision,tol,c64,budget", [
@@ -230,7 +253,7 @@ def test_batch_with_empty_problems():
         ys = b.matvec(_batch_vectors(probs, False))
         torch.cuda.synchronize()
         for P, y in zip(probs[:3], ys[:3]):
-            assert rel(y.cpu().numpy(), oracle_y(P)) <= TOL_FP64
+            assert_close(y.cpu().numpy(), oracle_y(P), TOL_FP64)
         assert ys[3].shape == (50,) and torch.all(ys[3] == 0)
         assert ys[4].shape == (0,)
     for p in plans:
@@ -264,10 +287,10 @@ def test_autotune_plan_and_batch():
     torch.cuda.synchronize()
     assert len(ms) == 8 and all(t > 0 for t in ms)
     assert best == plan.get_tune()
-    assert rel(y.cpu().numpy(), yo) <= TOL_FP32
+    assert_close(y.cpu().numpy(), yo, TOL_FP32)
     y2 = plan.matvec(to_dev(P.v))
     torch.cuda.synchronize()
-    assert rel(y2.cpu().numpy(), yo) <= TOL_FP32
+    assert_close(y2.cpu().numpy(), yo, TOL_FP32)
     plan.close()
 
     probs = small_batch(count=4, seed=48)

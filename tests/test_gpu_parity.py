@@ -10,7 +10,7 @@ import pytest
 
 import oracle
 import workloads as W
-from gpu_util import gpu_matvec, gpu_plan, rel, to_dev
+from gpu_util import assert_close, gpu_matvec, gpu_plan, rel, to_dev
 
 pytestmark = pytest.mark.gpu
 
@@ -89,14 +89,14 @@ def test_fp64_matches_oracle(name):
     P = case(name)
     y, _ = gpu_matvec(P)
     yo = oracle.matvec(oracle_plan(P), P.v)
-    assert rel(y, yo) <= TOL_FP64
+    assert_close(y, yo, TOL_FP64)
 
 
 def test_fp64_uniform2k_and_dense():
     P = W.config("uniform2k")
     y, gp = gpu_matvec(P)
     yo = oracle.matvec(oracle_plan(P), P.v)
-    assert rel(y, yo) <= TOL_FP64
+    assert_close(y, yo, TOL_FP64)
     yd = oracle.dense_matvec(P.points_T, P.points_S, P.v, P.kappa)
     assert 1e-5 < rel(y, yd) < 2e-3  # the method's own approximation error
 
@@ -105,7 +105,7 @@ def test_fp64_paper_grid_k5():
     P = W.config("paper_k5")
     y, _ = gpu_matvec(P)
     yo = oracle.matvec(oracle_plan(P), P.v)
-    assert rel(y, yo) <= TOL_FP64
+    assert_close(y, yo, TOL_FP64)
 
 
 @pytest.mark.parametrize("seed,levels", [(331, 2), (332, 3)])
@@ -119,7 +119,7 @@ def test_fp64_large_uneven_leaves(seed, levels):
     counts = gp.export(f"count_T{levels}")
     assert counts.mean() >= 32 and counts.max() > 256
     yo = oracle.matvec(oracle_plan(P), P.v)
-    assert rel(y, yo) <= TOL_FP64
+    assert_close(y, yo, TOL_FP64)
 
 
 def test_moments_and_locals_match_oracle():
@@ -142,7 +142,7 @@ def test_moments_and_locals_match_oracle():
             b, c = np.nonzero(need)
             ph = np.exp(1j * P.kappa * np.sum(T.centres(l)[b] * cv[c], axis=1))
             want = arr[b, c] * ph[:, None]
-            assert rel(g[b, c], want) <= TOL_FP64, (kind, l)
+            assert_close(g[b, c], want, TOL_FP64, (kind, l))
 
 
 def test_fp32_within_bound():
@@ -150,7 +150,7 @@ def test_fp32_within_bound():
         P = case(name)
         y, _ = gpu_matvec(P, "fp32")
         yo = oracle.matvec(oracle_plan(P), P.v)
-        assert rel(y, yo) <= TOL_FP32, name
+        assert_close(y, yo, TOL_FP32, name)
 
 
 def test_fp32_uniform2k():
@@ -187,6 +187,30 @@ def test_bf16x3_uniform2k():
     assert err <= 4 * emulated and err <= 2e-5, (err, emulated)
 
 
+def bf16x6_errors(P):
+    y, _ = gpu_matvec(P, "bf16x6")
+    op = oracle_plan(P)
+    yo, ye = oracle.matvec(op, P.v, m2l=("fp64", "bf16x6"))
+    return rel(y, yo), rel(ye, yo), y, yo
+
+
+@pytest.mark.parametrize("name", ["highfreq", "m6", "laplace", "m1", "shifted_box"])
+def test_bf16x6_error_matches_emulation(name):
+    """Six-product BF16 split: within the mixed-precision bound (1e-6) and
+    within 4x of the oracle's emulation of the same split arithmetic (parts
+    from FP64 values, FP32 sums), element by element too; and well above the
+    FP64 noise, so the reduced-precision products really run."""
+    err, emulated, y, yo = bf16x6_errors(case(name))
+    assert emulated > 0
+    assert_close(y, yo, min(TOL_FP32, 4 * emulated), name)
+    assert err > 1e-10, err
+
+
+def test_bf16x6_uniform2k():
+    err, emulated, y, yo = bf16x6_errors(W.config("uniform2k"))
+    assert_close(y, yo, min(TOL_FP32, 4 * emulated))
+
+
 def test_deterministic_fp64():
     P = case("highfreq")
     gp = gpu_plan(P)
@@ -214,7 +238,7 @@ def test_dense_gpu_matches_oracle():
     y = F.dense_matvec(to_dev(P.points_T), to_dev(P.points_S), P.kappa, to_dev(P.v))
     torch.cuda.synchronize()
     yo = oracle.dense_matvec(P.points_T, P.points_S, P.v, P.kappa)
-    assert rel(y.cpu().numpy(), yo) <= 1e-13
+    assert_close(y.cpu().numpy(), yo, 1e-13)
 
 
 def test_same_points_zero_diagonal():
@@ -224,7 +248,7 @@ def test_same_points_zero_diagonal():
     y, _ = gpu_matvec(P)
     yo = oracle.matvec(oracle_plan(P), P.v)
     assert np.all(np.isfinite(y))
-    assert rel(y, yo) <= TOL_FP64
+    assert_close(y, yo, TOL_FP64)
 
 
 def test_empty_inputs():
