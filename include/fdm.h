@@ -242,6 +242,30 @@ int fdm_plan_prepare(fdm_plan* plan, void* stream);
 int fdm_plan_coupling_launches(const fdm_plan* plan, int* n);
 int fdm_plan_wait_launch(const fdm_plan* plan, int i, double* ms);
 
+/*
+ * fdm_plan_matvec_noalloc -- fdm_plan_matvec (c64 = 0) or
+ * fdm_plan_matvec_c64 (c64 = 1) that allocates no memory, for callers that
+ * cannot allocate: code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc.  For plans with a streamed coupling bank
+ * (bank_budget_bytes > 0), whose matvec otherwise generates the bank into a
+ * workspace the plan allocates: here the bank goes to a static workspace of
+ * the library, 64 MiB on each GPU, held until the process ends.
+ *
+ *  plan    built with 0 < bank_budget_bytes and a bank workspace of at most
+ *          64 MiB (the workspace holds min(N_SC, floor(budget / matrix))
+ *          coupling matrices), else FDM_ERR_INVALID_ARG; prepared with
+ *          fdm_plan_prepare (which builds the launch schedule for the static
+ *          workspace), else FDM_ERR_STATE.
+ *  v, y    as for fdm_plan_matvec / fdm_plan_matvec_c64.
+ * Results are bit for bit those of fdm_plan_matvec{,_c64} on the same plan.
+ * Every such call on one GPU shares that GPU's static workspace: calls that
+ * overlap on one GPU (other streams, other threads, other plans) race and
+ * must be serialised by the caller.  Nothing in the workspace needs to start
+ * at zero.  No hipMalloc, hipFree or allocating library call is made.
+ */
+int fdm_plan_matvec_noalloc(fdm_plan* plan, const void* v, void* y, int c64,
+                            void* stream);
+
 /* Free a plan and all its device memory.  NULL is accepted. */
 int fdm_plan_destroy(fdm_plan* plan);
 

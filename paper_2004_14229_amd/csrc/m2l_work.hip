@@ -269,16 +269,30 @@ void plan_launch_events(Plan& P) {
   for (auto& e : P.launch_ev) FDM_HIP(hipEventCreate(&e));
 }
 
+int64_t plan_workspace_bytes(const Plan& P) {
+  if (P.bank_budget <= 0 || P.base_items.empty()) return 0;
+  const int64_t mb = bank_matrix_bytes(P.prec, P.ip);
+  return std::max<int64_t>(1, std::min(P.n_bank, P.bank_budget / mb)) * mb;
+}
+
 void build_plan_schedule(Plan& P, hipStream_t s) {
   void* ws = nullptr;
   int64_t ws_mats = 0;
-  if (P.bank_budget > 0 && !P.base_items.empty()) {
-    const int64_t mb = bank_matrix_bytes(P.prec, P.ip);
-    ws_mats = std::max<int64_t>(1, std::min(P.n_bank, P.bank_budget / mb));
-    if (P.bank_ws.size() < static_cast<size_t>(ws_mats * mb)) P.bank_ws.alloc(ws_mats * mb, &P.tally);
+  const int64_t ws_bytes = plan_workspace_bytes(P);
+  if (ws_bytes > 0) {
+    ws_mats = ws_bytes / bank_matrix_bytes(P.prec, P.ip);
+    if (P.bank_ws.size() < static_cast<size_t>(ws_bytes)) P.bank_ws.alloc(ws_bytes, &P.tally);
     ws = P.bank_ws.get();
   }
   P.sched = build_schedule({&P}, P.tune, ws, ws_mats, s);
+  P.sched_static.clear();
+  P.static_ready = false;
+  if (ws_bytes > 0 && ws_bytes <= static_workspace_bytes()) {
+    // same launches (the schedule depends only on the workspace's matrix
+    // count), the bank generated into the static workspace
+    P.sched_static = build_schedule({&P}, P.tune, static_workspace(), ws_mats, s);
+    P.static_ready = P.sched_static.size() == P.sched.size();
+  }
   P.heads.alloc(std::max<size_t>(P.sched.size(), 1), &P.tally);
   P.sched_ready = true;
   plan_launch_events(P);
@@ -434,6 +448,8 @@ void build_m2l_work(Plan& P, hipStream_t s) {
   P.base_items.clear();
   P.valid_off_h.clear();
   P.sched.clear();
+  P.sched_static.clear();
+  P.static_ready = false;
   P.sched_ready = false;
   P.item_tiles.clear();
   if (n_items == 0) {

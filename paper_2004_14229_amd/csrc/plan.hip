@@ -167,13 +167,20 @@ void plan_zero_output(Plan& P, void* y_user, bool c64, hipStream_t s) {
     launch_permute_out(P.y_tree.get(), P.T.perm.get(), P.nT, static_cast<double*>(y_user), s);
 }
 
-void plan_matvec(Plan& P, const void* v_user, void* y_user, bool c64, hipStream_t s) {
+void plan_matvec(Plan& P, const void* v_user, void* y_user, bool c64, hipStream_t s,
+                 bool use_static) {
   if (P.nT == 0) return;
   if (P.nS == 0) {  // no sources: y = 0
     plan_zero_output(P, y_user, c64, s);
     return;
   }
-  if (!P.sched_ready) build_plan_schedule(P, s);
+  if (use_static) {
+    if (!P.sched_ready || !P.static_ready)
+      fail(FDM_ERR_STATE, "the plan has no launch schedule for the static workspace");
+  } else if (!P.sched_ready) {
+    build_plan_schedule(P, s);
+  }
+  std::vector<M2LLaunch>& sched = use_static ? P.sched_static : P.sched;
   auto mark = [&](int i) {
     if (P.timing) FDM_HIP(hipEventRecord(P.ev[i], s));
   };
@@ -190,8 +197,8 @@ void plan_matvec(Plan& P, const void* v_user, void* y_user, bool c64, hipStream_
   if (P.l_min <= p)
     for (int l = p - 1; l >= P.l_min; --l) launch_m2m(P, l, s);
   mark(2);
-  run_schedule(P.sched, P.heads.get(), P.prec, P.ip, P.tune, s,   // multiplication phase
-               P.timing && P.launch_ev.size() == P.sched.size() ? P.launch_ev.data() : nullptr);
+  run_schedule(sched, P.heads.get(), P.prec, P.ip, P.tune, s,   // multiplication phase
+               P.timing && P.launch_ev.size() == sched.size() ? P.launch_ev.data() : nullptr);
   mark(3);
   if (!P.tune.p2p_in_queue || !p2p_queue_supported(P.prec, P.ip.Kp)) launch_p2p(P, s);           // near field (stored)
   mark(4);
@@ -259,6 +266,8 @@ void apply_plan_tune(Plan& P, const TuneConfig& c, hipStream_t s) {
   P.tune = c;
   if (rebuild && P.l_min <= P.levels) build_m2l_work(P, s);
   P.sched.clear();
+  P.sched_static.clear();
+  P.static_ready = false;
   P.sched_ready = false;
   FDM_HIP(hipStreamSynchronize(s));
 }

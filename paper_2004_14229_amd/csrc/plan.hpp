@@ -180,6 +180,11 @@ struct Plan {
   std::vector<M2LLaunch> sched;
   DevBuf<int32_t> heads;  // one queue head per launch
   bool sched_ready = false;
+  // the same launches with the streamed bank generated into the library's
+  // static workspace instead of bank_ws (built with sched when the plan's
+  // workspace fits it; used by the allocation-free matvec)
+  std::vector<M2LLaunch> sched_static;
+  bool static_ready = false;
   const void* batch_owner = nullptr;  // the batch holding this plan, if any
 
   // near field
@@ -206,7 +211,9 @@ struct Plan {
 
 void plan_build(Plan& P, const double* pT, const double* pS, hipStream_t s);
 // v_user / y_user are complex128, or complex64 when c64 is set.
-void plan_matvec(Plan& P, const void* v_user, void* y_user, bool c64, hipStream_t s);
+// use_static: run the launches of sched_static (the plan must be prepared).
+void plan_matvec(Plan& P, const void* v_user, void* y_user, bool c64, hipStream_t s,
+                 bool use_static = false);
 // The parts of a matvec around the coupling launches (batched matvecs).
 void plan_upward(Plan& P, const void* v_user, bool c64, hipStream_t s);
 void plan_downward(Plan& P, void* y_user, bool c64, hipStream_t s);
@@ -238,6 +245,12 @@ void build_m2l_work(Plan& P, hipStream_t s);  // base items for P.tune.nb
 int64_t bank_matrix_bytes(int prec, const Interp& ip);
 // Rebuild the plan's own launches (after a change of its tune config).
 void build_plan_schedule(Plan& P, hipStream_t s);
+// The library's static workspace (noalloc.hip): its size, and its address
+// on the current device (looked up once per device).
+int64_t static_workspace_bytes();
+void* static_workspace();
+// Bytes of the streamed-bank workspace a plan's schedule uses (0: resident).
+int64_t plan_workspace_bytes(const Plan& P);
 // (Re)create the per-launch timing events of the plan's schedule.
 void plan_launch_events(Plan& P);
 // A bank range [b0, b1) of one plan in a coupling launch.

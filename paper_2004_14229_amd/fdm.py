@@ -91,6 +91,7 @@ def lib() -> ctypes.CDLL:
                                     ci, vp, ctypes.POINTER(vp)]
     L.fdm_plan_matvec.argtypes = [vp, vp, vp, vp]
     L.fdm_plan_matvec_c64.argtypes = [vp, vp, vp, vp]
+    L.fdm_plan_matvec_noalloc.argtypes = [vp, vp, vp, ci, vp]
     L.fdm_plan_destroy.argtypes = [vp]
     L.fdm_plan_stats.argtypes = [vp, ctypes.POINTER(Stats)]
     L.fdm_plan_export.argtypes = [vp, ctypes.c_char_p, vp, i64, ctypes.POINTER(i64)]
@@ -118,7 +119,8 @@ def lib() -> ctypes.CDLL:
     L.fdm_last_error.restype = ctypes.c_char_p
     L.fdm_version.restype = ctypes.c_char_p
     for f in ("fdm_build_tree", "fdm_build_tree_ex", "fdm_build_tree_opts", "fdm_plan_matvec",
-              "fdm_plan_matvec_c64", "fdm_plan_destroy", "fdm_plan_stats",
+              "fdm_plan_matvec_c64", "fdm_plan_matvec_noalloc", "fdm_plan_destroy",
+              "fdm_plan_stats",
               "fdm_plan_export", "fdm_dense_matvec", "fdm_plan_set_timing",
               "fdm_plan_phase_ms", "fdm_plan_get_tune", "fdm_plan_set_tune",
               "fdm_plan_prepare", "fdm_plan_coupling_launches", "fdm_plan_wait_launch",
@@ -238,6 +240,20 @@ class Plan:
             v, out = self._vectors(v, out)
             fn = lib().fdm_plan_matvec if v.dtype == torch.complex128 else lib().fdm_plan_matvec_c64
             _check(fn(self._h, _ptr(v), _ptr(out), on.handle()))
+            on.keep(v, out)
+        return out
+
+    def matvec_noalloc(self, v, out, stream=None):
+        """``out = A~ v`` with the streamed coupling bank in the library's
+        static workspace (``fdm_plan_matvec_noalloc``): the library allocates
+        nothing; ``out`` must be given.  The plan must have been prepared."""
+        import torch
+        if out is None:
+            raise TypeError("out must be given (nothing is allocated)")
+        with _OnStream(stream) as on:
+            v, out = self._vectors(v, out)
+            _check(lib().fdm_plan_matvec_noalloc(self._h, _ptr(v), _ptr(out),
+                                                 int(v.dtype == torch.complex64), on.handle()))
             on.keep(v, out)
         return out
 
