@@ -41,6 +41,10 @@ def parse():
                     help="timed steps of the plain FP64 plan (0 = skip)")
     ap.add_argument("--bf16-steps", type=int, default=1,
                     help="timed steps of each BF16 split plan (bf16x3, bf16x6; 0 = skip)")
+    ap.add_argument("--aca-eps", type=float, default=1e-7,
+                    help="tolerance of the low-rank (ACA) coupling leg, FP32 (0 = skip)")
+    ap.add_argument("--aca-steps", type=int, default=1,
+                    help="timed steps of the low-rank coupling plan")
     ap.add_argument("--batch-steps", type=int, default=2,
                     help="timed batched matvecs of the 64-problem workload (0 = skip)")
     ap.add_argument("--bank-budget-gb", type=float, default=0.0,
@@ -444,6 +448,40 @@ def main():
                 np.linalg.norm(y_bf - y_plain) / np.linalg.norm(y_plain))
         print(f"[bench] {split}: {bms:.1f} ms/matvec, M2L {bm2l:.1f} ms", file=sys.stderr,
               flush=True)
+
+    if args.aca_eps > 0 and args.aca_steps > 0 and budget == 0:
+        t0 = time.perf_counter()
+        ap_ = F.Plan(pt, ps, P.kappa, P.box, P.levels, P.m, precision="fp32",
+                     aca_eps=args.aca_eps)
+        torch.cuda.synchronize()
+        aca_setup = time.perf_counter() - t0
+        ast = ap_.stats()
+        awall, aph = time_plan(ap_, v, y, args.aca_steps, min(args.warmup, 1), "aca")
+        y_aca = y.cpu().numpy()
+        ap_.close()
+        del ap_
+        ams = 1000.0 * awall / args.aca_steps
+        am2l = float(np.mean([p["m2l"] for p in aph]))
+        K = (P.m + 1) ** 3
+        # two stages of 8 K r flops per block at the matrices' mean rank r,
+        # and what the rank cap issues
+        alg = 16.0 * K * ast["aca_rank_mean"] * stats["n_couplings"]
+        issued = 16.0 * K * ast["aca_rank_cap"] * stats["n_couplings"]
+        out["aca"] = {"eps": args.aca_eps, "value": 1000.0 / ams, "ms_per_step": ams,
+                      "steps": args.aca_steps, "m2l_ms": am2l, "setup_s": aca_setup,
+                      "rank_cap": ast["aca_rank_cap"], "rank_max": ast["aca_rank_max"],
+                      "rank_mean": ast["aca_rank_mean"],
+                      "m2l_tflops_algorithmic": alg / (am2l * 1e-3) / 1e12,
+                      "m2l_tflops_issued": issued / (am2l * 1e-3) / 1e12,
+                      "frac_of_fp32_peak_issued": issued / (am2l * 1e-3) / 1e12 / 157.3,
+                      "speedup_vs_mixed": ms_per_step / ams,
+                      "device_bytes": ast["device_bytes"]}
+        if os.path.exists(golden):
+            out["aca"]["rel_l2_err_vs_oracle"] = float(
+                np.linalg.norm(y_aca[rows] - yo) / np.linalg.norm(yo))
+        print(f"[bench] aca {args.aca_eps:g}: {ams:.1f} ms/matvec, M2L {am2l:.1f} ms, "
+              f"rank mean {ast['aca_rank_mean']:.1f} max {ast['aca_rank_max']}",
+              file=sys.stderr, flush=True)
 
     if args.batch_steps > 0:
         del pt, ps, v, y

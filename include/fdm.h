@@ -160,6 +160,24 @@ typedef struct {
  *                     Streamed and BF16 split banks always hold one matrix
  *                     per offset.  Results agree to rounding (the k sums of
  *                     transposed matrices run in another order).
+ *  aca_eps            > 0: low-rank couplings (Sect. 2.7).  At plan build
+ *                     every stored coupling matrix is compressed on the device
+ *                     by partially pivoted adaptive cross approximation
+ *                     (the pivot rule and stopping test of fdm_aca, tolerance
+ *                     aca_eps, at most aca_rank crosses), A ~ U Vt, and each
+ *                     matvec applies it in two matrix-core stages, T = Vt v
+ *                     then U T (16 K k instead of 8 K^2 flops per block).
+ *                     FDM_PREC_FP32 only (else FDM_ERR_UNSUPPORTED), resident
+ *                     bank only (bank_budget_bytes 0, else
+ *                     FDM_ERR_INVALID_ARG); launch shape fixed to 64 targets
+ *                     per item, no compaction, near field apart.  0: dense
+ *                     couplings.  Must be finite and >= 0.
+ *  aca_rank           rank cap of the low-rank couplings: 32 or 64 (0: 64);
+ *                     a matrix that needs more crosses keeps the first
+ *                     aca_rank (fdm_plan_stats reports the largest rank).
+ *  aca_chunk_bytes    low-rank couplings: bound on the first stage's output
+ *                     held at once (the items run in chunks that fit it,
+ *                     at least one item each); 0: 4 GiB; >= 0.
  */
 typedef struct {
   int32_t precision;
@@ -167,6 +185,9 @@ typedef struct {
   int64_t bank_budget_bytes;
   fdm_tune tune;
   int32_t full_bank;
+  int32_t aca_rank;
+  double aca_eps;
+  int64_t aca_chunk_bytes;
 } fdm_options;
 
 /* fdm_build_tree with options (opts host, not NULL). */
@@ -287,6 +308,9 @@ typedef struct {
                                    incl. zero-padded columns                */
   int64_t device_bytes;         /* device memory held by the plan          */
   double setup_ms;              /* wall time of fdm_build_tree             */
+  int32_t aca_rank_cap;         /* low-rank couplings: rank cap, else 0    */
+  int32_t aca_rank_max;         /* largest rank among the stored matrices  */
+  double aca_rank_mean;         /* mean rank                               */
 } fdm_stats;
 
 int fdm_plan_stats(const fdm_plan* plan, fdm_stats* out);
@@ -310,6 +334,10 @@ int fdm_plan_stats(const fdm_plan* plan, fdm_stats* out);
  *           "D_Xl", "Dh_Xl" int64[]  active / inherited directions,
  *                                    sorted codes box * nd + dir
  *           "near_pairs", "near_entries"  int64[1]
+ *           "aca_rank"    int64[n]   low-rank couplings: crosses taken per
+ *                                    stored matrix (bank id order)
+ *           "bank_offsets" int64[5n] per bank id: level, offset x, y, z and
+ *                                    direction index of its matrix
  *           "mom_l", "loc_l"  complex128[nb * nd * K] moments / locals of
  *                                    the last matvec (centre-relative
  *                                    phase form, box-major)

@@ -163,6 +163,10 @@ int fdm_plan_autotune(fdm_plan* plan, const void* v, void* y, int c64, int max_c
     double best_ms = -1;
     TuneConfig keep = P.tune;
     for (int i = 0; i < max_candidates; ++i) {
+      if (P.aca_kp && cand[i].nb != 64) {  // low-rank items hold 64 targets
+        if (ms) ms[i] = -1.0;
+        continue;
+      }
       apply_plan_tune(P, cand[i], s);
       build_plan_schedule(P, s);
       const double t = time_on_stream(s, [&] {

@@ -64,6 +64,9 @@ std::vector<int64_t> export_int(const Plan& P, const std::string& name, bool& fo
   if (name == "perm_S") return widen_i32(P.S.perm.get(), P.nS);
   if (name == "l_hf") return {P.l_hf};
   if (name == "near_pairs") return {P.near_pairs};
+  if (name == "aca_rank") return std::vector<int64_t>(P.aca_rank.begin(), P.aca_rank.end());
+  if (name == "bank_offsets")
+    return std::vector<int64_t>(P.bank_info.begin(), P.bank_info.end());
   if (name == "near_entries") return {P.near_entries};
   for (const char* tag : {"T", "S"}) {
     const DevTree& A = tag[0] == 'T' ? P.T : P.S;

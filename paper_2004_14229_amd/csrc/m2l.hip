@@ -169,6 +169,10 @@ void launch_m2l_items(const M2LLaunch& L, int prec, int Kp, const TuneConfig& cf
   if (L.n_items == 0) return;
   if (L.n_items > INT32_MAX / 2) fail(FDM_ERR_UNSUPPORTED, "too many coupling items");
   const bool persistent = cfg.persistent && head != nullptr;
+  if (L.stage) {
+    launch_items_aca(L, L.stage, Kp, persistent, head, s);
+    return;
+  }
   if (prec == FDM_PREC_FP64)
     launch_items_f64(L, Kp, cfg.nb, persistent, head, s);
   else if (prec == FDM_PREC_BF16X3)

@@ -517,7 +517,21 @@ __device__ __forceinline__ void mfma32(f16v (&ar)[NB / 32], f16v (&ai)[NB / 32],
 // are added to the FP64 result in memory, which this workgroup alone owns.
 constexpr int kFlush = 16;
 
-template <int NB, bool ADD>
+// Columns of the second stage of a low-rank coupling item (ACA, NB = 64):
+// target slot j of the item's offset entry `pair` (its index in the plan's
+// offset lists) reads column pair * 64 + j of the first stage's output T
+// (D.mom, kp entries per column), or nothing where the source box is empty.
+__device__ __forceinline__ void aca_columns(TargetTile<64>& S, int buf, const M2LDesc& D,
+                                            int4 od, int c, int Kp, int64_t pair) {
+  for (int j = threadIdx.x; j < 64; j += blockDim.x)
+    S.col[buf][j] = source_column(S, j, D, od, c, Kp) >= 0 ? (pair * 64 + j) * D.kp : -1;
+}
+
+// ACA: the item is the second stage of a low-rank coupling (Sect. 2.7,
+// A~ = U Vt): the matrix applied is U (Kp x kp, k-major, from the ACA bank)
+// and the columns are the first stage's T = Vt M (kp per column); kp / 16
+// slabs per offset.
+template <int NB, bool ADD, bool ACA = false>
 __device__ __forceinline__ void item_f32(F32Shared<NB>& sh, const M2LItem& it,
                                          const M2LDesc& D, int Kp) {
   using Tr = F32Traits;
@@ -540,12 +554,21 @@ __device__ __forceinline__ void item_f32(F32Shared<NB>& sh, const M2LItem& it,
   zero(toi);
   const float* mom = static_cast<const float*>(D.mom);
   const float* bank = static_cast<const float*>(D.bank);
-  const int64_t per = int64_t(Kp) * Kp;
-  const int ns = Kp / Tr::KS;  // k slabs per offset (>= 2)
+  // matrix planes: Kp x Kp, or for ACA the U factor, Kp x kp (bank entries
+  // hold U and Vt, 4 planes)
+  const int64_t per = int64_t(Kp) * (ACA ? D.kp : Kp);
+  const int mplanes = ACA ? 4 : 2;
+  const int ns = (ACA ? D.kp : Kp) / Tr::KS;  // k slabs per offset (>= 2)
   const int total = nv * ns;
+  auto columns = [&](int buf, int4 od, int v) {
+    if constexpr (ACA)
+      aca_columns(sh.S, buf, D, od, it.c, Kp, int64_t(it.vo_begin) + v);
+    else
+      source_columns(sh.S, buf, D, od, it.c, Kp);
+  };
   int4 od_cur = offset_of(D, it.vo_begin);
   int4 od_next = od_cur;
-  source_columns(sh.S, 0, D, od_cur, it.c, Kp);
+  columns(0, od_cur, 0);
   __syncthreads();
   store_cols<Tr, NB>(sh, 0, load_cols<Tr, NB>(sh.S, 0, mom, 0));
   __syncthreads();
@@ -556,7 +579,7 @@ __device__ __forceinline__ void item_f32(F32Shared<NB>& sh, const M2LItem& it,
       od_cur = od_next;
       if (v + 1 < nv) {  // source columns of the next offset
         od_next = offset_of(D, it.vo_begin + v + 1);
-        source_columns(sh.S, (v + 1) & 1, D, od_next, it.c, Kp);
+        columns((v + 1) & 1, od_next, v + 1);
       }
     }
     const bool more = q + 1 < total;
@@ -570,7 +593,7 @@ __device__ __forceinline__ void item_f32(F32Shared<NB>& sh, const M2LItem& it,
       float a[2][8];
       // issue all of the slab's coupling-matrix loads before its MFMAs, so
       // that their latency overlaps the first products
-      load_a32<decltype(transposed)::value>(a, bank + (od_cur.w >> 1) * 2 * per, per,
+      load_a32<decltype(transposed)::value>(a, bank + (od_cur.w >> 1) * mplanes * per, per,
                                             s * Tr::KS, Kp, wave, lane);
       __builtin_amdgcn_sched_barrier(0);
       mfma32<NB>(acr, aci, a, sh, cur, lane);

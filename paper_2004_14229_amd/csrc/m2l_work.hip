@@ -64,10 +64,12 @@ M2LDesc level_desc(const Plan& P, int l, const void* bank, int64_t bank_id0) {
   d.nd = Ld.nd;
   d.level = l;
   d.K = P.ip.K;
+  d.kp = P.aca_kp;
   return d;
 }
 
 const void* resident_bank(const Plan& P) {
+  if (P.aca_kp) return P.aca_bank.get();
   if (P.prec == FDM_PREC_FP64) return P.bank64.get();
   if (P.prec == FDM_PREC_BF16X3 || P.prec == FDM_PREC_BF16X6) return P.bank16.get();
   return P.bank32.get();
@@ -275,7 +277,75 @@ int64_t plan_workspace_bytes(const Plan& P) {
   return std::max<int64_t>(1, std::min(P.n_bank, P.bank_budget / mb)) * mb;
 }
 
+// Low-rank couplings: the plan's items in chunks of consecutive items whose
+// stage-1 output T (kp x 64 complex FP32 per item offset) fits the budget;
+// per chunk a stage-1 and a stage-2 launch over the same items, T indexed
+// by the items' offset entries relative to the chunk's first.
+std::vector<M2LLaunch> build_aca_schedule(Plan& P, hipStream_t s) {
+  const int64_t per_entry = int64_t(64) * P.aca_kp * 2;  // floats of T per offset entry
+  const int64_t cap = std::max<int64_t>(per_entry, P.aca_T_budget / 4);
+  const auto& items = P.base_items;
+  // chunks [first, last) of consecutive items (their offset entries are
+  // consecutive in valid_off) and the largest chunk's T
+  std::vector<std::pair<size_t, size_t>> chunks;
+  int64_t need = 0;
+  for (size_t i = 0; i < items.size();) {
+    const int64_t vo0 = items[i].vo_begin;
+    size_t e = i + 1;
+    while (e < items.size() &&
+           (int64_t(items[e].vo_begin) + items[e].vo_count - vo0) * per_entry <= cap)
+      ++e;
+    need = std::max(need, (int64_t(items[e - 1].vo_begin) + items[e - 1].vo_count - vo0) *
+                              per_entry);
+    chunks.push_back({i, e});
+    i = e;
+  }
+  if (P.aca_T.size() < static_cast<size_t>(need)) P.aca_T.alloc(need, &P.tally);
+  std::vector<M2LLaunch> out;
+  for (auto [first, last] : chunks) {
+    // T of entry vo sits at T + (vo - vo0) * per_entry floats
+    const int64_t vo0 = items[first].vo_begin;
+    const void* T = reinterpret_cast<const void*>(reinterpret_cast<uintptr_t>(P.aca_T.get()) -
+                                                  static_cast<uintptr_t>(vo0 * per_entry * 4));
+    for (int stage = 1; stage <= 2; ++stage) {
+      LaunchBuilder B;
+      std::vector<int32_t> desc_of(P.levels + 1, -1);
+      for (int l = std::max(P.l_min, 0); l <= P.levels; ++l) {
+        desc_of[l] = static_cast<int32_t>(B.descs.size());
+        M2LDesc d = level_desc(P, l, resident_bank(P), 0);
+        if (stage == 1)
+          d.out = const_cast<void*>(T);  // stage 1 writes T
+        else
+          d.mom = T;  // stage 2 reads it
+        B.descs.push_back(d);
+      }
+      for (size_t k = first; k < last; ++k) {
+        M2LItem it = items[k];
+        if (stage == 1 && it.vo_count == 0) continue;
+        it.desc = desc_of[it.desc];
+        it.compact = 0;
+        B.items.push_back(it);
+        B.weight.push_back(static_cast<double>(it.vo_count));
+      }
+      M2LLaunch L = upload(B, P.tune, P.prec, P.ip.Kp, nullptr, s);
+      L.stage = stage;
+      L.resident_wgs = resident_aca(stage, P.ip.Kp);
+      out.push_back(std::move(L));
+    }
+  }
+  return out;
+}
+
 void build_plan_schedule(Plan& P, hipStream_t s) {
+  if (P.aca_kp) {
+    P.sched = build_aca_schedule(P, s);
+    P.sched_static.clear();
+    P.static_ready = false;
+    P.heads.alloc(std::max<size_t>(P.sched.size(), 1), &P.tally);
+    P.sched_ready = true;
+    plan_launch_events(P);
+    return;
+  }
   void* ws = nullptr;
   int64_t ws_mats = 0;
   const int64_t ws_bytes = plan_workspace_bytes(P);
@@ -351,12 +421,24 @@ void launch_bank(Plan& P, hipStream_t s) {
     for (size_t i = 0; i < T.adm.size(); ++i)
       P.bank_info.insert(P.bank_info.end(), {l, T.adm[i].x, T.adm[i].y, T.adm[i].z, T.dir[i]});
   }
-  P.sym = P.bank_budget == 0 && !P.full_bank &&
+  P.sym = P.bank_budget == 0 && !P.full_bank && !P.aca_kp &&
           (P.prec == FDM_PREC_FP64 || P.prec == FDM_PREC_FP32) && bank_pairs_mirror(P);
   P.n_bank_stored = 0;
   if (P.n_bank == 0 || P.bank_budget != 0) return;  // streamed: generated per matvec
   std::vector<BankLevel> bl(P.levels + 1);
   for (int l = 0; l <= P.levels; ++l) bl[l] = bank_level(P, l);
+  if (P.aca_kp) {  // low-rank bank: the crosses of every stored matrix
+    DevBuf<int32_t> d_info, d_rank(P.n_bank);
+    DevBuf<BankLevel> d_bl;
+    to_device(d_info, P.bank_info, s, nullptr);
+    to_device(d_bl, bl, s, nullptr);
+    P.aca_bank.alloc(P.n_bank * aca_matrix_bytes(P.ip, P.aca_kp) / 4, &P.tally);
+    launch_aca(d_info.get(), P.n_bank, d_bl.get(), P.ip, P.aca_eps, P.aca_kp,
+               P.aca_bank.get(), d_rank.get(), s);
+    P.aca_rank = to_host(d_rank.get(), P.n_bank, s);
+    P.n_bank_stored = P.n_bank;
+    return;
+  }
   std::vector<int32_t> info;  // the stored matrices, in bank order
   if (P.sym) {
     for (int l = std::max(P.l_min, 0); l <= P.levels; ++l) {

@@ -262,6 +262,9 @@ fdm_tune to_c(const TuneConfig& c) {
 }
 
 void apply_plan_tune(Plan& P, const TuneConfig& c, hipStream_t s) {
+  if (P.aca_kp && (c.nb != 64 || c.compact != 0 || c.p2p_in_queue != 0))
+    fail(FDM_ERR_UNSUPPORTED,
+         "low-rank couplings run 64 targets per item, no compaction, near field apart");
   const bool rebuild = c.nb != P.tune.nb;
   P.tune = c;
   if (rebuild && P.l_min <= P.levels) build_m2l_work(P, s);
@@ -297,6 +300,15 @@ int fdm_build_tree_opts(const double* points_T, int64_t n_T, const double* point
     if (opts->bank_budget_bytes < 0) fail(FDM_ERR_INVALID_ARG, "negative bank budget");
     if (opts->full_bank != 0 && opts->full_bank != 1)
       fail(FDM_ERR_INVALID_ARG, "full_bank must be 0 or 1");
+    if (!std::isfinite(opts->aca_eps) || opts->aca_eps < 0)
+      fail(FDM_ERR_INVALID_ARG, "aca_eps must be finite and >= 0");
+    if (opts->aca_rank != 0 && opts->aca_rank != 32 && opts->aca_rank != 64)
+      fail(FDM_ERR_INVALID_ARG, "aca_rank must be 0, 32 or 64");
+    if (opts->aca_chunk_bytes < 0) fail(FDM_ERR_INVALID_ARG, "negative aca_chunk_bytes");
+    if (opts->aca_eps > 0 && precision != FDM_PREC_FP32)
+      fail(FDM_ERR_UNSUPPORTED, "low-rank couplings run in the FP32 precision");
+    if (opts->aca_eps > 0 && opts->bank_budget_bytes != 0)
+      fail(FDM_ERR_INVALID_ARG, "low-rank couplings keep their bank resident");
     TuneConfig tune;
     if (opts->tune.nb != 0)
       tune = check_tune(opts->tune);
@@ -329,6 +341,14 @@ int fdm_build_tree_opts(const double* points_T, int64_t n_T, const double* point
       P.tune = tune;
       P.bank_budget = opts->bank_budget_bytes;
       P.full_bank = opts->full_bank != 0;
+      if (opts->aca_eps > 0) {
+        P.aca_eps = opts->aca_eps;
+        P.aca_kp = opts->aca_rank ? opts->aca_rank : 64;
+        if (opts->aca_chunk_bytes > 0) P.aca_T_budget = opts->aca_chunk_bytes;
+        P.tune.nb = 64;
+        P.tune.compact = 0;
+        P.tune.p2p_in_queue = 0;
+      }
       if (P.bank_budget > 0) {
         Interp ip{};
         ip.Kp = (K + 31) / 32 * 32;
@@ -500,6 +520,14 @@ int fdm_plan_stats(const fdm_plan* plan, fdm_stats* out) {
     st.n_couplings = P.n_couplings;
     st.n_stored_couplings = P.n_stored;
     st.n_bank_matrices = P.bank_budget == 0 ? P.n_bank_stored : P.n_bank;
+    st.aca_rank_cap = P.aca_kp;
+    st.aca_rank_max = 0;
+    st.aca_rank_mean = 0.0;
+    for (int32_t r : P.aca_rank) {
+      st.aca_rank_max = std::max(st.aca_rank_max, r);
+      st.aca_rank_mean += r;
+    }
+    if (!P.aca_rank.empty()) st.aca_rank_mean /= static_cast<double>(P.aca_rank.size());
     st.near_pairs = P.near_pairs;
     st.near_entries = P.near_entries;
     st.m2l_columns = issued_columns(P, P.tune);

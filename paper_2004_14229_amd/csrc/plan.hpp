@@ -60,6 +60,7 @@ struct M2LDesc {
   const void* bank;
   int32_t nd, level;
   int32_t K;  // interpolation nodes per box, (m+1)^3 <= Kp: rows / k beyond are padding
+  int32_t kp;  // low-rank couplings: the rank cap (columns of U, rows of Vt), else 0
 };
 
 // Descriptor of one plan's near field in a queued launch.
@@ -114,6 +115,7 @@ struct M2LLaunch {
   int64_t n_items = 0, n_p2p_items = 0;
   int64_t resident_wgs = 0;     // grid of the persistent launch
   bool has_parts = false;       // holds later parts of split items
+  int stage = 0;                // low-rank couplings: 1 T = Vt M, 2 g += U T; 0 dense
   DevBuf<M2LItem> items;
   DevBuf<M2LDesc> descs;
   DevBuf<P2PDesc> p2p;
@@ -160,6 +162,15 @@ struct Plan {
   bool full_bank = false;   // option: store every matrix
   bool sym = false;
   int64_t n_bank_stored = 0;  // matrices in the resident bank
+  // low-rank couplings (ACA, Sect. 2.7): per bank id the crosses of its
+  // matrix as U (Kp x kp) and Vt (kp x Kp), FP32, and the rank reached; the
+  // coupling step runs two stages per chunk of items, T of a chunk in aca_T
+  double aca_eps = 0;       // 0: dense couplings
+  int aca_kp = 0;           // rank cap (32 or 64)
+  DevBuf<float> aca_bank;
+  std::vector<int32_t> aca_rank;
+  DevBuf<float> aca_T;
+  int64_t aca_T_budget = int64_t(4) << 30;  // bytes of T per chunk
   DevBuf<double> bank64;
   DevBuf<float> bank32;
   DevBuf<uint16_t> bank16;
@@ -307,6 +318,13 @@ int64_t resident_f64(int nb, int Kp, bool parts);
 int64_t resident_f32(int nb, int Kp, bool parts);
 int64_t resident_bf16(int nb, int Kp, bool parts);
 int64_t resident_bf16x6(int nb, int Kp, bool parts);
+// low-rank couplings (aca.hip, m2l_aca.hip)
+int64_t aca_matrix_bytes(const Interp& ip, int kp);
+void launch_aca(const int32_t* info, int64_t n_mat, const BankLevel* lv, const Interp& ip,
+                double eps, int kp, float* bank, int32_t* rank, hipStream_t s);
+void launch_items_aca(const M2LLaunch& L, int stage, int Kp, bool persistent, int32_t* head,
+                      hipStream_t s);
+int64_t resident_aca(int stage, int Kp);
 
 // launch-shape helpers of the C ABI (plan.hip)
 TuneConfig check_tune(const fdm_tune& t);

@@ -55,7 +55,8 @@ class Tune(ctypes.Structure):
 class Options(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("l_hf", ctypes.c_int32),
                 ("bank_budget_bytes", ctypes.c_int64), ("tune", Tune),
-                ("full_bank", ctypes.c_int32)]
+                ("full_bank", ctypes.c_int32), ("aca_rank", ctypes.c_int32),
+                ("aca_eps", ctypes.c_double), ("aca_chunk_bytes", ctypes.c_int64)]
 
 
 class Stats(ctypes.Structure):
@@ -66,7 +67,9 @@ class Stats(ctypes.Structure):
                 ("n_couplings", ctypes.c_int64), ("n_stored_couplings", ctypes.c_int64),
                 ("n_bank_matrices", ctypes.c_int64), ("near_pairs", ctypes.c_int64),
                 ("near_entries", ctypes.c_int64), ("m2l_columns", ctypes.c_int64),
-                ("device_bytes", ctypes.c_int64), ("setup_ms", ctypes.c_double)]
+                ("device_bytes", ctypes.c_int64), ("setup_ms", ctypes.c_double),
+                ("aca_rank_cap", ctypes.c_int32), ("aca_rank_max", ctypes.c_int32),
+                ("aca_rank_mean", ctypes.c_double)]
 
 
 def header_functions() -> list[str]:
@@ -200,11 +203,13 @@ class Plan:
 
     def __init__(self, points_T, points_S, kappa: float, box, levels: int, m: int,
                  precision: str = "fp64", l_hf: int | None = None, stream=None,
-                 bank_budget: int = 0, tune: dict | None = None, full_bank: bool = False):
+                 bank_budget: int = 0, tune: dict | None = None, full_bank: bool = False,
+                 aca_eps: float = 0.0, aca_rank: int = 0, aca_chunk_bytes: int = 0):
         box_arr = (ctypes.c_double * 6)(*[float(b) for b in box])
         opts = Options(PRECISION[precision], -2 if l_hf is None else int(l_hf),
                        int(bank_budget), Tune.from_dict(tune, precision) if tune else Tune(),
-                       int(bool(full_bank)))
+                       int(bool(full_bank)), int(aca_rank), float(aca_eps),
+                       int(aca_chunk_bytes))
         h = ctypes.c_void_p()
         # the library synchronises the stream before returning
         with _OnStream(stream) as on:

@@ -52,11 +52,13 @@ def test_null_handles():
     assert L.fdm_plan_export(None, b"perm_T", None, 0, ctypes.byref(size)) == -1
 
 
-def _build_opts(nb=64, budget=0, prec=0, persistent=1, compact=1, full_bank=0):
+def _build_opts(nb=64, budget=0, prec=0, persistent=1, compact=1, full_bank=0, aca_eps=0.0,
+                aca_rank=0, aca_chunk=0):
     L = F.lib()
     h = ctypes.c_void_p()
     box = (ctypes.c_double * 6)(0, 0, 0, 1, 1, 1)
-    opts = F.fdm.Options(prec, -2, budget, F.fdm.Tune(nb, persistent, 1, 0, compact), full_bank)
+    opts = F.fdm.Options(prec, -2, budget, F.fdm.Tune(nb, persistent, 1, 0, compact), full_bank,
+                         aca_rank, aca_eps, aca_chunk)
     st = L.fdm_build_tree_opts(None, 0, None, 0, 1.0, box, 3, 4, ctypes.byref(opts), None,
                                ctypes.byref(h))
     return st, h, L.fdm_last_error().decode()
@@ -64,10 +66,20 @@ def _build_opts(nb=64, budget=0, prec=0, persistent=1, compact=1, full_bank=0):
 
 @pytest.mark.parametrize("kw", [dict(nb=48), dict(nb=0, budget=-1), dict(budget=1),
                                 dict(persistent=2), dict(prec=5), dict(compact=3),
-                                dict(compact=-1), dict(full_bank=2), dict(full_bank=-1)])
+                                dict(compact=-1), dict(full_bank=2), dict(full_bank=-1),
+                                dict(prec=1, aca_eps=-1.0), dict(prec=1, aca_eps=float("inf")),
+                                dict(prec=1, aca_eps=1e-6, aca_rank=48),
+                                dict(prec=1, aca_eps=1e-6, budget=1 << 30),
+                                dict(prec=1, aca_eps=1e-6, aca_chunk=-1)])
 def test_invalid_options_are_rejected(kw):
     st, h, msg = _build_opts(**kw)
     assert st == -1 and h.value is None and msg
+
+
+@pytest.mark.parametrize("prec", [0, 2, 3])
+def test_low_rank_couplings_need_fp32(prec):
+    st, h, msg = _build_opts(prec=prec, aca_eps=1e-6)
+    assert st == -3 and h.value is None and "FP32" in msg
 
 
 def test_null_handles_are_rejected():
