@@ -176,8 +176,10 @@ typedef struct {
  *                     a matrix that needs more crosses keeps the first
  *                     aca_rank (fdm_plan_stats reports the largest rank).
  *  aca_chunk_bytes    low-rank couplings: bound on the first stage's output
- *                     held at once (the items run in chunks that fit it,
- *                     at least one item each); 0: 4 GiB; >= 0.
+ *                     held at once.  Each item's offsets are ordered by rank
+ *                     and cut into groups of 16 (each run at its padded
+ *                     rank); a launch pair covers one group of as many items
+ *                     as fit (at least one).  0: 8 GiB; >= 0.
  */
 typedef struct {
   int32_t precision;
@@ -311,6 +313,11 @@ typedef struct {
   int32_t aca_rank_cap;         /* low-rank couplings: rank cap, else 0    */
   int32_t aca_rank_max;         /* largest rank among the stored matrices  */
   double aca_rank_mean;         /* mean rank                               */
+  double aca_flops;             /* low-rank coupling step: real flops of the
+                                   two products over the admissible blocks,
+                                   16 K r per block at its matrix's rank r */
+  double aca_issued_flops;      /* what its kernels issue: padded ranks,
+                                   rows to Kp, 64 target slots per item    */
 } fdm_stats;
 
 int fdm_plan_stats(const fdm_plan* plan, fdm_stats* out);

@@ -1,36 +1,43 @@
 // Low-rank coupling step (Sect. 2.7 with Alg. 4's M2L): each stored coupling
 // matrix is held as its adaptive cross approximation A~ ~ U Vt (aca.hip), and
 // a block's product A~ v~ is taken in two stages on the matrix cores,
-//   T = Vt v~   (kp x 1 per block),   g~ += U T,
-// which costs 16 K kp instead of 8 K^2 flops per block.
+//   T = Vt v~   (r x 1 per block),   g~ += U T,
+// which costs 16 K r instead of 8 K^2 flops per block at rank r.
 //
-// Stage 1 items (this file): a workgroup of 4 waves owns the 64 target slots
-// of a coupling item; for each of the item's offsets it gathers the source
-// moment columns (as the dense items do), multiplies them by Vt of that
-// offset (2 row tiles of 32 ranks x 2 column tiles of 32 slots, one per
-// wave, FP32 MFMA with FP32 sums) and writes the kp x 64 result to T at the
-// item's offset entry.  Stage 2 items are the FP32 item of m2l_device.hpp
-// with the U factor as its matrix and T as its columns (FP32 per-offset sums,
-// FP32 totals of 16 offsets, FP64 result).  The coupling step runs both
-// stages chunk by chunk over the plan's items, T holding one chunk.
+// Work units: an item's offsets are ordered by rank (highest first) and cut
+// into groups of 16; one launch pair covers one group of many items, so that
+// every group's T fits the plan's buffer and no two workgroups of a launch
+// add into the same result.  A group runs at its padded rank rp (its first
+// offset's rank rounded up to 16, at least 32; stored in the item's `first`
+// field as rp / 16 above the first-part bit): T rows and U columns beyond
+// the rank are zero, so the padding changes no value.  `compact` holds the
+// group's place in T, in units of 64 columns x 16 ranks.
+//
+// Stage 1 items (this file): a workgroup of 2 waves owns the 64 target
+// slots of a group; for each of its offsets it gathers the source moment
+// columns (as the dense items do), multiplies them by Vt of that offset
+// (wave w: slot tile w, 1 or 2 rank tiles of 32; FP32 MFMA with FP32 sums)
+// and writes the rp x 64 result to T.  Stage 2 items are the FP32 item of
+// m2l_device.hpp with the U factor as its matrix and T as its columns (FP32
+// per-offset sums, FP32 totals of the group, FP64 result).
 #include "m2l_device.hpp"
 
 namespace fdm {
 
 namespace {
 
-constexpr int kAca1Threads = 256;  // 4 waves: (rank tile, slot tile)
+constexpr int kAca1Threads = 128;  // 2 waves: one per 32-slot tile
 
-// Moment slab of 64 columns x 16 k, staged by 256 threads (2 pieces each).
+// Moment slab of 64 columns x 16 k, staged by 128 threads (4 pieces each).
 struct Slab64 {
-  float4 v[2];
+  float4 v[4];
 };
 
 __device__ __forceinline__ Slab64 load_slab64(const TargetTile<64>& S, int colbuf,
                                               const float* __restrict__ mom, int k0) {
   Slab64 r;
 #pragma unroll
-  for (int u = 0; u < 2; ++u) {
+  for (int u = 0; u < 4; ++u) {
     const int e = threadIdx.x + kAca1Threads * u;  // piece: column e / 8, k 2 (e % 8) ..
     const int64_t col = S.col[colbuf][e / 8];
     r.v[u] = col >= 0 ? gload16<float4>(mom + 2 * (col + k0) + (e % 8) * 4) : float4{};
@@ -40,7 +47,7 @@ __device__ __forceinline__ Slab64 load_slab64(const TargetTile<64>& S, int colbu
 
 __device__ __forceinline__ void store_slab64(F32Shared<64>& sh, int buf, const Slab64& r) {
 #pragma unroll
-  for (int u = 0; u < 2; ++u) {
+  for (int u = 0; u < 4; ++u) {
     const int e = threadIdx.x + kAca1Threads * u;
     const int j = e / 8, k = 2 * (e % 8);
     sh.B[buf][0][k][j] = r.v[u].x;
@@ -63,30 +70,55 @@ __device__ __forceinline__ void load_vt(float (&a)[2][8], const float* __restric
   }
 }
 
-// Stage 1 of one item: for each offset v, T[pair v] = Vt_v M_v (kp x 64).
+__device__ __forceinline__ void mfma_vt(f16v& acr, f16v& aci, const float (&a)[2][8],
+                                        const F32Shared<64>& sh, int buf, int cl, int kl) {
+#pragma unroll
+  for (int t = 0; t < 8; ++t) {
+    const float b_r = sh.B[buf][0][t + 8 * kl][cl];
+    const float b_i = sh.B[buf][1][t + 8 * kl][cl];
+    acr = __builtin_amdgcn_mfma_f32_32x32x2f32(a[0][t], b_r, acr, 0, 0, 0);
+    acr = __builtin_amdgcn_mfma_f32_32x32x2f32(-a[1][t], b_i, acr, 0, 0, 0);
+    aci = __builtin_amdgcn_mfma_f32_32x32x2f32(a[0][t], b_i, aci, 0, 0, 0);
+    aci = __builtin_amdgcn_mfma_f32_32x32x2f32(a[1][t], b_r, aci, 0, 0, 0);
+  }
+}
+
+// A wave's rows of one rank tile of T for its column: rows below rp.
+__device__ __forceinline__ void store_t(float2* col, const f16v& acr, const f16v& aci, int rt,
+                                        int rp, int lane) {
+#pragma unroll
+  for (int i = 0; i < 16; ++i) {
+    const int r = 32 * rt + 8 * (i / 4) + 4 * (lane / 32) + (i % 4);
+    if (r < rp) col[r] = make_float2(acr[i], aci[i]);
+  }
+}
+
+// Stage 1 of one group: for each offset v, T[v] = Vt_v M_v (rp x 64).
 __device__ __forceinline__ void item_aca1(F32Shared<64>& sh, const M2LItem& it,
                                           const M2LDesc& D, int Kp) {
   using Tr = F32Traits;
   const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
-  const int rt = wave / 2, ct = wave % 2;  // rank tile, slot tile of this wave
   load_targets(sh.S, it, D);
   __syncthreads();
   const int nv = it.vo_count;
   if (nv == 0) return;
   const int kp = D.kp;
+  const int rp = 16 * (it.first >> 1);  // padded rank of the group: 32, 48 or 64
+  const bool two = rp > 32;              // a second rank tile
   const float* mom = static_cast<const float*>(D.mom);
   const float* bank = static_cast<const float*>(D.bank);
-  float2* T = static_cast<float2*>(D.out);
+  float2* T = static_cast<float2*>(D.out) + int64_t(it.compact) * 1024;
   const int64_t per = int64_t(Kp) * kp;  // one plane of U or Vt
   const int ns = Kp / Tr::KS;
   const int total = nv * ns;
+  const int kl = lane / 32, cl = 32 * wave + lane % 32;
   int4 od_cur = offset_of(D, it.vo_begin);
   int4 od_next = od_cur;
   source_columns(sh.S, 0, D, od_cur, it.c, Kp);
   __syncthreads();
   store_slab64(sh, 0, load_slab64(sh.S, 0, mom, 0));
   __syncthreads();
-  f16v acr, aci;
+  f16v acr0, aci0, acr1, aci1;
   for (int q = 0; q < total; ++q) {
     const int v = q / ns, s = q % ns, cur = q & 1;
     if (s == 0) {
@@ -95,35 +127,26 @@ __device__ __forceinline__ void item_aca1(F32Shared<64>& sh, const M2LItem& it,
         od_next = offset_of(D, it.vo_begin + v + 1);
         source_columns(sh.S, (v + 1) & 1, D, od_next, it.c, Kp);
       }
-      acr = f16v{};
-      aci = f16v{};
+      acr0 = f16v{};
+      aci0 = f16v{};
+      acr1 = f16v{};
+      aci1 = f16v{};
     }
     const bool more = q + 1 < total;
     Slab64 nxt{};
     if (more) nxt = load_slab64(sh.S, ((q + 1) / ns) & 1, mom, ((q + 1) % ns) * Tr::KS);
-    if (32 * rt < kp) {
-      float a[2][8];
-      // Vt planes follow the two U planes of the matrix's bank entry
-      load_vt(a, bank + (od_cur.w >> 1) * 4 * per + 2 * per, per, s * Tr::KS, kp, rt, lane);
-      __builtin_amdgcn_sched_barrier(0);
-      const int kl = lane / 32, cl = 32 * ct + lane % 32;
-#pragma unroll
-      for (int t = 0; t < 8; ++t) {
-        const float b_r = sh.B[cur][0][t + 8 * kl][cl];
-        const float b_i = sh.B[cur][1][t + 8 * kl][cl];
-        acr = __builtin_amdgcn_mfma_f32_32x32x2f32(a[0][t], b_r, acr, 0, 0, 0);
-        acr = __builtin_amdgcn_mfma_f32_32x32x2f32(-a[1][t], b_i, acr, 0, 0, 0);
-        aci = __builtin_amdgcn_mfma_f32_32x32x2f32(a[0][t], b_i, aci, 0, 0, 0);
-        aci = __builtin_amdgcn_mfma_f32_32x32x2f32(a[1][t], b_r, aci, 0, 0, 0);
-      }
-      if (s == ns - 1) {  // the offset's T tile: column (pair, slot), kp ranks each
-        float2* col = T + ((int64_t(it.vo_begin) + v) * 64 + cl) * kp;
-#pragma unroll
-        for (int i = 0; i < 16; ++i) {
-          const int r = 32 * rt + 8 * (i / 4) + 4 * (lane / 32) + (i % 4);
-          col[r] = make_float2(acr[i], aci[i]);
-        }
-      }
+    // Vt planes follow the two U planes of the matrix's bank entry
+    const float* Vt = bank + (od_cur.w >> 1) * 4 * per + 2 * per;
+    float a0[2][8], a1[2][8];
+    load_vt(a0, Vt, per, s * Tr::KS, kp, 0, lane);
+    if (two) load_vt(a1, Vt, per, s * Tr::KS, kp, 1, lane);
+    __builtin_amdgcn_sched_barrier(0);
+    mfma_vt(acr0, aci0, a0, sh, cur, cl, kl);
+    if (two) mfma_vt(acr1, aci1, a1, sh, cur, cl, kl);
+    if (s == ns - 1) {  // the offset's T columns: rp ranks each
+      float2* col = T + (int64_t(v) * 64 + cl) * rp;
+      store_t(col, acr0, aci0, 0, rp, lane);
+      if (two) store_t(col, acr1, aci1, 1, rp, lane);
     }
     if (more) store_slab64(sh, cur ^ 1, nxt);
     __syncthreads();
@@ -131,7 +154,7 @@ __device__ __forceinline__ void item_aca1(F32Shared<64>& sh, const M2LItem& it,
 }
 
 template <bool QUEUE>
-__global__ void __launch_bounds__(kAca1Threads)
+__global__ void __launch_bounds__(kAca1Threads) __attribute__((amdgpu_waves_per_eu(3)))
     k_m2l_aca1(const M2LItem* __restrict__ items, int64_t n_items,
                const M2LDesc* __restrict__ descs, int32_t* head, int Kp) {
   __shared__ F32Shared<64> sh;

@@ -517,20 +517,26 @@ __device__ __forceinline__ void mfma32(f16v (&ar)[NB / 32], f16v (&ai)[NB / 32],
 // are added to the FP64 result in memory, which this workgroup alone owns.
 constexpr int kFlush = 16;
 
-// Columns of the second stage of a low-rank coupling item (ACA, NB = 64):
-// target slot j of the item's offset entry `pair` (its index in the plan's
-// offset lists) reads column pair * 64 + j of the first stage's output T
-// (D.mom, kp entries per column), or nothing where the source box is empty.
+// Columns of the second stage of a low-rank coupling group (ACA, NB = 64):
+// target slot j of the group's offset v reads column v * 64 + j of the
+// group's part of the first stage's output T (D.mom; the part starts
+// `base` units of 64 x 16 complex values in, rp entries per column), or
+// nothing where the source box is empty.
 __device__ __forceinline__ void aca_columns(TargetTile<64>& S, int buf, const M2LDesc& D,
-                                            int4 od, int c, int Kp, int64_t pair) {
+                                            int4 od, int c, int Kp, int64_t base, int v,
+                                            int rp) {
   for (int j = threadIdx.x; j < 64; j += blockDim.x)
-    S.col[buf][j] = source_column(S, j, D, od, c, Kp) >= 0 ? (pair * 64 + j) * D.kp : -1;
+    S.col[buf][j] = source_column(S, j, D, od, c, Kp) >= 0
+                        ? base * 1024 + (int64_t(v) * 64 + j) * rp
+                        : -1;
 }
 
-// ACA: the item is the second stage of a low-rank coupling (Sect. 2.7,
+// ACA: the item is the second stage of a low-rank coupling group (Sect. 2.7,
 // A~ = U Vt): the matrix applied is U (Kp x kp, k-major, from the ACA bank)
-// and the columns are the first stage's T = Vt M (kp per column); kp / 16
-// slabs per offset.
+// and the columns are the first stage's T = Vt M; rp / 16 slabs per offset
+// at the group's padded rank rp (`first` >> 1 = rp / 16, bit 0 the
+// first-part flag; `compact` = the group's place in T), every offset as
+// stored.
 template <int NB, bool ADD, bool ACA = false>
 __device__ __forceinline__ void item_f32(F32Shared<NB>& sh, const M2LItem& it,
                                          const M2LDesc& D, int Kp) {
@@ -546,7 +552,7 @@ __device__ __forceinline__ void item_f32(F32Shared<NB>& sh, const M2LItem& it,
   zero(aci);
   const int nv = it.vo_count;
   if (nv == 0) {  // no source box: the result is zero
-    if (rows_here && it.first)
+    if (rows_here && (it.first & 1))
       flush_rows32<NB>(acr, aci, sh.S, out, D.nd, it.c, Kp, wave, lane, true);
     return;
   }
@@ -558,11 +564,11 @@ __device__ __forceinline__ void item_f32(F32Shared<NB>& sh, const M2LItem& it,
   // hold U and Vt, 4 planes)
   const int64_t per = int64_t(Kp) * (ACA ? D.kp : Kp);
   const int mplanes = ACA ? 4 : 2;
-  const int ns = (ACA ? D.kp : Kp) / Tr::KS;  // k slabs per offset (>= 2)
+  const int ns = ACA ? (it.first >> 1) : Kp / Tr::KS;  // k slabs per offset (>= 2)
   const int total = nv * ns;
   auto columns = [&](int buf, int4 od, int v) {
     if constexpr (ACA)
-      aca_columns(sh.S, buf, D, od, it.c, Kp, int64_t(it.vo_begin) + v);
+      aca_columns(sh.S, buf, D, od, it.c, Kp, it.compact, v, ns * Tr::KS);
     else
       source_columns(sh.S, buf, D, od, it.c, Kp);
   };
@@ -572,7 +578,7 @@ __device__ __forceinline__ void item_f32(F32Shared<NB>& sh, const M2LItem& it,
   __syncthreads();
   store_cols<Tr, NB>(sh, 0, load_cols<Tr, NB>(sh.S, 0, mom, 0));
   __syncthreads();
-  bool first = it.first != 0;
+  bool first = (it.first & 1) != 0;
   auto step = [&](auto transposed, int q) {
     const int v = q / ns, s = q % ns, cur = q & 1;
     if (s == 0) {
@@ -616,7 +622,7 @@ __device__ __forceinline__ void item_f32(F32Shared<NB>& sh, const M2LItem& it,
   };
   // offsets applied as stored first, then the transposed ones (two loops:
   // one load pattern live at a time)
-  const int q_split = stored_prefix(D, it.vo_begin, nv) * ns;
+  const int q_split = ACA ? total : stored_prefix(D, it.vo_begin, nv) * ns;
   int q = 0;
   for (; q < q_split; ++q) step(std::false_type{}, q);
   for (; q < total; ++q) step(std::true_type{}, q);

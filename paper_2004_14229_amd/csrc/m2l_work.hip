@@ -166,7 +166,7 @@ M2LLaunch upload(LaunchBuilder& B, const TuneConfig& cfg, int prec, int Kp, void
   M2LLaunch L;
   L.n_items = static_cast<int64_t>(B.items.size() + B.p2p_items.size());
   L.n_p2p_items = static_cast<int64_t>(B.p2p_items.size());
-  for (const M2LItem& it : B.items) L.has_parts |= it.first == 0;
+  for (const M2LItem& it : B.items) L.has_parts |= (it.first & 1) == 0;
   L.resident_wgs = m2l_resident_groups(prec, cfg.nb, Kp, L.has_parts);
   B.items.insert(B.items.end(), B.p2p_items.begin(), B.p2p_items.end());
   to_device(L.items, B.items, s, nullptr);
@@ -282,50 +282,79 @@ int64_t plan_workspace_bytes(const Plan& P) {
 // per chunk a stage-1 and a stage-2 launch over the same items, T indexed
 // by the items' offset entries relative to the chunk's first.
 std::vector<M2LLaunch> build_aca_schedule(Plan& P, hipStream_t s) {
-  const int64_t per_entry = int64_t(64) * P.aca_kp * 2;  // floats of T per offset entry
-  const int64_t cap = std::max<int64_t>(per_entry, P.aca_T_budget / 4);
+  constexpr int G = 16;  // offsets per group: the FP32 totals' flush interval
   const auto& items = P.base_items;
-  // chunks [first, last) of consecutive items (their offset entries are
-  // consecutive in valid_off) and the largest chunk's T
-  std::vector<std::pair<size_t, size_t>> chunks;
+  // each item's offsets by rank, highest first (stable): a group's padded
+  // rank is that of its first offset.  The plan's low-rank bank stores
+  // every matrix at its bank id.
+  std::vector<int32_t> vo = P.valid_off_h;
+  for (const M2LItem& it : items)
+    std::stable_sort(vo.begin() + it.vo_begin, vo.begin() + it.vo_begin + it.vo_count,
+                     [&](int32_t a, int32_t b) { return P.aca_rank[a] > P.aca_rank[b]; });
+  to_device(P.aca_vo, vo, s, &P.tally);
+  auto padded = [&](int32_t b) {
+    const int r = (P.aca_rank[b] + 15) / 16 * 16;
+    return std::min(std::max(r, 32), P.aca_kp);
+  };
+  // launch pairs: group g of items, consecutive items while their T fits
+  const int64_t cap = std::max<int64_t>(int64_t(G) * 64 * P.aca_kp * 8, P.aca_T_budget);
+  int max_groups = 1;
+  for (const M2LItem& it : items) max_groups = std::max(max_groups, (it.vo_count + G - 1) / G);
+  struct Part {
+    M2LItem it;
+    int64_t units;  // T of the group in units of 64 x 16 complex values
+  };
+  std::vector<std::vector<Part>> launches;
   int64_t need = 0;
-  for (size_t i = 0; i < items.size();) {
-    const int64_t vo0 = items[i].vo_begin;
-    size_t e = i + 1;
-    while (e < items.size() &&
-           (int64_t(items[e].vo_begin) + items[e].vo_count - vo0) * per_entry <= cap)
-      ++e;
-    need = std::max(need, (int64_t(items[e - 1].vo_begin) + items[e - 1].vo_count - vo0) *
-                              per_entry);
-    chunks.push_back({i, e});
-    i = e;
+  P.aca_issued_cols = 0;
+  for (int g = 0; g < max_groups; ++g) {
+    std::vector<Part> cur;
+    int64_t used = 0;
+    for (const M2LItem& base : items) {
+      const int n = std::max(0, std::min(G, base.vo_count - g * G));
+      if (n == 0 && g > 0) continue;  // empty items are stored (as zero) by group 0
+      M2LItem it = base;
+      it.vo_begin = base.vo_begin + g * G;
+      it.vo_count = n;
+      const int rp = n ? padded(vo[it.vo_begin]) : 32;
+      it.first = (g == 0 ? 1 : 0) | (rp / 16) << 1;
+      const int64_t units = int64_t(n) * (rp / 16);
+      P.aca_issued_cols += 64.0 * n * rp;
+      if (used + units > cap / 8192 && !cur.empty()) {
+        launches.push_back(std::move(cur));
+        cur.clear();
+        used = 0;
+      }
+      it.compact = static_cast<int32_t>(used);
+      used += units;
+      need = std::max(need, used);
+      cur.push_back({it, units});
+    }
+    if (!cur.empty()) launches.push_back(std::move(cur));
   }
-  if (P.aca_T.size() < static_cast<size_t>(need)) P.aca_T.alloc(need, &P.tally);
+  if (P.aca_T.size() < static_cast<size_t>(need * 2048))
+    P.aca_T.alloc(std::max<int64_t>(need, 1) * 2048, &P.tally);
   std::vector<M2LLaunch> out;
-  for (auto [first, last] : chunks) {
-    // T of entry vo sits at T + (vo - vo0) * per_entry floats
-    const int64_t vo0 = items[first].vo_begin;
-    const void* T = reinterpret_cast<const void*>(reinterpret_cast<uintptr_t>(P.aca_T.get()) -
-                                                  static_cast<uintptr_t>(vo0 * per_entry * 4));
+  for (const auto& parts : launches) {
     for (int stage = 1; stage <= 2; ++stage) {
       LaunchBuilder B;
       std::vector<int32_t> desc_of(P.levels + 1, -1);
       for (int l = std::max(P.l_min, 0); l <= P.levels; ++l) {
         desc_of[l] = static_cast<int32_t>(B.descs.size());
         M2LDesc d = level_desc(P, l, resident_bank(P), 0);
+        d.valid_off = P.aca_vo.get();
         if (stage == 1)
-          d.out = const_cast<void*>(T);  // stage 1 writes T
+          d.out = P.aca_T.get();  // stage 1 writes T
         else
-          d.mom = T;  // stage 2 reads it
+          d.mom = P.aca_T.get();  // stage 2 reads it
         B.descs.push_back(d);
       }
-      for (size_t k = first; k < last; ++k) {
-        M2LItem it = items[k];
-        if (stage == 1 && it.vo_count == 0) continue;
+      for (const Part& pt : parts) {
+        if (stage == 1 && pt.it.vo_count == 0) continue;
+        M2LItem it = pt.it;
         it.desc = desc_of[it.desc];
-        it.compact = 0;
         B.items.push_back(it);
-        B.weight.push_back(static_cast<double>(it.vo_count));
+        B.weight.push_back(static_cast<double>(pt.units));
       }
       M2LLaunch L = upload(B, P.tune, P.prec, P.ip.Kp, nullptr, s);
       L.stage = stage;

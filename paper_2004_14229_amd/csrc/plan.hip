@@ -528,6 +528,10 @@ int fdm_plan_stats(const fdm_plan* plan, fdm_stats* out) {
       st.aca_rank_mean += r;
     }
     if (!P.aca_rank.empty()) st.aca_rank_mean /= static_cast<double>(P.aca_rank.size());
+    st.aca_flops = 0.0;
+    for (size_t b = 0; b < P.aca_rank.size() && b < P.bank_work.size(); ++b)
+      st.aca_flops += 16.0 * P.ip.K * P.aca_rank[b] * static_cast<double>(P.bank_work[b]);
+    st.aca_issued_flops = 16.0 * P.ip.Kp * P.aca_issued_cols;
     st.near_pairs = P.near_pairs;
     st.near_entries = P.near_entries;
     st.m2l_columns = issued_columns(P, P.tune);

@@ -164,13 +164,16 @@ struct Plan {
   int64_t n_bank_stored = 0;  // matrices in the resident bank
   // low-rank couplings (ACA, Sect. 2.7): per bank id the crosses of its
   // matrix as U (Kp x kp) and Vt (kp x Kp), FP32, and the rank reached; the
-  // coupling step runs two stages per chunk of items, T of a chunk in aca_T
+  // coupling step runs two stages per launch pair of offset groups, T of a
+  // launch pair in aca_T
   double aca_eps = 0;       // 0: dense couplings
   int aca_kp = 0;           // rank cap (32 or 64)
   DevBuf<float> aca_bank;
   std::vector<int32_t> aca_rank;
   DevBuf<float> aca_T;
-  int64_t aca_T_budget = int64_t(4) << 30;  // bytes of T per chunk
+  DevBuf<int32_t> aca_vo;  // the items' offsets, each item's by rank (highest first)
+  double aca_issued_cols = 0;  // sum over groups of offsets x 64 slots x padded rank
+  int64_t aca_T_budget = int64_t(8) << 30;  // bytes of T per launch pair
   DevBuf<double> bank64;
   DevBuf<float> bank32;
   DevBuf<uint16_t> bank16;

@@ -69,7 +69,8 @@ class Stats(ctypes.Structure):
                 ("near_entries", ctypes.c_int64), ("m2l_columns", ctypes.c_int64),
                 ("device_bytes", ctypes.c_int64), ("setup_ms", ctypes.c_double),
                 ("aca_rank_cap", ctypes.c_int32), ("aca_rank_max", ctypes.c_int32),
-                ("aca_rank_mean", ctypes.c_double)]
+                ("aca_rank_mean", ctypes.c_double), ("aca_flops", ctypes.c_double),
+                ("aca_issued_flops", ctypes.c_double)]
 
 
 def header_functions() -> list[str]:

@@ -34,17 +34,17 @@ _cache = {}
 BUDGET = {"uniform4m": 24 << 30}
 
 
-def run(name, prec):
+def run(name, prec, aca_eps=0.0):
     import torch
     import paper_2004_14229_amd as F
-    key = (name, prec)
+    key = (name, prec, aca_eps)
     if key not in _cache:
         P = W.config(name)
-        print(f"fullsize {name} {prec}", flush=True)
+        print(f"fullsize {name} {prec} aca_eps={aca_eps}", flush=True)
         pt = to_dev(P.points_T)
         ps = pt if P.same_points else to_dev(P.points_S)
         with F.Plan(pt, ps, P.kappa, P.box, P.levels, P.m, precision=prec,
-                    bank_budget=BUDGET.get(name, 0)) as plan:
+                    bank_budget=BUDGET.get(name, 0), aca_eps=aca_eps) as plan:
             y = plan.matvec(to_dev(P.v))
             torch.cuda.synchronize()
             _cache[key] = (y.cpu().numpy(), plan.stats())
@@ -70,7 +70,7 @@ def test_fp64_sampled_rows(name):
     if name == "paper_k6":  # Table 1, k = 6
         assert st["n_couplings"] == 166320 and st["n_stored_couplings"] == 1522
         assert round(100.0 * st["near_entries"] / 8 ** 12, 2) == 4.06
-        _cache.pop((name, "fp64"), None)
+        _cache.pop((name, "fp64", 0.0), None)
 
 
 @pytest.mark.parametrize("name", ["uniform100k", "uniform1m"])
@@ -80,7 +80,7 @@ def test_fp32_sampled_rows_and_full_vector(name):
     assert_close(y32[rows], yo, 1e-6)
     y64, _ = run(name, "fp64")
     assert_close(y32, y64, 1e-6)  # consistency over every row (GPU vs GPU)
-    _cache.pop((name, "fp64"), None)
+    _cache.pop((name, "fp64", 0.0), None)
 
 
 @pytest.mark.parametrize("name", ["uniform100k", "uniform1m"])
@@ -88,7 +88,7 @@ def test_bf16x3_sampled_rows(name):
     rows, yo = golden(name)
     _, ye = golden(name, "y_bf16x3")
     y, st = run(name, "bf16x3")
-    _cache.pop((name, "bf16x3"), None)
+    _cache.pop((name, "bf16x3", 0.0), None)
     assert np.all(np.isfinite(y))
     assert_close(y[rows], yo, 3 * rel(ye, yo))
 
@@ -100,9 +100,22 @@ def test_bf16x6_sampled_rows(name):
     rows, yo = golden(name)
     _, ye = golden(name, "y_bf16x6")
     y, st = run(name, "bf16x6")
-    _cache.pop((name, "bf16x6"), None)
+    _cache.pop((name, "bf16x6", 0.0), None)
     assert np.all(np.isfinite(y))
     assert_close(y[rows], yo, min(1e-6, 3 * rel(ye, yo)))
+
+
+@pytest.mark.parametrize("name", ["uniform100k", "uniform1m"])
+def test_aca_sampled_rows(name):
+    """Low-rank couplings (ACA to 1e-7, FP32 matrix-core stages) against the
+    oracle's dense-coupling rows: the mixed-precision bound 1e-6 covers the
+    compression and the FP32 arithmetic together."""
+    rows, yo = golden(name)
+    y, st = run(name, "fp32", 1e-7)
+    _cache.pop((name, "fp32", 1e-7), None)
+    assert np.all(np.isfinite(y))
+    assert 0 < st["aca_flops"] <= st["aca_issued_flops"]
+    assert_close(y[rows], yo, 1e-6)
 
 
 def test_structure_paper_grid_k6():
@@ -124,7 +137,7 @@ def test_uniform4m_sampled_rows(prec):
     six-product split within 1e-6 too)."""
     rows, yo = golden("uniform4m")
     y, st = run("uniform4m", prec)
-    _cache.pop(("uniform4m", prec), None)
+    _cache.pop(("uniform4m", prec, 0.0), None)
     assert np.all(np.isfinite(y))
     assert st["n_stored_couplings"] == 200258
     tol = 1e-6 if prec == "fp32" else 3 * rel(golden("uniform4m", f"y_{prec}")[1], yo)
