@@ -89,10 +89,16 @@ def _validate(box, kappa, levels, m):
 
 
 def build(points_T, points_S, kappa, box, levels, m, l_hf=None,
-          eta2=ETA2, rows=None) -> Plan:
+          eta2=ETA2, rows=None, n_max=None) -> Plan:
+    """Trees (Alg. 1; ``n_max=None``: uniform to depth ``levels``, else
+    adaptive with at most ``n_max`` points per leaf above that depth), block
+    tree (Alg. 2), directions (Alg. 3).  ``rows``: keep only what the given
+    target rows (user indices) need."""
     side = _validate(box, kappa, levels, m)
-    TT = build_box_tree(points_T, box, levels)
-    TS = build_box_tree(points_S, box, levels)
+    if n_max is not None and not (int(n_max) == n_max and n_max >= 0):
+        raise ValueError("n_max must be a non-negative integer")
+    TT = build_box_tree(points_T, box, levels, n_max)
+    TS = build_box_tree(points_S, box, levels, n_max)
     if l_hf is None:
         l_hf = high_frequency_level(kappa, side, levels)
     dirs = DirectionSets(l_hf, levels)
@@ -101,15 +107,12 @@ def build(points_T, points_S, kappa, box, levels, m, l_hf=None,
         rows = np.asarray(rows, dtype=np.int64)
         inv = np.empty(TT.n, dtype=np.int64)
         inv[TT.perm] = np.arange(TT.n)
-        leaf = TT.leaf_of_slot()[inv[rows]]
-        filt = [None] * (levels + 1)
-        box_idx = leaf
-        for level in range(levels, -1, -1):
+        filt = []
+        for level in range(levels + 1):  # boxes holding a requested row
+            b = TT.box_of_slots(level, inv[rows])
             mask = np.zeros(TT.keys[level].shape[0], dtype=bool)
-            mask[box_idx] = True
-            filt[level] = mask
-            if level > 0:
-                box_idx = TT.parent[level][box_idx]
+            mask[b[b >= 0]] = True
+            filt.append(mask)
     BT = block_tree(TT, TS, kappa, eta2, filt)
     DT, DhT, DS, DhS, cdir = active_directions(TT, TS, BT, dirs, side)
     return Plan(TT, TS, BT, dirs, float(kappa), m, l_hf, eta2,
@@ -223,23 +226,27 @@ def matvec(plan: Plan, v, chunk_points: int = 65536, keep: bool = False,
            for mode in modes}
     t_m2l = 0.0
 
-    # --- S2M (leaves of T_S) ----------------------------------------------
+    def s2m(level):
+        """S2M for the leaves of T_S on ``level``."""
+        need = (plan.DS[level] | plan.DhS[level]) & TS.is_leaf(level)[:, None]
+        cvec = dirs.vectors(level)
+        for c in range(need.shape[1]):
+            leaves = np.flatnonzero(need[:, c])
+            for a, b in _chunks(TS.count[level][leaves], chunk_points):
+                lv = leaves[a:b]
+                slots, owner = _segments(TS.start[level][lv], TS.count[level][lv])
+                y = TS.points[slots]
+                L = interpolation_rows(y, TS.lo[level][lv][owner], TS.hi[level][lv][owner], m)
+                # conj(L_{s,c}) rows times v: L_{s,nu}(y) exp(-i kappa <y,c>) v
+                w = np.exp(-1j * kappa * (y @ cvec[c])) * vt[slots]
+                contrib = L * w[:, None]
+                seg = np.concatenate(([0], np.cumsum(TS.count[level][lv])[:-1]))
+                mom[level][lv, c] = np.add.reduceat(contrib, seg, axis=0)
+
+    # --- S2M (leaves of T_S on the last level; other levels' leaves below) -
     mom = [None] * (p + 1)
-    need = plan.DS[p] | plan.DhS[p]
-    mom[p] = np.zeros(need.shape + (K,), dtype=np.complex128)
-    cvec = dirs.vectors(p)
-    for c in range(need.shape[1]):
-        leaves = np.flatnonzero(need[:, c])
-        for a, b in _chunks(TS.count[p][leaves], chunk_points):
-            lv = leaves[a:b]
-            slots, owner = _segments(TS.start[p][lv], TS.count[p][lv])
-            y = TS.points[slots]
-            L = interpolation_rows(y, TS.lo[p][lv][owner], TS.hi[p][lv][owner], m)
-            # conj(L_{s,c}) rows times v: L_{s,nu}(y) exp(-i kappa <y,c>) v
-            w = np.exp(-1j * kappa * (y @ cvec[c])) * vt[slots]
-            contrib = L * w[:, None]
-            seg = np.concatenate(([0], np.cumsum(TS.count[p][lv])[:-1]))
-            mom[p][lv, c] = np.add.reduceat(contrib, seg, axis=0)
+    mom[p] = np.zeros((plan.DS[p] | plan.DhS[p]).shape + (K,), dtype=np.complex128)
+    s2m(p)
     plan.timings["s2m"] = time.perf_counter() - t0
 
     # --- M2M (levels p-1 .. 0), each level's coupling step once its moments
@@ -252,7 +259,7 @@ def matvec(plan: Plan, v, chunk_points: int = 65536, keep: bool = False,
             par_dir = dirs.parent_index(level)
             cv, cv1 = dirs.vectors(level), dirs.vectors(level + 1)
             for c in range(need.shape[1]):
-                all_parents = np.flatnonzero(need[:, c])
+                all_parents = np.flatnonzero(need[:, c] & ~TS.is_leaf(level))
                 cp = par_dir[c]
                 for a in range(0, all_parents.size, chunk_boxes):
                     parents = all_parents[a:a + chunk_boxes]
@@ -269,6 +276,7 @@ def matvec(plan: Plan, v, chunk_points: int = 65536, keep: bool = False,
                             contrib[sel] = w[sel] @ Eref[q]  # rows of E_{s'}^T w
                     seg = np.concatenate(([0], np.cumsum(TS.child_count[level][parents])[:-1]))
                     mom[level][parents, c] = np.add.reduceat(contrib, seg, axis=0)
+            s2m(level)  # leaves of this level (adaptive trees)
         t2 = time.perf_counter()
         for mode in modes:
             _coupling_level(plan, level + 1, mom[level + 1], loc[mode][level + 1], mode)
@@ -303,7 +311,7 @@ def matvec(plan: Plan, v, chunk_points: int = 65536, keep: bool = False,
             par_dir = dirs.parent_index(level)
             cv, cv1 = dirs.vectors(level), dirs.vectors(level + 1)
             for c in range(need.shape[1]):
-                all_parents = np.flatnonzero(need[:, c])
+                all_parents = np.flatnonzero(need[:, c] & ~TT.is_leaf(level))
                 cp = par_dir[c]
                 for a in range(0, all_parents.size, chunk_boxes):
                     parents = all_parents[a:a + chunk_boxes]
@@ -321,39 +329,42 @@ def matvec(plan: Plan, v, chunk_points: int = 65536, keep: bool = False,
                     lm[level + 1][ch, cp] += Ed * Eg
         plan.timings["l2l"] = time.perf_counter() - t3
 
-        # --- L2T (leaves of T_T) -------------------------------------------
+        # --- L2T (leaves of T_T, last level first) -------------------------
         t4 = time.perf_counter()
         g_tree = np.zeros(TT.n, dtype=np.complex128)
-        need = plan.DT[p] | plan.DhT[p]
-        cvec = dirs.vectors(p)
-        for c in range(need.shape[1]):
-            leaves = np.flatnonzero(need[:, c])
-            for a, b in _chunks(TT.count[p][leaves], chunk_points):
-                lv = leaves[a:b]
-                slots, owner = _segments(TT.start[p][lv], TT.count[p][lv])
-                if plan.rows is not None:
-                    sel = want[slots]
-                    slots, owner = slots[sel], owner[sel]
-                x = TT.points[slots]
-                L = interpolation_rows(x, TT.lo[p][lv][owner], TT.hi[p][lv][owner], m)
-                ph = np.exp(1j * kappa * (x @ cvec[c]))
-                g_tree[slots] += ph * np.einsum("nk,nk->n", L, lm[p][lv[owner], c])
+        for lev in [p] + list(range(p)):
+            need = (plan.DT[lev] | plan.DhT[lev]) & TT.is_leaf(lev)[:, None]
+            cvec = dirs.vectors(lev)
+            for c in range(need.shape[1]):
+                leaves = np.flatnonzero(need[:, c])
+                for a, b in _chunks(TT.count[lev][leaves], chunk_points):
+                    lv = leaves[a:b]
+                    slots, owner = _segments(TT.start[lev][lv], TT.count[lev][lv])
+                    if plan.rows is not None:
+                        sel = want[slots]
+                        slots, owner = slots[sel], owner[sel]
+                    x = TT.points[slots]
+                    L = interpolation_rows(x, TT.lo[lev][lv][owner], TT.hi[lev][lv][owner], m)
+                    ph = np.exp(1j * kappa * (x @ cvec[c]))
+                    g_tree[slots] += ph * np.einsum("nk,nk->n", L, lm[lev][lv[owner], c])
         plan.timings["l2t"] = time.perf_counter() - t4
 
-        # --- near field -------------------------------------------------------
+        # --- near field (inadmissible leaf blocks, last level first) ---------
         t5 = time.perf_counter()
-        nt, ns = BT.near_t[p], BT.near_s[p]
-        if nt.size:
-            tslots, towner = _segments(TT.start[p][nt], TT.count[p][nt])
+        for lev in [p] + list(range(p)):
+            nt, ns = BT.near_t[lev], BT.near_s[lev]
+            if not nt.size:
+                continue
+            tslots, towner = _segments(TT.start[lev][nt], TT.count[lev][nt])
             if plan.rows is not None:
                 sel = want[tslots]
                 tslots, towner = tslots[sel], towner[sel]
             # every target slot meets every source slot of its pair's source box
             srcs = ns[towner]
-            cnt = TS.count[p][srcs]
+            cnt = TS.count[lev][srcs]
             for a, b in _chunks(cnt, 4 * chunk_points):
                 ts = tslots[a:b]
-                sl, own = _segments(TS.start[p][srcs[a:b]], cnt[a:b])
+                sl, own = _segments(TS.start[lev][srcs[a:b]], cnt[a:b])
                 tj = ts[own]
                 d = TT.points[tj] - TS.points[sl]
                 # f(x, y) = 0 exactly when the two points coincide (diagonal)
@@ -373,9 +384,9 @@ def matvec(plan: Plan, v, chunk_points: int = 65536, keep: bool = False,
 
 
 def sample_rows(points_T, points_S, v, kappa, box, levels, m, rows,
-                l_hf=None, eta2=ETA2) -> np.ndarray:
+                l_hf=None, eta2=ETA2, n_max=None) -> np.ndarray:
     """Alg. 4 evaluated at the given target rows only (user indices)."""
-    plan = build(points_T, points_S, kappa, box, levels, m, l_hf, eta2, rows)
+    plan = build(points_T, points_S, kappa, box, levels, m, l_hf, eta2, rows, n_max)
     return matvec(plan, v)
 
 
@@ -416,8 +427,11 @@ def structure(plan: Plan) -> dict:
                        ("Dh_S", plan.DhS)):
             b, c = np.nonzero(D[l])
             out[f"{tag}{l}"] = np.sort(b * D[l].shape[1] + c)
-    nt, ns = plan.BT.near_t[p], plan.BT.near_s[p]
-    out["near_pairs"] = np.array([nt.shape[0]])
-    out["near_entries"] = np.array([int(np.sum(plan.TT.count[p][nt] *
-                                               plan.TS.count[p][ns]))])
+    pairs = entries = 0
+    for l in range(p + 1):  # inadmissible leaf blocks of every level
+        nt, ns = plan.BT.near_t[l], plan.BT.near_s[l]
+        pairs += nt.shape[0]
+        entries += int(np.sum(plan.TT.count[l][nt] * plan.TS.count[l][ns]))
+    out["near_pairs"] = np.array([pairs])
+    out["near_entries"] = np.array([entries])
     return out

@@ -18,6 +18,8 @@ Reading taken here: both criteria are compared in squared form in FP64,
 Alg. 2 builds the block tree from the pair of roots: a pair with a leaf on
 either side is a leaf block; otherwise a pair violating (A1) or (A3) is split
 into all pairs of children; a pair satisfying both is an admissible leaf.
+With adaptive trees (Alg. 1's n_max rule) inadmissible leaf blocks occur on
+every level, between a leaf and a box of any size.
 The recursion is carried out level by level over arrays of pairs; an optional
 target filter keeps only pairs whose target box is listed (exact for the rows
 below those boxes, used by the row-sampled oracle).
@@ -55,6 +57,7 @@ class BlockTree:
     adm_s: list  # per level: source box indices of admissible leaves
     near_t: list  # per level: target box of inadmissible leaves
     near_s: list  # per level: source box of inadmissible leaves
+    # (uniform trees: only on the last level)
 
     def n_admissible(self) -> int:
         return int(sum(a.shape[0] for a in self.adm_t))
@@ -85,19 +88,22 @@ def block_tree(TT: BoxTree, TS: BoxTree, kappa: float, eta2: float = ETA2,
         ok = admissible(kappa, h_root * 2.0 ** (-level), o, eta2)
         adm_t.append(t[ok])
         adm_s.append(s[ok])
-        if level == p:  # both boxes are leaves: the pair is a leaf block
-            near_t.append(t[~ok])
-            near_s.append(s[~ok])
+        # a pair with a leaf on either side is a leaf block (inadmissible
+        # ones form the near field); other inadmissible pairs are refined
+        leaf = TT.is_leaf(level)[t] | TS.is_leaf(level)[s]
+        near = ~ok & leaf
+        near_t.append(t[near])
+        near_s.append(s[near])
+        if level == p:  # every box of the last level is a leaf
             break
-        near_t.append(np.zeros(0, dtype=np.int64))
-        near_s.append(np.zeros(0, dtype=np.int64))
-        rt, rs = t[~ok], s[~ok]  # refine: all pairs of children
+        refine = ~ok & ~leaf
+        rt, rs = t[refine], s[refine]  # refine: all pairs of children
         ct = TT.child_count[level][rt]
         cs = TS.child_count[level][rs]
         npairs = ct * cs
         rep_t = np.repeat(rt, npairs)
         rep_s = np.repeat(rs, npairs)
-        first = np.concatenate(([0], np.cumsum(npairs)[:-1]))
+        first = np.cumsum(npairs) - npairs
         local = np.arange(rep_t.shape[0]) - np.repeat(first, npairs)
         cs_rep = np.repeat(cs, npairs)
         t = TT.child_start[level][rep_t] + local // cs_rep

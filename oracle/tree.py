@@ -6,10 +6,13 @@ only children that contain a point, and recursing.
 
 Readings taken here (the paper leaves them open):
 
-* Stop rule.  The paper stops at ``n_max`` points per leaf; this build gives
-  the depth instead: every non-empty box above level ``levels`` is split, so
-  all leaves sit at level ``levels`` (the paper's own test trees are uniform
-  octrees of fixed depth, Sect. 4).
+* Stop rule.  Alg. 1 refines a box while it holds more than ``n_max``
+  points.  Here the depth is also capped at ``levels`` (a box at that level is
+  a leaf whatever its count; Alg. 1 alone never stops on coincident points).
+  ``n_max=None`` refines every non-empty box down to ``levels``, so all
+  leaves sit on that level: the uniform octrees of fixed depth that the
+  paper's own tests use (Sect. 4).  With ``n_max`` given, leaves sit on
+  several levels (an adaptive tree).
 * A point ``x`` lies in the upper child along axis ``d`` iff ``x_d > c_d``
   (the boxes are half-open at the lower end), with ``c_d`` computed as
   ``0.5*(lo_d + hi_d)`` from the parent's bounds, level by level.
@@ -57,9 +60,19 @@ class BoxTree:
     def centres(self, level: int) -> np.ndarray:
         return 0.5 * (self.lo[level] + self.hi[level])
 
-    def leaf_of_slot(self) -> np.ndarray:
-        p = self.levels
-        return np.repeat(np.arange(self.keys[p].shape[0]), self.count[p])
+    def is_leaf(self, level: int) -> np.ndarray:
+        """Leaves of ``level``: boxes without children."""
+        return self.child_count[level] == 0
+
+    def box_of_slots(self, level: int, slots: np.ndarray) -> np.ndarray:
+        """Box of ``level`` holding each tree slot, -1 where the slot lies
+        below a leaf of a coarser level."""
+        slots = np.asarray(slots, dtype=np.int64)
+        b = np.searchsorted(self.start[level], slots, side="right") - 1
+        ok = b >= 0
+        bb = np.where(ok, b, 0)
+        ok &= slots < self.start[level][bb] + self.count[level][bb]
+        return np.where(ok, b, -1)
 
 
 def _deinterleave(keys: np.ndarray, level: int) -> np.ndarray:
@@ -82,8 +95,10 @@ def check_inside(points: np.ndarray, lo: np.ndarray, hi: np.ndarray) -> None:
         raise ValueError("point outside the half-open root box (a, b]")
 
 
-def build_box_tree(points, box, levels: int) -> BoxTree:
-    """Alg. 1 with every non-empty box refined down to level ``levels``."""
+def build_box_tree(points, box, levels: int, n_max: int | None = None) -> BoxTree:
+    """Alg. 1: a non-empty box is refined while it holds more than ``n_max``
+    points and lies above level ``levels`` (``n_max=None``: every non-empty
+    box above ``levels``)."""
     pts = np.ascontiguousarray(np.asarray(points, dtype=np.float64).reshape(-1, 3))
     root_lo = np.asarray(box[:3], dtype=np.float64)
     root_hi = np.asarray(box[3:], dtype=np.float64)
@@ -115,10 +130,22 @@ def build_box_tree(points, box, levels: int) -> BoxTree:
         else:
             first = np.zeros(0, dtype=bool)
         st = np.flatnonzero(first).astype(np.int64)
-        keys.append(k[st])
+        kk = k[st]
+        cnt = np.diff(np.concatenate((st, [n]))).astype(np.int64)
+        if n_max is not None and level > 0:
+            # a box exists if its parent exists and holds more than n_max
+            # points (the boxes of the previous level are those that exist)
+            pk = kk >> 3
+            npar = keys[level - 1].shape[0]
+            exists = np.zeros(kk.shape[0], dtype=bool)
+            if npar:
+                pi = np.minimum(np.searchsorted(keys[level - 1], pk), npar - 1)
+                exists = (keys[level - 1][pi] == pk) & (count[level - 1][pi] > n_max)
+            st, kk, cnt = st[exists], kk[exists], cnt[exists]
+        keys.append(kk)
         start.append(st)
-        count.append(np.diff(np.concatenate((st, [n]))).astype(np.int64))
-        coords.append(_deinterleave(k[st], level))
+        count.append(cnt)
+        coords.append(_deinterleave(kk, level))
 
     # Box bounds from the same centre recursion as the point classification.
     blo = [root_lo[None, :].copy() if n else np.zeros((0, 3))]

@@ -100,8 +100,8 @@ def _literal_block_tree(TT, TS, kappa):
     def refine(level, t, s):
         o = TT.coords[level][t] - TS.coords[level][s]
         ok = bool(oracle.admissible(kappa, TT.side(level), o))
-        if level == TT.levels:
-            (adm if ok else near).append((level, t, s))
+        if TT.child_count[level][t] == 0 or TS.child_count[level][s] == 0:
+            (adm if ok else near).append((level, t, s))  # t or s is a leaf
             return
         if ok:
             adm.append((level, t, s))
