@@ -78,10 +78,12 @@ typedef enum {
  *            level is split (leaves all sit on this level).  levels outside
  *            0..9 give FDM_ERR_INVALID_ARG.
  *  m         Chebyshev degree per axis: (m+1)^3 nodes per box.  m outside
- *            1..8 gives FDM_ERR_INVALID_ARG; m = 7 and 8 give
- *            FDM_ERR_UNSUPPORTED, because the coupling kernels give one
- *            wave to each 32 of the (m+1)^3 nodes padded to a multiple of 32
- *            and hold at most 384 of them (m <= 6).
+ *            1..8 gives FDM_ERR_INVALID_ARG.  The coupling kernels give one
+ *            wave to each 32 of the (m+1)^3 nodes padded to a multiple of
+ *            32, at most 384 rows per workgroup: at m = 7 and 8 (512 and
+ *            736 padded rows) each coupling item runs once per row block.
+ *            Low-rank couplings (aca_eps > 0) need m <= 6
+ *            (FDM_ERR_UNSUPPORTED).
  *  precision an fdm_precision.
  *  stream    HIP stream for the device work; the call synchronises it
  *            before returning (box counts size the plan).
@@ -180,6 +182,14 @@ typedef struct {
  *                     and cut into groups of 16 (each run at its padded
  *                     rank); a launch pair covers one group of as many items
  *                     as fit (at least one).  0: 8 GiB; >= 0.
+ *  n_max              Alg. 1's stop rule (Sect. 2.1): a box is refined only
+ *                     while it holds more than n_max points (and lies above
+ *                     level `levels`), so leaves sit on several levels and
+ *                     near-field blocks (a leaf against a box of any size)
+ *                     on every level (Alg. 2).  0: every non-empty box is
+ *                     refined down to `levels` (a uniform tree).  >= 0 (else
+ *                     FDM_ERR_INVALID_ARG); when > 0 the near field never
+ *                     shares the coupling queue.
  */
 typedef struct {
   int32_t precision;
@@ -190,6 +200,7 @@ typedef struct {
   int32_t aca_rank;
   double aca_eps;
   int64_t aca_chunk_bytes;
+  int64_t n_max;
 } fdm_options;
 
 /* fdm_build_tree with options (opts host, not NULL). */
@@ -371,7 +382,8 @@ int fdm_dense_matvec(const double* points_T, int64_t n_T,
  * and wave numbers, one launch sequence).
  *
  * fdm_batch_create -- group n plans (same m and precision, each in at most
- * one batch) into a batch.  The plans stay owned by the caller and must
+ * one batch, none with low-rank couplings: FDM_ERR_UNSUPPORTED) into a
+ * batch.  The plans stay owned by the caller and must
  * outlive the batch; while they belong to it they cannot be re-tuned or
  * destroyed (FDM_ERR_STATE).  Plans built with bank_budget_bytes > 0 have
  * their coupling banks generated during each batched matvec into one

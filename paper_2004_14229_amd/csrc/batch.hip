@@ -42,7 +42,7 @@ void batch_enqueue(fdm_batch& b, const void* const* v, void* const* y, bool c64,
       plan_zero_output(P, y[i], c64, s);
       continue;
     }
-    if (!b.tune.p2p_in_queue || !p2p_queue_supported(b.prec, b.ip.Kp)) launch_p2p(P, s);
+    if (!p2p_queued(P, b.tune)) launch_p2p(P, s);
     plan_downward(P, y[i], c64, s);
   }
 }
@@ -197,6 +197,8 @@ int fdm_batch_create(fdm_plan* const* plans, int n, int64_t workspace_bytes, voi
       if (plans[i]->p.batch_owner) fail(FDM_ERR_STATE, "a plan already belongs to a batch");
       if (plans[i]->p.m != plans[0]->p.m || plans[i]->p.prec != plans[0]->p.prec)
         fail(FDM_ERR_UNSUPPORTED, "plans of a batch must share m and precision");
+      if (plans[i]->p.aca_kp)
+        fail(FDM_ERR_UNSUPPORTED, "plans with low-rank couplings cannot join a batch");
     }
     hipStream_t s = static_cast<hipStream_t>(stream);
     auto* b = new fdm_batch();

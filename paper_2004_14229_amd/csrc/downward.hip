@@ -96,14 +96,16 @@ __global__ void __launch_bounds__(kXT) k_l2l(
 __global__ void __launch_bounds__(64) k_l2t(
     const double* __restrict__ x, const double* __restrict__ y,
     const double* __restrict__ z, const uint32_t* __restrict__ key,
-    const int32_t* __restrict__ start, const int32_t* __restrict__ count, int64_t nb,
+    const int32_t* __restrict__ start, const int32_t* __restrict__ count,
+    const int32_t* __restrict__ boxes, int64_t nb,
     int level, double lo0, double lo1, double lo2, double h,
     const double* __restrict__ dirvec, int nd, double kappa, Interp ip,
     const double2* __restrict__ loc, double2* __restrict__ y_tree) {
   __shared__ double lag[3][kMaxM1];
   const int lane = threadIdx.x;
   const int m1 = ip.m1, K = ip.K, Kp = ip.Kp;
-  for (int64_t b = blockIdx.x; b < nb; b += gridDim.x) {
+  for (int64_t bi = blockIdx.x; bi < nb; bi += gridDim.x) {
+    const int64_t b = boxes ? boxes[bi] : bi;
     int ix, iy, iz;
     demorton3(key[b], level, ix, iy, iz);
     const double mx = lo0 + (ix + 0.5) * h, my = lo1 + (iy + 0.5) * h,
@@ -181,18 +183,27 @@ void launch_l2l(Plan& P, int level, hipStream_t s) {
   FDM_LAUNCH("k_l2l");
 }
 
-void launch_l2t(Plan& P, hipStream_t s) {
-  const int p = P.levels;
-  const int64_t nb = P.T.nb[p];
-  if (P.nT == 0) return;
-  if (P.l_min > p || nb == 0) return;  // no coupling anywhere: the far field is zero
-  LevelData& Lp = P.L[p];
+void launch_l2t_boxes(Plan& P, int level, const int32_t* boxes, int64_t nb, hipStream_t s) {
+  if (P.nT == 0 || nb == 0) return;
+  if (level < P.l_min) return;  // no coupling on or above it: the far field is zero
+  LevelData& Lp = P.L[level];
   k_l2t<<<static_cast<unsigned>(std::min<int64_t>(nb, 1 << 20)), 64, 0, s>>>(
-      P.T.x.get(), P.T.y.get(), P.T.z.get(), P.T.key[p].get(), P.T.start[p].get(),
-      P.T.count[p].get(), nb, p, P.lo[0], P.lo[1], P.lo[2], Lp.h, Lp.dirvec.get(), Lp.nd,
-      P.kappa, P.ip, reinterpret_cast<const double2*>(Lp.loc64.get()),
+      P.T.x.get(), P.T.y.get(), P.T.z.get(), P.T.key[level].get(), P.T.start[level].get(),
+      P.T.count[level].get(), boxes, nb, level, P.lo[0], P.lo[1], P.lo[2], Lp.h,
+      Lp.dirvec.get(), Lp.nd, P.kappa, P.ip, reinterpret_cast<const double2*>(Lp.loc64.get()),
       reinterpret_cast<double2*>(P.y_tree.get()));
   FDM_LAUNCH("k_l2t");
+}
+
+void launch_l2t(Plan& P, hipStream_t s) {
+  const int p = P.levels;
+  if (!P.adaptive()) {
+    launch_l2t_boxes(P, p, nullptr, P.T.nb[p], s);
+    return;
+  }
+  // adaptive trees: the leaves of every level, last level first
+  launch_l2t_boxes(P, p, P.leafT[p].get(), P.n_leafT[p], s);
+  for (int l = 0; l < p; ++l) launch_l2t_boxes(P, l, P.leafT[l].get(), P.n_leafT[l], s);
 }
 
 }  // namespace fdm

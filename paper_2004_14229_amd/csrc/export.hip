@@ -32,9 +32,16 @@ std::vector<std::set<int>> active_dirs(const Plan& P, int l, bool target) {
   if (A.nb[l] == 0 || B.nb[l] == 0 || l < P.l_min) return D;
   std::vector<uint32_t> keys = to_host(A.key[l].get(), A.nb[l], nullptr);
   std::vector<int32_t> grid = to_host(B.grid[l].get(), size_t(1) << (3 * l), nullptr);
+  if (P.adaptive()) {  // only boxes that exist in the adaptive trees
+    const auto& sb = target ? P.stateS_h[l] : P.stateT_h[l];
+    for (auto& g : grid)
+      if (g >= 0 && sb[g] == 0) g = -1;
+  }
+  const auto* sa = P.adaptive() ? &(target ? P.stateT_h : P.stateS_h)[l] : nullptr;
   const LevelTable& T = P.tab[l];
   const int lim = 1 << l;
   for (size_t b = 0; b < keys.size(); ++b) {
+    if (sa && (*sa)[b] == 0) continue;
     int ix, iy, iz;
     demorton3(keys[b], l, ix, iy, iz);
     for (size_t i = 0; i < T.adm.size(); ++i) {
@@ -50,10 +57,27 @@ std::vector<std::set<int>> active_dirs(const Plan& P, int l, bool target) {
   return D;
 }
 
-std::vector<int64_t> dir_codes(const std::vector<std::set<int>>& D, int nd) {
+// Codes box * nd + c; with `state` (adaptive trees) boxes are numbered
+// among those that exist.
+std::vector<int64_t> dir_codes(const std::vector<std::set<int>>& D, int nd,
+                               const std::vector<uint8_t>* state = nullptr) {
   std::vector<int64_t> out;
-  for (size_t b = 0; b < D.size(); ++b)
-    for (int c : D[b]) out.push_back(int64_t(b) * nd + c);
+  int64_t idx = 0;
+  for (size_t b = 0; b < D.size(); ++b) {
+    if (state && (*state)[b] == 0) continue;
+    for (int c : D[b]) out.push_back(idx * nd + c);
+    ++idx;
+  }
+  return out;
+}
+
+// Values of the boxes that exist in the adaptive trees (all for uniform ones).
+std::vector<int64_t> existing(const Plan& P, const std::vector<int64_t>& v, bool target, int l) {
+  if (!P.adaptive()) return v;
+  const auto& st = (target ? P.stateT_h : P.stateS_h)[l];
+  std::vector<int64_t> out;
+  for (size_t b = 0; b < v.size(); ++b)
+    if (st[b] != 0) out.push_back(v[b]);
   return out;
 }
 
@@ -76,9 +100,10 @@ std::vector<int64_t> export_int(const Plan& P, const std::string& name, bool& fo
         int l = lev(pre.size());
         if (l < 0 || l > P.levels) break;
         if (A.n == 0) return {};
-        if (what[0] == 'k') return widen_u32(A.key[l].get(), A.nb[l]);
-        if (what[0] == 's') return widen_i32(A.start[l].get(), A.nb[l]);
-        return widen_i32(A.count[l].get(), A.nb[l]);
+        const bool tg = tag[0] == 'T';
+        if (what[0] == 'k') return existing(P, widen_u32(A.key[l].get(), A.nb[l]), tg, l);
+        if (what[0] == 's') return existing(P, widen_i32(A.start[l].get(), A.nb[l]), tg, l);
+        return existing(P, widen_i32(A.count[l].get(), A.nb[l]), tg, l);
       }
     }
   }
@@ -116,7 +141,9 @@ std::vector<int64_t> export_int(const Plan& P, const std::string& name, bool& fo
       if (l < 0 || l > P.levels) break;
       const bool target = pre.back() == 'T';
       const int nd = direction_count(l, P.l_hf);
-      if (pre[1] != 'h') return dir_codes(active_dirs(P, l, target), nd);
+      const std::vector<uint8_t>* st =
+          P.adaptive() ? &(target ? P.stateT_h : P.stateS_h)[l] : nullptr;
+      if (pre[1] != 'h') return dir_codes(active_dirs(P, l, target), nd, st);
       // inherited: D^(t) = { dir_(l)(c) : c in D(t') u D^(t'), t' = parent(t) }
       const DevTree& A = target ? P.T : P.S;
       std::vector<std::set<int>> up;  // D u D^ of the boxes one level up
@@ -131,7 +158,7 @@ std::vector<int64_t> export_int(const Plan& P, const std::string& name, bool& fo
             for (int c : up[par]) Dh[b].insert(k <= P.l_hf ? (c >> 2) : 0);
           }
         }
-        if (k == l) return dir_codes(Dh, nd);
+        if (k == l) return dir_codes(Dh, nd, st);
         up.assign(A.nb[k], {});
         for (size_t b = 0; b < Dk.size(); ++b) {
           up[b] = Dk[b];

@@ -155,7 +155,15 @@ __global__ void __launch_bounds__(64) k_valid_offsets(
 
 }  // namespace
 
-int m2l_threads(int Kp) { return std::max(2 * Kp, 512); }  // one wave per 32 rows, >= 8 waves
+// Row blocks of a coupling matrix of Kp rows, and the workgroup size: one
+// wave per 32 rows of a block, at least 8 waves.
+int m2l_row_blocks(int Kp) { return (Kp + kMaxKp - 1) / kMaxKp; }
+
+int m2l_threads(int Kp) {
+  const int rb = m2l_row_blocks(Kp);
+  const int rows = ((Kp + rb - 1) / rb + 31) / 32 * 32;
+  return std::max(2 * rows, 512);
+}
 
 int64_t m2l_resident_groups(int prec, int nb, int Kp, bool parts) {
   if (prec == FDM_PREC_FP64) return resident_f64(nb, Kp, parts);

@@ -181,6 +181,13 @@ __device__ __forceinline__ const __attribute__((address_space(4))) T* cmem(const
   return (const __attribute__((address_space(4))) T*)p;
 }
 
+// Row tile (of 32 coupling-matrix rows) owned by this wave.  A matrix with
+// more rows than one workgroup's waves cover runs each item once per row
+// block: `first` >> 1 is the block, bit 0 the first-part flag.
+__device__ __forceinline__ int row_wave(const M2LItem& it) {
+  return threadIdx.x / 64 + (it.first >> 1) * (blockDim.x / 64);
+}
+
 __device__ __forceinline__ int4 offset_of(const M2LDesc& D, int32_t vo) {
   const int32_t b = *cmem(D.valid_off + vo);
   const int32_t* o = reinterpret_cast<const int32_t*>(D.offtab) + 4 * int64_t(b);
@@ -372,7 +379,7 @@ template <int NB, bool ADD>
 __device__ __forceinline__ void item_f64(F64Shared<NB>& sh, const M2LItem& it,
                                          const M2LDesc& D, int Kp) {
   using Tr = F64Traits;
-  const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+  const int wave = row_wave(it), lane = threadIdx.x % 64;
   const bool rows_here = 32 * wave < Kp;  // waves past Kp only help with loads
   load_targets(sh.S, it, D);
   __syncthreads();
@@ -424,7 +431,7 @@ __device__ __forceinline__ void item_f64(F64Shared<NB>& sh, const M2LItem& it,
     for (; q < total; ++q) step(std::true_type{}, q);
   }
   if (rows_here) {
-    if (!ADD || it.first)
+    if (!ADD || (it.first & 1))
       flush_rows64<NB, true>(acr, aci, sh.S, out, D.nd, it.c, Kp, wave, lane);
     else if (nv > 0)  // later part of a split item (streamed bank): add
       flush_rows64<NB, false>(acr, aci, sh.S, out, D.nd, it.c, Kp, wave, lane);
@@ -542,7 +549,7 @@ __device__ __forceinline__ void item_f32(F32Shared<NB>& sh, const M2LItem& it,
                                          const M2LDesc& D, int Kp) {
   using Tr = F32Traits;
   constexpr int NT = NB / 32;
-  const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+  const int wave = ACA ? threadIdx.x / 64 : row_wave(it), lane = threadIdx.x % 64;
   const bool rows_here = 32 * wave < Kp;
   load_targets(sh.S, it, D);
   __syncthreads();
@@ -942,7 +949,7 @@ template <int NB, bool ADD, int SPLIT>
 __device__ __forceinline__ void item_bf16(BF16SharedS<NB, SPLIT>& sh, const M2LItem& it,
                                           const M2LDesc& D, int Kp) {
   constexpr int NT = NB / 32;
-  const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+  const int wave = row_wave(it), lane = threadIdx.x % 64;
   const bool rows_here = 32 * wave < Kp;
   load_targets(sh.S, it, D);
   __syncthreads();
@@ -953,7 +960,7 @@ __device__ __forceinline__ void item_bf16(BF16SharedS<NB, SPLIT>& sh, const M2LI
   zero(aci);
   const int nv = it.vo_count;
   if (nv == 0) {  // no source box: the result is zero
-    if (rows_here && it.first)
+    if (rows_here && (it.first & 1))
       flush_rows32<NB>(acr, aci, sh.S, out, D.nd, it.c, Kp, wave, lane, true);
     return;
   }
@@ -984,7 +991,7 @@ __device__ __forceinline__ void item_bf16(BF16SharedS<NB, SPLIT>& sh, const M2LI
   __syncthreads();
   store(0, load(0, 0));
   __syncthreads();
-  bool first = it.first != 0;
+  bool first = (it.first & 1) != 0;
   for (int q = 0; q < total; ++q) {
     const int v = q / ns, s = q % ns, cur = q & 1;
     if (s == 0) {
@@ -1048,7 +1055,7 @@ __device__ __forceinline__ void item_compact(SH& sh, const M2LItem& it, const M2
   constexpr bool BF16 = MODE != 0;
   constexpr int KS = 16;  // k per slab in both precisions
   static_assert(F32Traits::KS == KS && kBKS == KS, "one slab size");
-  const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+  const int wave = row_wave(it), lane = threadIdx.x % 64;
   const bool rows_here = 32 * wave < Kp;
   load_targets(sh.S, it, D);
   __syncthreads();
@@ -1058,7 +1065,7 @@ __device__ __forceinline__ void item_compact(SH& sh, const M2LItem& it, const M2
   zero(toi);
   const int nv = it.vo_count;
   if (nv == 0) {  // no source box: the result is zero
-    if (rows_here && it.first)
+    if (rows_here && (it.first & 1))
       flush_rows32<64>(tor, toi, sh.S, out, D.nd, it.c, Kp, wave, lane, true);
     return;
   }
@@ -1092,7 +1099,7 @@ __device__ __forceinline__ void item_compact(SH& sh, const M2LItem& it, const M2
   int np = passes(0);
   stage(0, load(0, 0, 0));
   __syncthreads();
-  bool first = it.first != 0;
+  bool first = (it.first & 1) != 0;
   f16v acr[1], aci[1];
   f16v bgr[1], bgi[1];  // per-pass hi * hi sums (MODE 6, see mfma_bf16x6)
   int v = 0, p = 0, s = 0, cur = 0;

@@ -49,7 +49,7 @@ namespace {
 M2LDesc level_desc(const Plan& P, int l, const void* bank, int64_t bank_id0) {
   const LevelData& Ld = P.L[l];
   M2LDesc d{};
-  d.gridS = P.S.grid[l].get();
+  d.gridS = P.adaptive() ? P.gridS_alive[l].get() : P.S.grid[l].get();
   d.keyT = P.T.key[l].get();
   d.mom = P.prec == FDM_PREC_FP64    ? static_cast<const void*>(Ld.mom64.get())
           : P.prec == FDM_PREC_BF16X6 ? static_cast<const void*>(Ld.mom16.get())
@@ -97,6 +97,7 @@ void add_source(LaunchBuilder& B, const Plan& P, int64_t b0, int64_t b1, const v
     B.descs.push_back(level_desc(P, l, bank, b0 - slot0));
   }
   const auto& vo = P.valid_off_h;
+  const int row_blocks = m2l_row_blocks(P.ip.Kp);
   for (size_t i = 0; i < P.base_items.size(); ++i) {
     const M2LItem& it = P.base_items[i];
     M2LItem o = it;
@@ -115,12 +116,17 @@ void add_source(LaunchBuilder& B, const Plan& P, int64_t b0, int64_t b1, const v
       o.first = emitted[i] ? 0 : 1;
     }
     emitted[i] = 1;
-    B.items.push_back(o);
-    // plain: nb / 32 tiles per offset; compacted: the item's tiles, shared
-    // over its parts in proportion to their offsets
-    B.weight.push_back(o.compact ? double(P.item_tiles[i]) * o.vo_count /
-                                       std::max(it.vo_count, 1)
-                                 : double(o.vo_count) * cfg.nb / 32);
+    // one item per row block of the matrices (disjoint rows of the result)
+    for (int rb = 0; rb < row_blocks; ++rb) {
+      M2LItem r = o;
+      r.first = o.first | rb << 1;
+      B.items.push_back(r);
+      // plain: nb / 32 tiles per offset; compacted: the item's tiles, shared
+      // over its parts in proportion to their offsets
+      B.weight.push_back(o.compact ? double(P.item_tiles[i]) * o.vo_count /
+                                         std::max(it.vo_count, 1)
+                                   : double(o.vo_count) * cfg.nb / 32);
+    }
   }
 }
 
@@ -143,7 +149,7 @@ void add_generation(LaunchBuilder& B, const Plan& P, int64_t b0, int64_t b1) {
 }
 
 void add_near_field(LaunchBuilder& B, Plan& P, int chunk) {
-  if (P.nT == 0 || P.nS == 0) return;
+  if (P.nT == 0 || P.nS == 0 || P.adaptive()) return;  // adaptive: own launch
   const int32_t d = static_cast<int32_t>(B.p2p.size());
   B.p2p.push_back(p2p_desc(P));
   for (int64_t j = 0; j < P.nT; j += chunk) {
@@ -531,7 +537,9 @@ void build_m2l_work(Plan& P, hipStream_t s) {
     // target boxes grouped by octant, in Morton order
     std::vector<uint32_t> keys = to_host(P.T.key[l].get(), P.T.nb[l], s);
     std::vector<std::vector<int32_t>> by_oct(8);
-    for (size_t b = 0; b < keys.size(); ++b) by_oct[keys[b] & 7].push_back(static_cast<int32_t>(b));
+    for (size_t b = 0; b < keys.size(); ++b)  // (adaptive trees: boxes that exist)
+      if (!P.adaptive() || P.stateT_h[l][b] != 0)
+        by_oct[keys[b] & 7].push_back(static_cast<int32_t>(b));
     // items ordered (octant, direction, block): one group per (octant,
     // direction), blocks in Morton order within a group
     for (int q = 0; q < 8; ++q) {

@@ -140,6 +140,10 @@ P2PDesc p2p_desc(const Plan& P) {
 
 void launch_p2p(Plan& P, hipStream_t s) {
   if (P.nT == 0 || P.nS == 0) return;
+  if (P.adaptive()) {
+    launch_p2p_adaptive(P, s);
+    return;
+  }
   const int p = P.levels;
   const int64_t n_leaf = P.T.nb[p];
   if (n_leaf > 0 && P.nT >= int64_t(kLeafTile / 8) * n_leaf) {  // large leaves

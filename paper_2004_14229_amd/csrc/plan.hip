@@ -54,6 +54,7 @@ void plan_build(Plan& P, const double* pT, const double* pS, hipStream_t s) {
       if (P.kappa * (P.side * std::ldexp(1.0, -l)) >= 3.2) P.l_hf = l;
   }
   P.tab = build_level_tables(P.kappa, P.side, P.levels, P.l_hf, P.eta2);
+  if (P.adaptive()) build_adaptive(P, s);
   P.l_min = P.levels + 1;
   for (int l = 0; l <= P.levels; ++l)
     if (!P.tab[l].adm.empty()) {
@@ -104,7 +105,9 @@ void plan_build(Plan& P, const double* pT, const double* pS, hipStream_t s) {
     build_m2l_work(P, s);
   }
   // near-field statistics (host, from box counts)
-  {
+  if (P.adaptive()) {
+    adaptive_near_stats(P, s);
+  } else {
     const int p = P.levels;
     P.near_pairs = 0;
     P.near_entries = 0;
@@ -133,6 +136,19 @@ void plan_build(Plan& P, const double* pT, const double* pS, hipStream_t s) {
                    std::chrono::steady_clock::now() - t0).count();
 }
 
+// Moments of one level below the last: M2M from the children, then, for an
+// adaptive tree, S2M of the level's leaves (whose children are pruned).
+void plan_m2m_level(Plan& P, int l, hipStream_t s) {
+  launch_m2m(P, l, s);
+  if (P.adaptive()) launch_s2m_boxes(P, l, P.leafS[l].get(), P.n_leafS[l], s);
+}
+
+// The near field runs as its own launch unless its items share the
+// coupling queue (uniform trees only: the queued items read one level).
+bool p2p_queued(const Plan& P, const TuneConfig& t) {
+  return t.p2p_in_queue && p2p_queue_supported(P.prec, P.ip.Kp) && !P.adaptive();
+}
+
 // Forward pass of one plan: user v -> tree order, S2M, M2M.
 void plan_upward(Plan& P, const void* v_user, bool c64, hipStream_t s) {
   if (c64)
@@ -143,7 +159,7 @@ void plan_upward(Plan& P, const void* v_user, bool c64, hipStream_t s) {
                       P.v_tree.get(), s);
   if (P.l_min <= P.levels) {
     launch_s2m(P, s);
-    for (int l = P.levels - 1; l >= P.l_min; --l) launch_m2m(P, l, s);
+    for (int l = P.levels - 1; l >= P.l_min; --l) plan_m2m_level(P, l, s);
   }
 }
 
@@ -195,12 +211,12 @@ void plan_matvec(Plan& P, const void* v_user, void* y_user, bool c64, hipStream_
   if (P.l_min <= p) launch_s2m(P, s);                   // forward transformation
   mark(1);
   if (P.l_min <= p)
-    for (int l = p - 1; l >= P.l_min; --l) launch_m2m(P, l, s);
+    for (int l = p - 1; l >= P.l_min; --l) plan_m2m_level(P, l, s);
   mark(2);
   run_schedule(sched, P.heads.get(), P.prec, P.ip, P.tune, s,   // multiplication phase
                P.timing && P.launch_ev.size() == sched.size() ? P.launch_ev.data() : nullptr);
   mark(3);
-  if (!P.tune.p2p_in_queue || !p2p_queue_supported(P.prec, P.ip.Kp)) launch_p2p(P, s);           // near field (stored)
+  if (!p2p_queued(P, P.tune)) launch_p2p(P, s);         // near field (stored)
   mark(4);
   if (P.l_min <= p)
     for (int l = P.l_min; l < p; ++l) launch_l2l(P, l, s);  // backward transformation
@@ -309,6 +325,7 @@ int fdm_build_tree_opts(const double* points_T, int64_t n_T, const double* point
       fail(FDM_ERR_UNSUPPORTED, "low-rank couplings run in the FP32 precision");
     if (opts->aca_eps > 0 && opts->bank_budget_bytes != 0)
       fail(FDM_ERR_INVALID_ARG, "low-rank couplings keep their bank resident");
+    if (opts->n_max < 0) fail(FDM_ERR_INVALID_ARG, "negative n_max");
     TuneConfig tune;
     if (opts->tune.nb != 0)
       tune = check_tune(opts->tune);
@@ -320,8 +337,8 @@ int fdm_build_tree_opts(const double* points_T, int64_t n_T, const double* point
     if (!(box[3] - box[0] == box[4] - box[1] && box[3] - box[0] == box[5] - box[2]))
       fail(FDM_ERR_UNSUPPORTED, "the root box must be a cube");
     const int K = (m + 1) * (m + 1) * (m + 1);
-    if ((K + 31) / 32 * 32 > kMaxKp)
-      fail(FDM_ERR_UNSUPPORTED, "m > 6 is not supported by the coupling kernels");
+    if (opts->aca_eps > 0 && (K + 31) / 32 * 32 > kMaxKp)
+      fail(FDM_ERR_UNSUPPORTED, "low-rank couplings need m <= 6");
     if (n_T) check_device_ptr(points_T, "points_T");
     if (n_S) check_device_ptr(points_S, "points_S");
     auto* h = new fdm_plan();
@@ -341,6 +358,7 @@ int fdm_build_tree_opts(const double* points_T, int64_t n_T, const double* point
       P.tune = tune;
       P.bank_budget = opts->bank_budget_bytes;
       P.full_bank = opts->full_bank != 0;
+      P.n_max = opts->n_max;
       if (opts->aca_eps > 0) {
         P.aca_eps = opts->aca_eps;
         P.aca_kp = opts->aca_rank ? opts->aca_rank : 64;

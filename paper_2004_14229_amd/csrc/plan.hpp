@@ -40,11 +40,12 @@ int direction_count(int level, int l_hf);
 // ------------------------------------------------------- coupling work --
 // A coupling work item is a block of <= nb target boxes (nb = 32 or 64) of
 // one octant on one level, for one direction, with the list of offsets that
-// hit at least one non-empty source box.  One wave per 32 padded rows:
-// Kp <= 384, i.e. m <= 6, in the coupling kernels.
+// hit at least one non-empty source box.  One wave per 32 padded rows, at
+// most 384 rows (12 waves) per workgroup: a matrix with more rows (m = 7,
+// 8: Kp = 512, 736) runs each item once per row block.
 constexpr int kMaxNB = 64;
 constexpr int kM2LMaxThreads = 768;
-constexpr int kMaxKp = kM2LMaxThreads / 2;
+constexpr int kMaxKp = kM2LMaxThreads / 2;  // rows per workgroup
 
 // Descriptor of one (plan, level) of a coupling launch.
 struct M2LDesc {
@@ -75,6 +76,16 @@ struct P2PDesc {
   double* y;             // complex128 result, tree order (stored)
   double kappa;
   int32_t n_off, level;
+};
+
+// Per level of an adaptive plan, what its near-field kernel reads.
+struct AdaptNear {
+  const int32_t* gridT;   // full target grid: key -> box
+  const uint8_t* stateT;  // box -> 0 pruned, 1 refined, 2 leaf
+  const int32_t* gridS;   // source grid without the pruned boxes
+  const uint8_t* stateS;
+  const int32_t* startS;
+  const int32_t* countS;
 };
 
 // Queue item.  desc >= 0: coupling item of descriptor `desc` -- targets
@@ -205,6 +216,24 @@ struct Plan {
   DevBuf<int32_t> near_off;  // x, y, z triples at the leaf level
   int n_near_off = 0;
 
+  // adaptive trees (Alg. 1's stop rule, n_max > 0).  The device trees stay
+  // refined to the full depth; a box exists in the adaptive tree when every
+  // ancestor holds more than n_max points.  Per level and box: 0 pruned,
+  // 1 refined, 2 leaf.  Work on pruned boxes is either never issued
+  // (couplings, near field, L2T) or computed and never read (moments and
+  // locals of the full-depth pass).
+  int64_t n_max = 0;
+  std::vector<std::vector<uint8_t>> stateT_h, stateS_h;
+  std::vector<DevBuf<uint8_t>> stateT, stateS;
+  std::vector<DevBuf<int32_t>> gridS_alive;  // source grid without pruned boxes
+  std::vector<DevBuf<int32_t>> leafT, leafS;  // per level: leaf boxes
+  std::vector<int64_t> n_leafT, n_leafS;
+  DevBuf<int32_t> adapt_off;     // per level: inadmissible offsets (x, y, z)
+  std::vector<int32_t> adapt_off_begin;  // per level: first triple, and the end
+  DevBuf<int32_t> adapt_off_begin_d;
+  DevBuf<AdaptNear> adapt_near;  // per level: what the near-field kernel reads
+  bool adaptive() const { return n_max > 0; }
+
   // workspaces
   DevBuf<double> v_tree;  // complex128 [nS]
   DevBuf<double> y_tree;  // complex128 [nT]
@@ -232,6 +261,8 @@ void plan_matvec(Plan& P, const void* v_user, void* y_user, bool c64, hipStream_
 void plan_upward(Plan& P, const void* v_user, bool c64, hipStream_t s);
 void plan_downward(Plan& P, void* y_user, bool c64, hipStream_t s);
 void plan_zero_output(Plan& P, void* y_user, bool c64, hipStream_t s);
+void plan_m2m_level(Plan& P, int l, hipStream_t s);
+bool p2p_queued(const Plan& P, const TuneConfig& t);
 
 // ------------------------------------------------------------ kernels --
 void launch_permute_in(const double* v_user, const int32_t* perm, int64_t n,
@@ -243,6 +274,9 @@ void launch_permute_in_c64(const float* v_user, const int32_t* perm, int64_t n,
 void launch_permute_out_c64(const double* y_tree, const int32_t* perm, int64_t n,
                             float* y_user, hipStream_t s);
 void launch_s2m(Plan& P, hipStream_t s);
+// S2M / L2T of the listed boxes of one level (adaptive trees: its leaves)
+void launch_s2m_boxes(Plan& P, int level, const int32_t* boxes, int64_t n, hipStream_t s);
+void launch_l2t_boxes(Plan& P, int level, const int32_t* boxes, int64_t n, hipStream_t s);
 void launch_m2m(Plan& P, int level, hipStream_t s);
 void launch_l2l(Plan& P, int level, hipStream_t s);
 void launch_zero_c128(double* p, int64_t n, hipStream_t s);
@@ -252,6 +286,11 @@ void launch_p2p(Plan& P, hipStream_t s);  // stores the near field into y_tree
 void launch_dense(const double* pT, int64_t nT, const double* pS, int64_t nS,
                   double kappa, const double* v, double* y, hipStream_t s);
 P2PDesc p2p_desc(const Plan& P);
+// adaptive trees (adaptive.hip): box states, leaf lists and pruned grids
+// after the full-depth trees are built; near-field statistics; near field
+void build_adaptive(Plan& P, hipStream_t s);
+void adaptive_near_stats(Plan& P, hipStream_t s);
+void launch_p2p_adaptive(Plan& P, hipStream_t s);
 
 // coupling work and schedules (m2l_work.hip)
 void launch_bank(Plan& P, hipStream_t s);  // resident bank
@@ -294,6 +333,7 @@ void launch_valid_offsets(const M2LItem* items, int64_t n_items, const int32_t* 
                           unsigned long long* blocks_per_off, int32_t* tiles,
                           hipStream_t s);
 int m2l_threads(int Kp);
+int m2l_row_blocks(int Kp);
 // Near-field items can share the coupling launch (FP32 / BF16, Kp <= 256);
 // otherwise the near field runs as its own launch whatever the tune says.
 inline bool p2p_queue_supported(int prec, int Kp) {

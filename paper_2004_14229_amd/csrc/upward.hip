@@ -103,12 +103,14 @@ __global__ void k_permute_out_c64(const double2* __restrict__ y_tree,
     y_user[perm[i]] = make_float2(float(y_tree[i].x), float(y_tree[i].y));
 }
 
-// One wave per (leaf box, direction).
+// One wave per (leaf box, direction); boxes: the listed boxes of the level
+// (adaptive trees), or NULL for boxes 0 .. nb-1.
 __global__ void __launch_bounds__(64) k_s2m(
     const double* __restrict__ x, const double* __restrict__ y,
     const double* __restrict__ z, const double2* __restrict__ v,
     const uint32_t* __restrict__ key, const int32_t* __restrict__ start,
-    const int32_t* __restrict__ count, int64_t nb, int level, double lo0,
+    const int32_t* __restrict__ count, const int32_t* __restrict__ boxes, int64_t nb,
+    int level, double lo0,
     double lo1, double lo2, double h, const double* __restrict__ dirvec, int nd,
     double kappa, Interp ip, double2* __restrict__ mom, float2* __restrict__ mom32,
     uint16_t* __restrict__ mom16) {
@@ -117,7 +119,8 @@ __global__ void __launch_bounds__(64) k_s2m(
   const int c = blockIdx.y;
   const int m1 = ip.m1, K = ip.K, Kp = ip.Kp;
   const double cx = dirvec[3 * c], cy = dirvec[3 * c + 1], cz = dirvec[3 * c + 2];
-  for (int64_t b = blockIdx.x; b < nb; b += gridDim.x) {
+  for (int64_t bi = blockIdx.x; bi < nb; bi += gridDim.x) {
+    const int64_t b = boxes ? boxes[bi] : bi;
     int ix, iy, iz;
     demorton3(key[b], level, ix, iy, iz);
     const double mx = lo0 + (ix + 0.5) * h, my = lo1 + (iy + 0.5) * h,
@@ -246,19 +249,22 @@ void launch_permute_out_c64(const double* y_tree, const int32_t* perm, int64_t n
   FDM_LAUNCH("k_permute_out_c64");
 }
 
-void launch_s2m(Plan& P, hipStream_t s) {
-  const int p = P.levels;
-  LevelData& Lp = P.L[p];
-  const int64_t nb = P.S.nb[p];
+void launch_s2m_boxes(Plan& P, int level, const int32_t* boxes, int64_t nb, hipStream_t s) {
+  LevelData& Lp = P.L[level];
   if (nb == 0) return;
   dim3 grid(static_cast<unsigned>(std::min<int64_t>(nb, 1 << 20)), Lp.nd);
   k_s2m<<<grid, 64, 0, s>>>(P.S.x.get(), P.S.y.get(), P.S.z.get(),
                             reinterpret_cast<const double2*>(P.v_tree.get()),
-                            P.S.key[p].get(), P.S.start[p].get(), P.S.count[p].get(), nb, p,
-                            P.lo[0], P.lo[1], P.lo[2], Lp.h, Lp.dirvec.get(), Lp.nd,
-                            P.kappa, P.ip, reinterpret_cast<double2*>(Lp.mom64.get()),
+                            P.S.key[level].get(), P.S.start[level].get(),
+                            P.S.count[level].get(), boxes, nb, level, P.lo[0], P.lo[1],
+                            P.lo[2], Lp.h, Lp.dirvec.get(), Lp.nd, P.kappa, P.ip,
+                            reinterpret_cast<double2*>(Lp.mom64.get()),
                             reinterpret_cast<float2*>(Lp.mom32.get()), Lp.mom16.get());
   FDM_LAUNCH("k_s2m");
+}
+
+void launch_s2m(Plan& P, hipStream_t s) {
+  launch_s2m_boxes(P, P.levels, nullptr, P.S.nb[P.levels], s);
 }
 
 void launch_m2m(Plan& P, int level, hipStream_t s) {

@@ -56,7 +56,8 @@ class Options(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("l_hf", ctypes.c_int32),
                 ("bank_budget_bytes", ctypes.c_int64), ("tune", Tune),
                 ("full_bank", ctypes.c_int32), ("aca_rank", ctypes.c_int32),
-                ("aca_eps", ctypes.c_double), ("aca_chunk_bytes", ctypes.c_int64)]
+                ("aca_eps", ctypes.c_double), ("aca_chunk_bytes", ctypes.c_int64),
+                ("n_max", ctypes.c_int64)]
 
 
 class Stats(ctypes.Structure):
@@ -205,12 +206,13 @@ class Plan:
     def __init__(self, points_T, points_S, kappa: float, box, levels: int, m: int,
                  precision: str = "fp64", l_hf: int | None = None, stream=None,
                  bank_budget: int = 0, tune: dict | None = None, full_bank: bool = False,
-                 aca_eps: float = 0.0, aca_rank: int = 0, aca_chunk_bytes: int = 0):
+                 aca_eps: float = 0.0, aca_rank: int = 0, aca_chunk_bytes: int = 0,
+                 n_max: int = 0):
         box_arr = (ctypes.c_double * 6)(*[float(b) for b in box])
         opts = Options(PRECISION[precision], -2 if l_hf is None else int(l_hf),
                        int(bank_budget), Tune.from_dict(tune, precision) if tune else Tune(),
                        int(bool(full_bank)), int(aca_rank), float(aca_eps),
-                       int(aca_chunk_bytes))
+                       int(aca_chunk_bytes), int(n_max))
         h = ctypes.c_void_p()
         # the library synchronises the stream before returning
         with _OnStream(stream) as on:

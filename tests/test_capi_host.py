@@ -34,7 +34,7 @@ def _build(**kw):
     (dict(kappa=-1.0), -1), (dict(kappa=float("nan")), -1), (dict(prec=7), -1),
     (dict(n_T=-5), -1), (dict(l_hf=5, levels=3), -1),
     (dict(box=(0, 0, 0, 1, 1, 2)), -3), (dict(box=(0, 0, 0, 0, 1, 1)), -1),
-    (dict(m=7), -3), (dict(prec=4), -1), (dict(prec=-1), -1),
+    (dict(prec=4), -1), (dict(prec=-1), -1),
     (dict(n_T=2 ** 30), -3), (dict(n_S=2 ** 30), -3), (dict(n_S=-1), -1),
 ])
 def test_invalid_arguments_are_rejected(kw, status):
@@ -53,13 +53,13 @@ def test_null_handles():
 
 
 def _build_opts(nb=64, budget=0, prec=0, persistent=1, compact=1, full_bank=0, aca_eps=0.0,
-                aca_rank=0, aca_chunk=0):
+                aca_rank=0, aca_chunk=0, m=4, n_max=0):
     L = F.lib()
     h = ctypes.c_void_p()
     box = (ctypes.c_double * 6)(0, 0, 0, 1, 1, 1)
     opts = F.fdm.Options(prec, -2, budget, F.fdm.Tune(nb, persistent, 1, 0, compact), full_bank,
-                         aca_rank, aca_eps, aca_chunk)
-    st = L.fdm_build_tree_opts(None, 0, None, 0, 1.0, box, 3, 4, ctypes.byref(opts), None,
+                         aca_rank, aca_eps, aca_chunk, n_max)
+    st = L.fdm_build_tree_opts(None, 0, None, 0, 1.0, box, 3, m, ctypes.byref(opts), None,
                                ctypes.byref(h))
     return st, h, L.fdm_last_error().decode()
 
@@ -70,7 +70,7 @@ def _build_opts(nb=64, budget=0, prec=0, persistent=1, compact=1, full_bank=0, a
                                 dict(prec=1, aca_eps=-1.0), dict(prec=1, aca_eps=float("inf")),
                                 dict(prec=1, aca_eps=1e-6, aca_rank=48),
                                 dict(prec=1, aca_eps=1e-6, budget=1 << 30),
-                                dict(prec=1, aca_eps=1e-6, aca_chunk=-1)])
+                                dict(prec=1, aca_eps=1e-6, aca_chunk=-1), dict(n_max=-1)])
 def test_invalid_options_are_rejected(kw):
     st, h, msg = _build_opts(**kw)
     assert st == -1 and h.value is None and msg
@@ -80,6 +80,12 @@ def test_invalid_options_are_rejected(kw):
 def test_low_rank_couplings_need_fp32(prec):
     st, h, msg = _build_opts(prec=prec, aca_eps=1e-6)
     assert st == -3 and h.value is None and "FP32" in msg
+
+
+@pytest.mark.parametrize("m", [7, 8])
+def test_low_rank_couplings_need_m_at_most_6(m):
+    st, h, msg = _build_opts(prec=1, aca_eps=1e-6, m=m)
+    assert st == -3 and h.value is None and "m <= 6" in msg
 
 
 def test_null_handles_are_rejected():
