@@ -20,11 +20,18 @@ Readings taken here:
   This makes ``dir(-v) = -dir(v)``.
 * Membership of ``psi_Q(v) = v / max|v_j|`` in a closed face is decided in
   exact integer arithmetic: the argument is an integer offset between box
-  centres (cubic boxes), or a face midpoint, which is dyadic.
+  centres (cubic boxes), or a face midpoint, which is dyadic.  For a
+  non-cubic root box the centre offset is ``o * h`` with the box sides
+  ``h``: floating-point sides are dyadic rationals, so ``o * h`` times a
+  common power of two is an integer vector, and the same exact test
+  applies (Python integers).
+* ``l_hf`` for a non-cubic root box uses the longest side.
 """
 from __future__ import annotations
 
+import math
 from dataclasses import dataclass
+from fractions import Fraction
 
 import numpy as np
 
@@ -129,7 +136,9 @@ class DirectionSets:
         Returns 0 on low-frequency levels (the single direction ``0``) and -1
         for ``v = 0`` on high-frequency levels.
         """
-        v = np.asarray(v, dtype=np.int64)
+        v = np.asarray(v)
+        if v.dtype != object:
+            v = v.astype(np.int64)
         shape = v.shape[:-1]
         v = v.reshape(-1, 3)
         if level > self.l_hf:
@@ -153,7 +162,24 @@ class DirectionSets:
         return self.dir_index(level + 1, mids)
 
 
-def active_directions(TT, TS, BT, dirs: DirectionSets, side: float):
+def exact_offsets(o: np.ndarray, side) -> np.ndarray:
+    """Box-centre offsets ``o * h`` (``o`` integer, ``h`` the side lengths at
+    any level) as exact integer vectors up to one positive factor; ``o``
+    itself for equal sides."""
+    side = np.asarray(side, dtype=np.float64).reshape(3)
+    if side[0] == side[1] == side[2]:
+        return o
+    fr = [Fraction(float(x)) for x in side]
+    den = math.lcm(*[f.denominator for f in fr])
+    S = [int(f * den) for f in fr]
+    o = np.asarray(o, dtype=np.int64).reshape(-1, 3)
+    out = np.empty(o.shape, dtype=object)
+    for d in range(3):
+        out[:, d] = [int(a) * S[d] for a in o[:, d]]
+    return out
+
+
+def active_directions(TT, TS, BT, dirs: DirectionSets, side):
     """Def. of active and inherited directions for both trees.
 
     Returns ``(DT, DhT, DS, DhS)``, each a list over levels of boolean arrays
@@ -168,7 +194,7 @@ def active_directions(TT, TS, BT, dirs: DirectionSets, side: float):
         ds = np.zeros((TS.keys[level].shape[0], nd), dtype=bool)
         t, s = BT.adm_t[level], BT.adm_s[level]
         o = TT.coords[level][t] - TS.coords[level][s]  # (m_t - m_s) / h
-        c = dirs.dir_index(level, o)
+        c = dirs.dir_index(level, exact_offsets(o, TT.root_hi - TT.root_lo))
         dt[t, c] = True
         ds[s, c] = True
         DT.append(dt)

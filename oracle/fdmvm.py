@@ -77,15 +77,13 @@ def _validate(box, kappa, levels, m):
             np.all(hi > lo)):
         raise ValueError("invalid root box")
     side = hi - lo
-    if not (side[0] == side[1] == side[2]):
-        raise ValueError("root box must be a cube")
     if not (np.isfinite(kappa) and kappa >= 0):
         raise ValueError("kappa must be finite and >= 0")
     if not (0 <= levels <= 10):
         raise ValueError("levels must be in [0, 10]")
     if not (1 <= m <= 8):
         raise ValueError("m must be in [1, 8]")
-    return float(side[0])
+    return side
 
 
 def build(points_T, points_S, kappa, box, levels, m, l_hf=None,
@@ -99,8 +97,8 @@ def build(points_T, points_S, kappa, box, levels, m, l_hf=None,
         raise ValueError("n_max must be a non-negative integer")
     TT = build_box_tree(points_T, box, levels, n_max)
     TS = build_box_tree(points_S, box, levels, n_max)
-    if l_hf is None:
-        l_hf = high_frequency_level(kappa, side, levels)
+    if l_hf is None:  # (the longest side for a non-cubic box)
+        l_hf = high_frequency_level(kappa, float(np.max(side)), levels)
     dirs = DirectionSets(l_hf, levels)
     filt = None
     if rows is not None:
