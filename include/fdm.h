@@ -70,9 +70,14 @@ typedef enum {
  *            during the call.  May equal points_T.
  *  kappa     wave number, finite, >= 0 (0 gives the Laplace kernel).
  *  box       host, 6 doubles {lo_x, lo_y, lo_z, hi_x, hi_y, hi_z}: the root
- *            box (lo, hi] shared by both trees.  Must be a cube (else
- *            FDM_ERR_UNSUPPORTED).  Every point must satisfy lo < x <= hi
- *            per axis (else FDM_ERR_POINT_OUTSIDE_BOX).
+ *            box (lo, hi] shared by both trees, any axis-parallel box
+ *            (Sect. 2.1): the boxes of a level are its translates scaled by
+ *            2^-level per axis, and the direction of a box pair is that of
+ *            its centre offset, evaluated exactly (FDM_ERR_UNSUPPORTED only
+ *            for sides whose binary mantissas and exponents do not fit one
+ *            63-bit integer scale); the high-frequency rule uses the longest
+ *            side.  Every point must satisfy lo < x <= hi per axis (else
+ *            FDM_ERR_POINT_OUTSIDE_BOX).
  *  levels    tree depth below the root, 0..9 (the per-level key -> box
  *            grids hold 8^levels entries); every non-empty box above this
  *            level is split (leaves all sit on this level).  levels outside

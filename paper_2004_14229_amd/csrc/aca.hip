@@ -35,8 +35,8 @@ __device__ __forceinline__ double2 coupling_entry(int row, int col, const BankLe
   const int b[3] = {col / (m1 * m1), (col / m1) % m1, col % m1};
   double d[3], rel[3];
   for (int q = 0; q < 3; ++q) {
-    rel[q] = 0.5 * L.h * (ip.node[a[q]] - ip.node[b[q]]);
-    d[q] = L.h * o[q] + rel[q];
+    rel[q] = 0.5 * L.h[q] * (ip.node[a[q]] - ip.node[b[q]]);
+    d[q] = L.h[q] * o[q] + rel[q];
   }
   const double rr = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
   const double arg = L.kappa * rr - L.kappa * (rel[0] * c[0] + rel[1] * c[1] + rel[2] * c[2]);

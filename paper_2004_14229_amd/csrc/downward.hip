@@ -30,7 +30,7 @@ __device__ __forceinline__ double2 load_c<float2>(const float2* p, int64_t i) {
 template <class GT>
 __global__ void __launch_bounds__(kXT) k_l2l(
     const double2* __restrict__ ploc, int nd, const int32_t* __restrict__ pgrid,
-    const uint32_t* __restrict__ key1, int64_t nb1, int level, double h1,
+    const uint32_t* __restrict__ key1, int64_t nb1, int level, double3 h1,
     const double* __restrict__ dirvec, const double* __restrict__ dirvec1, int nd1,
     int l_hf, double kappa, Interp ip, const GT* g_m2l,
     double2* loc1) {  // g_m2l may alias loc1 (read before write, same thread)
@@ -61,8 +61,9 @@ __global__ void __launch_bounds__(kXT) k_l2l(
       __syncthreads();
       if (lane < 3 * m1) {
         const int d = lane / m1, nu = lane % m1;
-        const double r = 0.5 * h1 * ip.node[nu];  // xi - m_{t'}
-        const double off = (bq[d] - 0.5) * h1;    // m_{t'} - m_t
+        const double hd = d == 0 ? h1.x : d == 1 ? h1.y : h1.z;
+        const double r = 0.5 * hd * ip.node[nu];  // xi - m_{t'}
+        const double off = (bq[d] - 0.5) * hd;    // m_{t'} - m_t
         double sn, cs;
         phase_sincos(kappa * ((r + off) * cv[d] - r * cv1[d]), sn, cs);
         ph[d][nu] = make_double2(cs, sn);
@@ -98,7 +99,7 @@ __global__ void __launch_bounds__(64) k_l2t(
     const double* __restrict__ z, const uint32_t* __restrict__ key,
     const int32_t* __restrict__ start, const int32_t* __restrict__ count,
     const int32_t* __restrict__ boxes, int64_t nb,
-    int level, double lo0, double lo1, double lo2, double h,
+    int level, double lo0, double lo1, double lo2, double3 h,
     const double* __restrict__ dirvec, int nd, double kappa, Interp ip,
     const double2* __restrict__ loc, double2* __restrict__ y_tree) {
   __shared__ double lag[3][kMaxM1];
@@ -108,9 +109,9 @@ __global__ void __launch_bounds__(64) k_l2t(
     const int64_t b = boxes ? boxes[bi] : bi;
     int ix, iy, iz;
     demorton3(key[b], level, ix, iy, iz);
-    const double mx = lo0 + (ix + 0.5) * h, my = lo1 + (iy + 0.5) * h,
-                 mz = lo2 + (iz + 0.5) * h;
-    const double inv_half = 2.0 / h;
+    const double mx = lo0 + (ix + 0.5) * h.x, my = lo1 + (iy + 0.5) * h.y,
+                 mz = lo2 + (iz + 0.5) * h.z;
+    const double inv_half[3] = {2.0 / h.x, 2.0 / h.y, 2.0 / h.z};
     const int p0 = start[b], pn = count[b];
     for (int pi = 0; pi < pn; ++pi) {
       const int64_t j = p0 + pi;
@@ -118,7 +119,7 @@ __global__ void __launch_bounds__(64) k_l2t(
       __syncthreads();
       if (lane < 3 * m1) {
         const int d = lane / m1, nu = lane % m1;
-        const double u = (d == 0 ? dx : d == 1 ? dy : dz) * inv_half;
+        const double u = (d == 0 ? dx : d == 1 ? dy : dz) * inv_half[d];
         lag[d][nu] = lagrange1d(ip, nu, u);
       }
       __syncthreads();
@@ -177,7 +178,7 @@ void launch_l2l(Plan& P, int level, hipStream_t s) {
   dim3 grid(static_cast<unsigned>(std::min<int64_t>(nb1, 1 << 20)), L1.nd);
   k_l2l<double2><<<grid, kXT, 0, s>>>(
       reinterpret_cast<const double2*>(Lc.loc64.get()), Lc.nd, P.T.grid[level].get(),
-      P.T.key[level + 1].get(), nb1, level, L1.h, Lc.dirvec.get(), L1.dirvec.get(),
+      P.T.key[level + 1].get(), nb1, level, L1.hv(), Lc.dirvec.get(), L1.dirvec.get(),
       L1.nd, P.l_hf, P.kappa, P.ip, reinterpret_cast<const double2*>(L1.loc64.get()),
       reinterpret_cast<double2*>(L1.loc64.get()));
   FDM_LAUNCH("k_l2l");
@@ -189,7 +190,7 @@ void launch_l2t_boxes(Plan& P, int level, const int32_t* boxes, int64_t nb, hipS
   LevelData& Lp = P.L[level];
   k_l2t<<<static_cast<unsigned>(std::min<int64_t>(nb, 1 << 20)), 64, 0, s>>>(
       P.T.x.get(), P.T.y.get(), P.T.z.get(), P.T.key[level].get(), P.T.start[level].get(),
-      P.T.count[level].get(), boxes, nb, level, P.lo[0], P.lo[1], P.lo[2], Lp.h,
+      P.T.count[level].get(), boxes, nb, level, P.lo[0], P.lo[1], P.lo[2], Lp.hv(),
       Lp.dirvec.get(), Lp.nd, P.kappa, P.ip, reinterpret_cast<const double2*>(Lp.loc64.get()),
       reinterpret_cast<double2*>(P.y_tree.get()));
   FDM_LAUNCH("k_l2t");

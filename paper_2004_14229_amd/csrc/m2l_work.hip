@@ -20,7 +20,8 @@ int64_t bank_matrix_bytes(int prec, const Interp& ip) {
 namespace {
 
 BankLevel bank_level(const Plan& P, int l) {
-  return BankLevel{P.L[l].dirvec.get(), P.L[l].h, P.kappa, l, P.L[l].nd};
+  const LevelData& Ld = P.L[l];
+  return BankLevel{Ld.dirvec.get(), {Ld.h[0], Ld.h[1], Ld.h[2]}, P.kappa, l, Ld.nd};
 }
 
 // Whether base item i runs with compacted columns under `cfg`: mode 1 when

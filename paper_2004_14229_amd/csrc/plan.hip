@@ -45,7 +45,8 @@ Interp make_interp(int m) {
 void plan_build(Plan& P, const double* pT, const double* pS, hipStream_t s) {
   auto t0 = std::chrono::steady_clock::now();
   P.ip = make_interp(P.m);
-  P.side = P.hi[0] - P.lo[0];
+  const double sidev[3] = {P.hi[0] - P.lo[0], P.hi[1] - P.lo[1], P.hi[2] - P.lo[2]};
+  P.side = std::max(sidev[0], std::max(sidev[1], sidev[2]));  // the longest side
   build_tree(pT, P.nT, P.lo, P.hi, P.levels, s, &P.tally, P.T);
   build_tree(pS, P.nS, P.lo, P.hi, P.levels, s, &P.tally, P.S);
   if (P.l_hf == -2) {
@@ -53,7 +54,7 @@ void plan_build(Plan& P, const double* pT, const double* pS, hipStream_t s) {
     for (int l = 0; l <= P.levels; ++l)
       if (P.kappa * (P.side * std::ldexp(1.0, -l)) >= 3.2) P.l_hf = l;
   }
-  P.tab = build_level_tables(P.kappa, P.side, P.levels, P.l_hf, P.eta2);
+  P.tab = build_level_tables(P.kappa, sidev, P.levels, P.l_hf, P.eta2);
   if (P.adaptive()) build_adaptive(P, s);
   P.l_min = P.levels + 1;
   for (int l = 0; l <= P.levels; ++l)
@@ -71,7 +72,7 @@ void plan_build(Plan& P, const double* pT, const double* pS, hipStream_t s) {
     LevelData& Ld = P.L[l];
     Ld.level = l;
     Ld.nd = direction_count(l, P.l_hf);
-    Ld.h = P.side * std::ldexp(1.0, -l);
+    for (int d = 0; d < 3; ++d) Ld.h[d] = sidev[d] * std::ldexp(1.0, -l);
     to_device(Ld.dirvec, direction_vectors(l, P.l_hf), s, &P.tally);
     Ld.bank_base = P.n_bank;
     if (l >= P.l_min) {
@@ -334,8 +335,6 @@ int fdm_build_tree_opts(const double* points_T, int64_t n_T, const double* point
     for (int d = 0; d < 3; ++d)
       if (!std::isfinite(box[d]) || !std::isfinite(box[d + 3]) || !(box[d + 3] > box[d]))
         fail(FDM_ERR_INVALID_ARG, "invalid box");
-    if (!(box[3] - box[0] == box[4] - box[1] && box[3] - box[0] == box[5] - box[2]))
-      fail(FDM_ERR_UNSUPPORTED, "the root box must be a cube");
     const int K = (m + 1) * (m + 1) * (m + 1);
     if (opts->aca_eps > 0 && (K + 31) / 32 * 32 > kMaxKp)
       fail(FDM_ERR_UNSUPPORTED, "low-rank couplings need m <= 6");

@@ -31,9 +31,17 @@ struct LevelTable {
   std::vector<Off> inadm;
 };
 
-std::vector<LevelTable> build_level_tables(double kappa, double side, int levels,
+// side: the root box's three side lengths.
+std::vector<LevelTable> build_level_tables(double kappa, const double side[3], int levels,
                                            int l_hf, double eta2);
-int direction_index(int level, int l_hf, const Off& o);
+// dir_(level) of the centre offset o * h of two boxes of one level; scale:
+// the box sides as integers up to one common factor ({1, 1, 1} for cubes).
+int direction_index(int level, int l_hf, const Off& o, const int64_t scale[3]);
+int direction_index(int level, int l_hf, const Off& o);  // cubic boxes
+// The root box's sides as integers up to one common positive factor (exact:
+// the doubles' odd mantissas shifted to a common exponent); throws
+// FDM_ERR_UNSUPPORTED when that does not fit 63 bits.
+void side_scale(const double side[3], int64_t scale[3]);
 std::vector<double> direction_vectors(int level, int l_hf);  // nd * 3
 int direction_count(int level, int l_hf);
 
@@ -103,7 +111,8 @@ struct M2LItem {
 // offset and direction.
 struct BankLevel {
   const double* dirvec;
-  double h, kappa;
+  double h[3];  // box sides of the level
+  double kappa;
   int32_t level, nd;
 };
 
@@ -135,7 +144,8 @@ struct M2LLaunch {
 struct LevelData {
   int level = 0;
   int nd = 1;          // #D^(l) (1 on low-frequency levels)
-  double h = 0;        // box side
+  double h[3] = {0, 0, 0};  // box sides
+  double3 hv() const { return make_double3(h[0], h[1], h[2]); }
   int64_t bank_base = 0;  // bank id of adm[0]
   DevBuf<double> dirvec;  // nd * 3
   DevBuf<int32_t> offs;   // adm offsets: x, y, z, bank id

@@ -28,12 +28,12 @@ namespace fdm {
 
 #pragma clang fp contract(off)
 
-static bool admissible(double kappa, double h, const Off& o, double eta2) {
+static bool admissible(double kappa, const double h[3], const Off& o, double eta2) {
   double g0 = std::max(std::abs(o.x) - 1, 0);
   double g1 = std::max(std::abs(o.y) - 1, 0);
   double g2 = std::max(std::abs(o.z) - 1, 0);
-  double d2 = h * h + h * h + h * h;
-  double s2 = (g0 * h) * (g0 * h) + (g1 * h) * (g1 * h) + (g2 * h) * (g2 * h);
+  double d2 = h[0] * h[0] + h[1] * h[1] + h[2] * h[2];
+  double s2 = (g0 * h[0]) * (g0 * h[0]) + (g1 * h[1]) * (g1 * h[1]) + (g2 * h[2]) * (g2 * h[2]);
   double e2 = eta2 * eta2;
   bool a1 = d2 <= e2 * s2;
   bool a3 = (kappa * kappa) * (d2 * d2) <= e2 * s2;
@@ -42,12 +42,15 @@ static bool admissible(double kappa, double h, const Off& o, double eta2) {
 
 static int ceil_half(int v) { return (v + 1) >> 1; }  // ceil(v / 2), arithmetic shift
 
-std::vector<LevelTable> build_level_tables(double kappa, double side, int levels,
+std::vector<LevelTable> build_level_tables(double kappa, const double side[3], int levels,
                                            int l_hf, double eta2) {
   std::vector<LevelTable> tab(levels + 1);
   tab[0].inadm.push_back({0, 0, 0});  // the root pair: offset 0, never admissible
+  int64_t scale[3];
+  side_scale(side, scale);
   for (int l = 1; l <= levels; ++l) {
-    const double h = side * std::ldexp(1.0, -l);
+    const double h[3] = {side[0] * std::ldexp(1.0, -l), side[1] * std::ldexp(1.0, -l),
+                         side[2] * std::ldexp(1.0, -l)};
     const int lim = (1 << l) - 1;
     std::set<Off> parents(tab[l - 1].inadm.begin(), tab[l - 1].inadm.end());
     std::set<Off> cand;
@@ -70,7 +73,7 @@ std::vector<LevelTable> build_level_tables(double kappa, double side, int levels
         }
         T.adm.push_back(o);
         T.mask.push_back(mask);
-        T.dir.push_back(direction_index(l, l_hf, o));
+        T.dir.push_back(direction_index(l, l_hf, o, scale));
       } else {
         T.inadm.push_back(o);
       }
@@ -84,23 +87,62 @@ int direction_count(int level, int l_hf) {
   return 6 * (1 << (2 * (l_hf - level)));
 }
 
+void side_scale(const double side[3], int64_t scale[3]) {
+  if (side[0] == side[1] && side[1] == side[2]) {
+    scale[0] = scale[1] = scale[2] = 1;
+    return;
+  }
+  // side_d = mant_d 2^exp_d with odd integer mantissas; then shift to the
+  // smallest exponent
+  int64_t mant[3];
+  int ex[3];
+  for (int d = 0; d < 3; ++d) {
+    int e = 0;
+    const double f = std::frexp(side[d], &e);
+    int64_t m = static_cast<int64_t>(std::ldexp(f, 53));
+    e -= 53;
+    while (m % 2 == 0) {
+      m /= 2;
+      ++e;
+    }
+    mant[d] = m;
+    ex[d] = e;
+  }
+  const int emin = std::min(ex[0], std::min(ex[1], ex[2]));
+  for (int d = 0; d < 3; ++d) {
+    const int sh = ex[d] - emin;
+    if (sh > 62 || (sh > 0 && mant[d] > (INT64_MAX >> sh)))
+      fail(FDM_ERR_UNSUPPORTED, "root box sides too unequal for the exact direction map");
+    scale[d] = mant[d] << sh;
+  }
+}
+
 int direction_index(int level, int l_hf, const Off& o) {
+  const int64_t one[3] = {1, 1, 1};
+  return direction_index(level, l_hf, o, one);
+}
+
+int direction_index(int level, int l_hf, const Off& o, const int64_t scale[3]) {
   if (level > l_hf) return 0;
-  const int v[3] = {o.x, o.y, o.z};
-  const int M = std::max(std::abs(v[0]), std::max(std::abs(v[1]), std::abs(v[2])));
+  // the centre offset o * h up to a positive factor, exactly (|o| < 2^10,
+  // scale < 2^63: products < 2^73, later terms < 2^83)
+  const __int128 v[3] = {__int128(o.x) * scale[0], __int128(o.y) * scale[1],
+                         __int128(o.z) * scale[2]};
+  auto mag = [](__int128 x) { return x < 0 ? -x : x; };
+  const __int128 M = std::max(mag(v[0]), std::max(mag(v[1]), mag(v[2])));
   if (M == 0) return -1;
   int a = 0;
-  while (std::abs(v[a]) != M) ++a;  // lowest axis attaining the maximum
+  while (mag(v[a]) != M) ++a;  // lowest axis attaining the maximum
   const int sgn = v[a] > 0 ? 1 : -1;
   const int64_t n = int64_t(1) << (l_hf - level);
   int64_t idx[2];
   int j = 0;
   for (int b = 0; b < 3; ++b) {
     if (b == a) continue;
-    int64_t num = (int64_t(sgn) * v[b] + M) * n;  // >= 0
-    int64_t den = 2 * int64_t(M);
-    int64_t i = (num + den - 1) / den - 1;        // closed cells, lowest index
-    idx[j++] = std::max<int64_t>(i, 0);
+    const __int128 num = (sgn * v[b] + M) * n;  // >= 0
+    const __int128 den = 2 * M;
+    const __int128 i = (num + den - 1) / den - 1;  // closed cells, lowest index
+    idx[j++] = i < 0 ? 0 : static_cast<int64_t>(i);
   }
   int64_t q = 0;
   for (int bit = l_hf - level - 1; bit >= 0; --bit)

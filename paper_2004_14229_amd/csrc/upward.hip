@@ -111,7 +111,7 @@ __global__ void __launch_bounds__(64) k_s2m(
     const uint32_t* __restrict__ key, const int32_t* __restrict__ start,
     const int32_t* __restrict__ count, const int32_t* __restrict__ boxes, int64_t nb,
     int level, double lo0,
-    double lo1, double lo2, double h, const double* __restrict__ dirvec, int nd,
+    double lo1, double lo2, double3 h, const double* __restrict__ dirvec, int nd,
     double kappa, Interp ip, double2* __restrict__ mom, float2* __restrict__ mom32,
     uint16_t* __restrict__ mom16) {
   __shared__ double lag[3][kMaxM1];
@@ -123,9 +123,9 @@ __global__ void __launch_bounds__(64) k_s2m(
     const int64_t b = boxes ? boxes[bi] : bi;
     int ix, iy, iz;
     demorton3(key[b], level, ix, iy, iz);
-    const double mx = lo0 + (ix + 0.5) * h, my = lo1 + (iy + 0.5) * h,
-                 mz = lo2 + (iz + 0.5) * h;
-    const double inv_half = 2.0 / h;
+    const double mx = lo0 + (ix + 0.5) * h.x, my = lo1 + (iy + 0.5) * h.y,
+                 mz = lo2 + (iz + 0.5) * h.z;
+    const double inv_half[3] = {2.0 / h.x, 2.0 / h.y, 2.0 / h.z};
     double2 acc[kPerLane];
     for (int i = 0; i < kPerLane; ++i) acc[i] = make_double2(0.0, 0.0);
     const int p0 = start[b], pn = count[b];
@@ -135,7 +135,7 @@ __global__ void __launch_bounds__(64) k_s2m(
       __syncthreads();
       if (lane < 3 * m1) {
         const int d = lane / m1, nu = lane % m1;
-        const double u = (d == 0 ? dx : d == 1 ? dy : dz) * inv_half;
+        const double u = (d == 0 ? dx : d == 1 ? dy : dz) * inv_half[d];
         lag[d][nu] = lagrange1d(ip, nu, u);
       }
       __syncthreads();
@@ -162,7 +162,7 @@ __global__ void __launch_bounds__(64) k_s2m(
 // turn, each transformed by the whole workgroup.
 __global__ void __launch_bounds__(kXT) k_m2m(
     const double2* __restrict__ child_mom, int nd1, const int32_t* __restrict__ grid1,
-    const uint32_t* __restrict__ key, int64_t nb, int level, double h1,
+    const uint32_t* __restrict__ key, int64_t nb, int level, double3 h1,
     const double* __restrict__ dirvec, const double* __restrict__ dirvec1, int nd,
     int l_hf, double kappa, Interp ip, double2* __restrict__ mom,
     float2* __restrict__ mom32, uint16_t* __restrict__ mom16) {
@@ -186,8 +186,9 @@ __global__ void __launch_bounds__(kXT) k_m2m(
       // per-axis factors of conj(E~d): exp(-i kappa ((xi-m_s) c - (xi-m_s') c'))
       if (lane < 3 * m1) {
         const int d = lane / m1, nu = lane % m1;
-        const double r = 0.5 * h1 * ip.node[nu];          // xi - m_{s'}
-        const double off = (bq[d] - 0.5) * h1;            // m_{s'} - m_s
+        const double hd = d == 0 ? h1.x : d == 1 ? h1.y : h1.z;
+        const double r = 0.5 * hd * ip.node[nu];          // xi - m_{s'}
+        const double off = (bq[d] - 0.5) * hd;            // m_{s'} - m_s
         double sn, cs;
         phase_sincos(-kappa * ((r + off) * cv[d] - r * cv1[d]), sn, cs);
         ph[d][nu] = make_double2(cs, sn);
@@ -257,7 +258,7 @@ void launch_s2m_boxes(Plan& P, int level, const int32_t* boxes, int64_t nb, hipS
                             reinterpret_cast<const double2*>(P.v_tree.get()),
                             P.S.key[level].get(), P.S.start[level].get(),
                             P.S.count[level].get(), boxes, nb, level, P.lo[0], P.lo[1],
-                            P.lo[2], Lp.h, Lp.dirvec.get(), Lp.nd, P.kappa, P.ip,
+                            P.lo[2], Lp.hv(), Lp.dirvec.get(), Lp.nd, P.kappa, P.ip,
                             reinterpret_cast<double2*>(Lp.mom64.get()),
                             reinterpret_cast<float2*>(Lp.mom32.get()), Lp.mom16.get());
   FDM_LAUNCH("k_s2m");
@@ -275,7 +276,7 @@ void launch_m2m(Plan& P, int level, hipStream_t s) {
   dim3 grid(static_cast<unsigned>(std::min<int64_t>(nb, 1 << 20)), Lc.nd);
   k_m2m<<<grid, kXT, 0, s>>>(reinterpret_cast<const double2*>(L1.mom64.get()), L1.nd,
                             P.S.grid[level + 1].get(), P.S.key[level].get(), nb, level,
-                            L1.h, Lc.dirvec.get(), L1.dirvec.get(), Lc.nd, P.l_hf,
+                            L1.hv(), Lc.dirvec.get(), L1.dirvec.get(), Lc.nd, P.l_hf,
                             P.kappa, P.ip, reinterpret_cast<double2*>(Lc.mom64.get()),
                             reinterpret_cast<float2*>(Lc.mom32.get()), Lc.mom16.get());
   FDM_LAUNCH("k_m2m");

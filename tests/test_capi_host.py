@@ -33,7 +33,7 @@ def _build(**kw):
     (dict(levels=-1), -1), (dict(levels=10), -1), (dict(m=0), -1), (dict(m=9), -1),
     (dict(kappa=-1.0), -1), (dict(kappa=float("nan")), -1), (dict(prec=7), -1),
     (dict(n_T=-5), -1), (dict(l_hf=5, levels=3), -1),
-    (dict(box=(0, 0, 0, 1, 1, 2)), -3), (dict(box=(0, 0, 0, 0, 1, 1)), -1),
+    (dict(box=(0, 0, 0, 0, 1, 1)), -1), (dict(box=(0, 0, 0, 1, float("inf"), 1)), -1),
     (dict(prec=4), -1), (dict(prec=-1), -1),
     (dict(n_T=2 ** 30), -3), (dict(n_S=2 ** 30), -3), (dict(n_S=-1), -1),
 ])
