@@ -240,14 +240,15 @@ def cpu_baseline(P, stats, shape, sub_div: int = 4):
             "measured_s": tm["total"], "extrapolated_s_per_matvec": total, "phases": phases}
 
 
-def batched(steps: int, compact: int = 1) -> dict:
+def batched(steps: int, compact: int = 1, aca_eps: float = 0.0) -> dict:
     """The batched workload: 64 independent problems (N log-uniform in
     [1e4, 2e5], kappa uniform in [10, 80], half uniform, half clustered, m=5,
     complex64 v) in one batch: mixed FP32 coupling, every problem's bank
     resident (one matrix per offset pair), coupling and near-field work of
     all problems from one device queue in one persistent launch, the whole
     batched matvec replayed as a HIP graph, launch shape picked by the
-    autotuner."""
+    autotuner.  aca_eps > 0: every coupling matrix compressed by ACA (low-rank
+    launch pairs over all problems' offset groups, near field apart)."""
     import torch
     import paper_2004_14229_amd as F
     import workloads as W
@@ -258,7 +259,8 @@ def batched(steps: int, compact: int = 1) -> dict:
         qt = torch.from_numpy(Q.points_T).cuda()
         qs = torch.from_numpy(Q.points_S).cuda()
         plans.append(F.Plan(qt, qs, Q.kappa, Q.box, Q.levels, Q.m, precision="fp32",
-                            tune={"compact": compact}))
+                            **({"aca_eps": aca_eps} if aca_eps > 0 else
+                               {"tune": {"compact": compact}})))
         del qt, qs
     b = F.Batch(plans)
     torch.cuda.synchronize()
@@ -279,12 +281,16 @@ def batched(steps: int, compact: int = 1) -> dict:
     K = (probs[0].m + 1) ** 3
     stats = [p.stats() for p in plans]
     flops = sum(8.0 * K * K * st["n_couplings"] for st in stats)
+    if aca_eps > 0:  # the low-rank products' own flops
+        flops = sum(st["aca_flops"] for st in stats)
     res = {"workload": ("64 problems, N log-uniform in [1e4, 2e5] (sum %d), kappa U[10,80], "
                         "32 uniform + 32 clustered (8 blobs, sigma 0.05), 4-5 levels, m=5, "
                         "complex64 v and y" % sum(Q.points_T.shape[0] for Q in probs)),
            "value": 1.0 / wall, "unit": "batches/s", "problem_matvecs_per_s": 64.0 / wall,
            "ms_per_batch": 1000.0 * wall, "steps": steps, "setup_s": setup_s,
-           "precision": "FP32 coupling, resident banks (one matrix per offset pair)",
+           "precision": ("FP32 coupling, resident banks (one matrix per offset pair)"
+                         if aca_eps <= 0 else
+                         f"FP32 low-rank coupling (ACA to {aca_eps:g}), resident low-rank banks"),
            "bank_matrices": sum(st["n_bank_matrices"] for st in stats),
            "device_bytes": sum(st["device_bytes"] for st in stats),
            "tune": best, "autotune_m2l_ms": tune_ms,
@@ -307,7 +313,8 @@ def batched(steps: int, compact: int = 1) -> dict:
     b.close()
     for p in plans:
         p.close()
-    print(f"[bench] batched: {1000.0 * wall:.1f} ms per batch of 64", file=sys.stderr, flush=True)
+    print(f"[bench] batched{' aca' if aca_eps > 0 else ''}: {1000.0 * wall:.1f} ms per batch "
+          "of 64", file=sys.stderr, flush=True)
     return res
 
 
@@ -449,7 +456,8 @@ def main():
         print(f"[bench] {split}: {bms:.1f} ms/matvec, M2L {bm2l:.1f} ms", file=sys.stderr,
               flush=True)
 
-    if args.aca_eps > 0 and args.aca_steps > 0 and budget == 0:
+    if args.aca_eps > 0 and args.aca_steps > 0 and P.m <= 6:
+        # (its low-rank bank is resident whatever the dense plans' budget)
         t0 = time.perf_counter()
         ap_ = F.Plan(pt, ps, P.kappa, P.box, P.levels, P.m, precision="fp32",
                      aca_eps=args.aca_eps)
@@ -486,6 +494,11 @@ def main():
         del pt, ps, v, y
         torch.cuda.empty_cache()
         out["batched"] = batched(args.batch_steps, args.compact)
+        if args.aca_eps > 0 and args.aca_steps > 0:
+            torch.cuda.empty_cache()
+            out["batched_aca"] = batched(args.batch_steps, args.compact, args.aca_eps)
+            out["batched_aca"]["speedup_vs_dense_batch"] = (
+                out["batched"]["ms_per_batch"] / out["batched_aca"]["ms_per_batch"])
 
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(P, stats, shape, args.cpu_sub)

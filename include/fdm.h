@@ -387,8 +387,9 @@ int fdm_dense_matvec(const double* points_T, int64_t n_T,
  * and wave numbers, one launch sequence).
  *
  * fdm_batch_create -- group n plans (same m and precision, each in at most
- * one batch, none with low-rank couplings: FDM_ERR_UNSUPPORTED) into a
- * batch.  The plans stay owned by the caller and must
+ * one batch; with low-rank couplings either all, with one rank cap, or none,
+ * else FDM_ERR_UNSUPPORTED) into a batch.  The plans stay owned by the
+ * caller and must
  * outlive the batch; while they belong to it they cannot be re-tuned or
  * destroyed (FDM_ERR_STATE).  Plans built with bank_budget_bytes > 0 have
  * their coupling banks generated during each batched matvec into one
@@ -403,7 +404,8 @@ int fdm_dense_matvec(const double* points_T, int64_t n_T,
  * persistent launches pulling from one device queue over (plan, level,
  * direction, target block) items, with every plan's near field queued
  * behind them (one launch when all banks are resident or fit the
- * workspace); then for every plan L2L, L2T and the permutation back.
+ * workspace; low-rank plans: launch pairs over every plan's offset groups,
+ * near field apart); then for every plan L2L, L2T and the permutation back.
  */
 typedef struct fdm_batch fdm_batch;
 

@@ -21,6 +21,11 @@ void invalidate_graph(fdm_batch& b) {
 
 void batch_schedule(fdm_batch& b, hipStream_t s) {
   invalidate_graph(b);
+  if (b.aca_kp) {  // low-rank couplings: launch pairs over every plan's groups
+    b.sched = build_aca_schedule(b.plans, b.tune, b.aca_T, int64_t(8) << 30, &b.tally, s);
+    b.heads.alloc(std::max<size_t>(b.sched.size(), 1), &b.tally);
+    return;
+  }
   const int64_t mb = bank_matrix_bytes(b.prec, b.ip);
   const int64_t ws_mats = b.ws.size() / mb;
   b.sched = build_schedule(b.plans, b.tune, b.ws.get(), ws_mats, s);
@@ -197,8 +202,9 @@ int fdm_batch_create(fdm_plan* const* plans, int n, int64_t workspace_bytes, voi
       if (plans[i]->p.batch_owner) fail(FDM_ERR_STATE, "a plan already belongs to a batch");
       if (plans[i]->p.m != plans[0]->p.m || plans[i]->p.prec != plans[0]->p.prec)
         fail(FDM_ERR_UNSUPPORTED, "plans of a batch must share m and precision");
-      if (plans[i]->p.aca_kp)
-        fail(FDM_ERR_UNSUPPORTED, "plans with low-rank couplings cannot join a batch");
+      if (plans[i]->p.aca_kp != plans[0]->p.aca_kp)
+        fail(FDM_ERR_UNSUPPORTED,
+             "plans of a batch must all have low-rank couplings with one rank cap, or none");
     }
     hipStream_t s = static_cast<hipStream_t>(stream);
     auto* b = new fdm_batch();
@@ -210,6 +216,11 @@ int fdm_batch_create(fdm_plan* const* plans, int n, int64_t workspace_bytes, voi
       b->tune.lpt = 1;
       b->tune.p2p_in_queue = 1;
       b->tune.compact = plans[0]->p.tune.compact;
+      b->aca_kp = plans[0]->p.aca_kp;
+      if (b->aca_kp) {  // low-rank items: 64 targets, no compaction, near field apart
+        b->tune.p2p_in_queue = 0;
+        b->tune.compact = 0;
+      }
       const int64_t mb = bank_matrix_bytes(b->prec, b->ip);
       int64_t need = 0;
       for (int i = 0; i < n; ++i) {
@@ -290,7 +301,7 @@ int fdm_batch_autotune(fdm_batch* batch, const void* const* v, void* const* y, i
   return guarded([&] {
     if (!batch) fail(FDM_ERR_INVALID_ARG, "batch is NULL");
     fdm_batch& b = *batch;
-    const auto cand = candidates(true, 1, b.tune.compact);
+    const auto cand = candidates(true, b.aca_kp ? 0 : 1, b.tune.compact);
     if (max_candidates < 1 || max_candidates > static_cast<int>(cand.size()))
       fail(FDM_ERR_INVALID_ARG, "max_candidates out of range");
     check_vectors(b, v, y, c64);
@@ -310,6 +321,10 @@ int fdm_batch_autotune(fdm_batch* batch, const void* const* v, void* const* y, i
       batch_schedule(b, s);
     };
     for (int i = 0; i < max_candidates; ++i) {
+      if (b.aca_kp && (cand[i].nb != 64 || cand[i].p2p_in_queue || cand[i].compact)) {
+        if (ms) ms[i] = -1.0;  // low-rank items: 64 targets, no compaction, near field apart
+        continue;
+      }
       apply(cand[i]);
       const double t = time_on_stream(s, [&] {
         run_schedule(b.sched, b.heads.get(), b.prec, b.ip, b.tune, s);

@@ -284,88 +284,103 @@ int64_t plan_workspace_bytes(const Plan& P) {
   return std::max<int64_t>(1, std::min(P.n_bank, P.bank_budget / mb)) * mb;
 }
 
-// Low-rank couplings: the plan's items in chunks of consecutive items whose
-// stage-1 output T (kp x 64 complex FP32 per item offset) fits the budget;
-// per chunk a stage-1 and a stage-2 launch over the same items, T indexed
-// by the items' offset entries relative to the chunk's first.
-std::vector<M2LLaunch> build_aca_schedule(Plan& P, hipStream_t s) {
-  constexpr int G = 16;  // offsets per group: the FP32 totals' flush interval
-  const auto& items = P.base_items;
-  // each item's offsets by rank, highest first (stable): a group's padded
-  // rank is that of its first offset.  The plan's low-rank bank stores
-  // every matrix at its bank id.
-  std::vector<int32_t> vo = P.valid_off_h;
-  for (const M2LItem& it : items)
-    std::stable_sort(vo.begin() + it.vo_begin, vo.begin() + it.vo_begin + it.vo_count,
-                     [&](int32_t a, int32_t b) { return P.aca_rank[a] > P.aca_rank[b]; });
-  to_device(P.aca_vo, vo, s, &P.tally);
-  auto padded = [&](int32_t b) {
-    const int r = (P.aca_rank[b] + 15) / 16 * 16;
-    return std::min(std::max(r, 32), P.aca_kp);
-  };
-  // launch pairs: group g of items, consecutive items while their T fits
-  const int64_t cap = std::max<int64_t>(int64_t(G) * 64 * P.aca_kp * 8, P.aca_T_budget);
+// Low-rank couplings of one or more plans (one batch): every item's offsets
+// ordered by rank (highest first, stable) and cut into groups of 16 (the
+// FP32 totals' flush interval); a group runs at the padded rank of its
+// first offset.  One launch pair (stage 1, stage 2) covers group g of
+// consecutive items, over all plans, while their stage-1 output fits the T
+// buffer; T of an item group sits at `compact` units of 64 x 16 complex
+// values.  An item with no offset is stored (as zero) by group 0.
+std::vector<M2LLaunch> build_aca_schedule(const std::vector<Plan*>& plans,
+                                          const TuneConfig& cfg, DevBuf<float>& T,
+                                          int64_t T_budget, int64_t* tally, hipStream_t s) {
+  constexpr int G = 16;
+  if (plans.empty()) return {};
+  const int kp = plans[0]->aca_kp, Kp = plans[0]->ip.Kp, prec = plans[0]->prec;
+  std::vector<std::vector<int32_t>> vos(plans.size());
   int max_groups = 1;
-  for (const M2LItem& it : items) max_groups = std::max(max_groups, (it.vo_count + G - 1) / G);
+  for (size_t q = 0; q < plans.size(); ++q) {
+    Plan& P = *plans[q];
+    std::vector<int32_t>& vo = vos[q];
+    vo = P.valid_off_h;  // the low-rank bank stores every matrix at its bank id
+    for (const M2LItem& it : P.base_items) {
+      std::stable_sort(vo.begin() + it.vo_begin, vo.begin() + it.vo_begin + it.vo_count,
+                       [&](int32_t a, int32_t b) { return P.aca_rank[a] > P.aca_rank[b]; });
+      max_groups = std::max(max_groups, (it.vo_count + G - 1) / G);
+    }
+    to_device(P.aca_vo, vo, s, &P.tally);
+    P.aca_issued_cols = 0;
+  }
+  const int64_t cap_units = std::max<int64_t>(G * (kp / 16), T_budget / 8192);
   struct Part {
+    int plan;
     M2LItem it;
-    int64_t units;  // T of the group in units of 64 x 16 complex values
+    int64_t units;
   };
   std::vector<std::vector<Part>> launches;
   int64_t need = 0;
-  P.aca_issued_cols = 0;
   for (int g = 0; g < max_groups; ++g) {
     std::vector<Part> cur;
     int64_t used = 0;
-    for (const M2LItem& base : items) {
-      const int n = std::max(0, std::min(G, base.vo_count - g * G));
-      if (n == 0 && g > 0) continue;  // empty items are stored (as zero) by group 0
-      M2LItem it = base;
-      it.vo_begin = base.vo_begin + g * G;
-      it.vo_count = n;
-      const int rp = n ? padded(vo[it.vo_begin]) : 32;
-      it.first = (g == 0 ? 1 : 0) | (rp / 16) << 1;
-      const int64_t units = int64_t(n) * (rp / 16);
-      P.aca_issued_cols += 64.0 * n * rp;
-      if (used + units > cap / 8192 && !cur.empty()) {
-        launches.push_back(std::move(cur));
-        cur.clear();
-        used = 0;
+    for (size_t q = 0; q < plans.size(); ++q) {
+      Plan& P = *plans[q];
+      for (const M2LItem& base : P.base_items) {
+        const int n = std::max(0, std::min(G, base.vo_count - g * G));
+        if (n == 0 && g > 0) continue;
+        M2LItem it = base;
+        it.vo_begin = base.vo_begin + g * G;
+        it.vo_count = n;
+        int rp = 32;
+        if (n) {
+          rp = (P.aca_rank[vos[q][it.vo_begin]] + 15) / 16 * 16;
+          rp = std::min(std::max(rp, 32), kp);
+        }
+        it.first = (g == 0 ? 1 : 0) | (rp / 16) << 1;
+        const int64_t units = int64_t(n) * (rp / 16);
+        P.aca_issued_cols += 64.0 * n * rp;
+        if (used + units > cap_units && !cur.empty()) {
+          launches.push_back(std::move(cur));
+          cur.clear();
+          used = 0;
+        }
+        it.compact = static_cast<int32_t>(used);
+        used += units;
+        need = std::max(need, used);
+        cur.push_back({static_cast<int>(q), it, units});
       }
-      it.compact = static_cast<int32_t>(used);
-      used += units;
-      need = std::max(need, used);
-      cur.push_back({it, units});
     }
     if (!cur.empty()) launches.push_back(std::move(cur));
   }
-  if (P.aca_T.size() < static_cast<size_t>(need * 2048))
-    P.aca_T.alloc(std::max<int64_t>(need, 1) * 2048, &P.tally);
+  if (T.size() < static_cast<size_t>(need * 2048)) T.alloc(std::max<int64_t>(need, 1) * 2048, tally);
   std::vector<M2LLaunch> out;
   for (const auto& parts : launches) {
     for (int stage = 1; stage <= 2; ++stage) {
       LaunchBuilder B;
-      std::vector<int32_t> desc_of(P.levels + 1, -1);
-      for (int l = std::max(P.l_min, 0); l <= P.levels; ++l) {
-        desc_of[l] = static_cast<int32_t>(B.descs.size());
-        M2LDesc d = level_desc(P, l, resident_bank(P), 0);
-        d.valid_off = P.aca_vo.get();
-        if (stage == 1)
-          d.out = P.aca_T.get();  // stage 1 writes T
-        else
-          d.mom = P.aca_T.get();  // stage 2 reads it
-        B.descs.push_back(d);
+      std::vector<std::vector<int32_t>> desc_of(plans.size());
+      for (size_t q = 0; q < plans.size(); ++q) {
+        Plan& P = *plans[q];
+        desc_of[q].assign(P.levels + 1, -1);
+        for (int l = std::max(P.l_min, 0); l <= P.levels; ++l) {
+          desc_of[q][l] = static_cast<int32_t>(B.descs.size());
+          M2LDesc d = level_desc(P, l, resident_bank(P), 0);
+          d.valid_off = P.aca_vo.get();
+          if (stage == 1)
+            d.out = T.get();  // stage 1 writes T
+          else
+            d.mom = T.get();  // stage 2 reads it
+          B.descs.push_back(d);
+        }
       }
       for (const Part& pt : parts) {
         if (stage == 1 && pt.it.vo_count == 0) continue;
         M2LItem it = pt.it;
-        it.desc = desc_of[it.desc];
+        it.desc = desc_of[pt.plan][it.desc];
         B.items.push_back(it);
         B.weight.push_back(static_cast<double>(pt.units));
       }
-      M2LLaunch L = upload(B, P.tune, P.prec, P.ip.Kp, nullptr, s);
+      M2LLaunch L = upload(B, cfg, prec, Kp, nullptr, s);
       L.stage = stage;
-      L.resident_wgs = resident_aca(stage, P.ip.Kp);
+      L.resident_wgs = resident_aca(stage, Kp);
       out.push_back(std::move(L));
     }
   }
@@ -374,7 +389,7 @@ std::vector<M2LLaunch> build_aca_schedule(Plan& P, hipStream_t s) {
 
 void build_plan_schedule(Plan& P, hipStream_t s) {
   if (P.aca_kp) {
-    P.sched = build_aca_schedule(P, s);
+    P.sched = build_aca_schedule({&P}, P.tune, P.aca_T, P.aca_T_budget, &P.tally, s);
     P.sched_static.clear();
     P.static_ready = false;
     P.heads.alloc(std::max<size_t>(P.sched.size(), 1), &P.tally);

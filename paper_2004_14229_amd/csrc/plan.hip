@@ -147,7 +147,7 @@ void plan_m2m_level(Plan& P, int l, hipStream_t s) {
 // The near field runs as its own launch unless its items share the
 // coupling queue (uniform trees only: the queued items read one level).
 bool p2p_queued(const Plan& P, const TuneConfig& t) {
-  return t.p2p_in_queue && p2p_queue_supported(P.prec, P.ip.Kp) && !P.adaptive();
+  return t.p2p_in_queue && p2p_queue_supported(P.prec, P.ip.Kp) && !P.adaptive() && !P.aca_kp;
 }
 
 // Forward pass of one plan: user v -> tree order, S2M, M2M.

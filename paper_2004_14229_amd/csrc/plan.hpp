@@ -308,6 +308,11 @@ void build_m2l_work(Plan& P, hipStream_t s);  // base items for P.tune.nb
 int64_t bank_matrix_bytes(int prec, const Interp& ip);
 // Rebuild the plan's own launches (after a change of its tune config).
 void build_plan_schedule(Plan& P, hipStream_t s);
+// Launch pairs of the low-rank coupling step of plans with low-rank
+// couplings (one plan, or a batch), stage-1 output in T (grown to fit).
+std::vector<M2LLaunch> build_aca_schedule(const std::vector<Plan*>& plans,
+                                          const TuneConfig& cfg, DevBuf<float>& T,
+                                          int64_t T_budget, int64_t* tally, hipStream_t s);
 // The library's static workspace (noalloc.hip): its size, and its address
 // on the current device (looked up once per device).
 int64_t static_workspace_bytes();
@@ -407,5 +412,7 @@ struct fdm_batch {
   hipStream_t graph_stream = nullptr;
   int graph_c64 = -1;
   bool use_graph = true;
+  int aca_kp = 0;                // low-rank couplings (all plans), else 0
+  fdm::DevBuf<float> aca_T;      // their stage-1 output
   int64_t tally = 0;
 };

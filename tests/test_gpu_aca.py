@@ -95,3 +95,38 @@ def test_aca_launch_shapes_and_chunks():
     yo = oracle.matvec(oracle.build(P.points_T, P.points_S, P.kappa, P.box, P.levels, P.m),
                        P.v, m2l=f"aca:{EPS}")
     assert_close(y0, yo, 1e-6)
+
+
+def test_batch_of_low_rank_plans():
+    """A batch of low-rank plans runs their groups in shared launch pairs
+    (one T buffer), graph-replayed; each result as the plan's own within
+    rounding of the FP32 sums, and within 1e-6 of the oracle's ACA matvec.
+    Mixing low-rank and dense plans is refused."""
+    import torch
+    import paper_2004_14229_amd as F
+    Ps = [W.random_problem(407, 900, 850, 30.0, 4, 3),
+          W.clustered_problem(408, 1200, 1100, 20.0, 5, 3),
+          W.random_problem(409, 600, 650, 12.0, 3, 3)]
+    plans = [aca_plan(P) for P in Ps]
+    try:
+        solo = [p.matvec(to_dev(P.v)).cpu().numpy() for p, P in zip(plans, Ps)]
+        with F.Batch(plans) as b:
+            vs = [to_dev(P.v) for P in Ps]
+            ys = b.matvec(vs)
+            ys2 = b.matvec(vs, [torch.empty_like(y) for y in ys])
+            torch.cuda.synchronize()
+            for k, P in enumerate(Ps):
+                y, y2 = ys[k].cpu().numpy(), ys2[k].cpu().numpy()
+                assert np.array_equal(y, y2)
+                assert np.array_equal(y, solo[k])  # same groups, sums and flushes
+                yo = oracle.matvec(oracle.build(P.points_T, P.points_S, P.kappa, P.box,
+                                                P.levels, P.m), P.v, m2l=f"aca:{EPS}")
+                assert_close(y, yo, 1e-6, k)
+        dense = F.Plan(to_dev(Ps[0].points_T), to_dev(Ps[0].points_S), Ps[0].kappa,
+                       Ps[0].box, Ps[0].levels, Ps[0].m, precision="fp32")
+        with pytest.raises(Exception, match="low-rank"):
+            F.Batch([plans[0], dense])
+        dense.close()
+    finally:
+        for p in plans:
+            p.close()
