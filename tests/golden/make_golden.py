@@ -12,7 +12,10 @@ domain boundary, where blocks have the fewest partners, and in the middle,
 where they have the most).  Run from the repository root:
 
     python tests/golden/make_golden.py uniform100k uniform1m paper_k6 uniform4m
+    python tests/golden/make_golden.py degree7 degree8
     python tests/golden/make_golden.py batch
+
+``degree7`` / ``degree8``: small problems at m = 7 and 8, every row.
 
 ``batch``: the batched workload (64 problems of ``workloads.batch_problems``),
 oracle rows of four of its problems (two uniform, two clustered), saved as
@@ -31,6 +34,8 @@ import oracle  # noqa: E402
 import workloads as W  # noqa: E402
 
 SAMPLES = {"uniform100k": 64, "uniform1m": 256, "uniform4m": 32, "paper_k6": 256}
+# small workloads stored whole (every target row)
+WHOLE = ("degree7", "degree8")
 MODES = ("fp64", "bf16x3", "bf16x6")
 BATCH_GOLDEN = (2, 4, 35, 46)  # problem indices in workloads.batch_problems()
 BATCH_ROWS = 16
@@ -49,6 +54,8 @@ def landmark_rows(P) -> np.ndarray:
 
 def sample(name: str, R: int) -> np.ndarray:
     P = W.config(name)
+    if name in WHOLE:
+        return np.arange(P.points_T.shape[0])
     rows = np.random.default_rng(12345).choice(P.points_T.shape[0], R, replace=False)
     if name != "uniform100k":  # (its stored sample predates the landmarks)
         rows = np.concatenate([rows, landmark_rows(P)])
@@ -79,7 +86,7 @@ def main(names):
         names = [n for n in names if n != "batch"]
     for name in names:
         P = W.config(name)
-        rows = sample(name, SAMPLES[name])
+        rows = sample(name, SAMPLES.get(name, 0))
         t = time.time()
         plan = oracle.build(P.points_T, P.points_S, P.kappa, P.box, P.levels, P.m,
                             rows=rows)

@@ -104,12 +104,24 @@ UNIFORM = {
 }
 
 
+# Small problems at the highest interpolation degrees (m = 7, 8: K = 512,
+# 729), separate random target and source sets in the unit cube:
+# name -> (seed, n_T, n_S, kappa, levels, m).
+HIGH_DEGREE = {
+    "degree7": (701, 600, 560, 20.0, 3, 7),
+    "degree8": (702, 500, 480, 12.0, 3, 8),
+}
+
+
 def config(name: str) -> Problem:
     if name in UNIFORM:
         seed, n, kappa, levels, m = UNIFORM[name]
         return uniform_problem(name, seed, n, kappa, levels, m)
     if name.startswith("paper_k"):
         return paper_grid_problem(int(name[len("paper_k"):]))
+    if name in HIGH_DEGREE:
+        seed, nT, nS, kappa, levels, m = HIGH_DEGREE[name]
+        return random_problem(seed, nT, nS, kappa, levels, m)
     raise KeyError(name)
 
 
