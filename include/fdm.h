@@ -256,6 +256,25 @@ int fdm_plan_matvec(fdm_plan* plan, const void* v, void* y, void* stream);
 int fdm_plan_matvec_c64(fdm_plan* plan, const void* v, void* y, void* stream);
 
 /*
+ * fdm_plan_matvec_multi -- Y = A~ V for nrhs right-hand sides (repeated
+ * application of one operator, Sect. 4): the plan's trees, work lists and
+ * coupling bank serve every vector, and the near field evaluates each kernel
+ * value once for up to four vectors.  Each result equals fdm_plan_matvec's
+ * on the same vector bit for bit.  Asynchronous on `stream`.
+ *
+ *  V     device, nrhs vectors of n_S complex values one after the other
+ *        (complex64 when c64 = 1, else complex128); not modified.
+ *  Y     device, nrhs vectors of n_T complex values, same type; overwritten.
+ *        V and Y must not overlap.
+ *  nrhs  >= 1.  The plan holds two tree-order copies of nrhs vectors
+ *        (allocated on the first call with that many, kept for later calls).
+ * FDM_ERR_INVALID_ARG for NULL or host pointers, nrhs < 1, c64 not 0/1, or
+ * overlapping V and Y; FDM_ERR_STATE while the plan belongs to a batch.
+ */
+int fdm_plan_matvec_multi(fdm_plan* plan, const void* V, void* Y, int nrhs, int c64,
+                          void* stream);
+
+/*
  * Per-phase timing of later matvecs with HIP events recorded on the matvec's
  * stream (enable != 0 turns it on).  fdm_plan_phase_ms waits for the last
  * matvec's events and writes 7 values in milliseconds: S2M, M2M, M2L, L2L,

@@ -192,8 +192,8 @@ void launch_p2p_adaptive(Plan& P, hipStream_t s) {
   k_p2p_adaptive<<<static_cast<unsigned>((P.nT + B - 1) / B), B, 0, s>>>(
       P.adapt_near.get(), P.levels, P.T.key[P.levels].get(), P.T.leaf_of.get(), P.T.x.get(),
       P.T.y.get(), P.T.z.get(), P.S.x.get(), P.S.y.get(), P.S.z.get(),
-      reinterpret_cast<const double2*>(P.v_tree.get()), P.adapt_off.get(),
-      P.adapt_off_begin_d.get(), P.kappa, reinterpret_cast<double2*>(P.y_tree.get()), P.nT);
+      reinterpret_cast<const double2*>(P.vtree()), P.adapt_off.get(),
+      P.adapt_off_begin_d.get(), P.kappa, reinterpret_cast<double2*>(P.ytree()), P.nT);
   FDM_LAUNCH("k_p2p_adaptive");
 }
 

@@ -192,7 +192,7 @@ void launch_l2t_boxes(Plan& P, int level, const int32_t* boxes, int64_t nb, hipS
       P.T.x.get(), P.T.y.get(), P.T.z.get(), P.T.key[level].get(), P.T.start[level].get(),
       P.T.count[level].get(), boxes, nb, level, P.lo[0], P.lo[1], P.lo[2], Lp.hv(),
       Lp.dirvec.get(), Lp.nd, P.kappa, P.ip, reinterpret_cast<const double2*>(Lp.loc64.get()),
-      reinterpret_cast<double2*>(P.y_tree.get()));
+      reinterpret_cast<double2*>(P.ytree()));
   FDM_LAUNCH("k_l2t");
 }
 

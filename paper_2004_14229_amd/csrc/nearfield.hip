@@ -126,12 +126,12 @@ P2PDesc p2p_desc(const Plan& P) {
   d.xs = P.S.x.get();
   d.ys = P.S.y.get();
   d.zs = P.S.z.get();
-  d.v = P.v_tree.get();
+  d.v = P.vtree();
   d.startS = P.S.start[p].get();
   d.countS = P.S.count[p].get();
   d.gridS = P.S.grid[p].get();
   d.near_off = P.near_off.get();
-  d.y = P.y_tree.get();
+  d.y = P.ytree();
   d.kappa = P.kappa;
   d.n_off = P.n_near_off;
   d.level = p;

@@ -9,18 +9,37 @@
 
 namespace fdm {
 
-__device__ __forceinline__ void kernel_add(double xt, double yt, double zt, double xs,
-                                           double ys, double zs, double2 v, double kappa,
-                                           double& ar, double& ai) {
+// f(x, y) as (fr, fi); false (and f = 0) for bitwise-equal points.
+__device__ __forceinline__ bool kernel_value(double xt, double yt, double zt, double xs,
+                                             double ys, double zs, double kappa, double& fr,
+                                             double& fi) {
   const double dx = xt - xs, dy = yt - ys, dz = zt - zs;
-  if (xt == xs && yt == ys && zt == zs) return;  // f(x, x) = 0
+  if (xt == xs && yt == ys && zt == zs) return false;  // f(x, x) = 0
   const double r = sqrt(dx * dx + dy * dy + dz * dz);
   double sn, cs;
   phase_sincos(kappa * r, sn, cs);
   const double w = 1.0 / (4.0 * M_PI * r);
-  const double fr = cs * w, fi = sn * w;
-  ar += fr * v.x - fi * v.y;
-  ai += fr * v.y + fi * v.x;
+  fr = cs * w;
+  fi = sn * w;
+  return true;
+}
+
+// (ar, ai) += f v as four fused multiply-adds in a fixed order, so that every
+// kernel that sums near-field terms rounds them the same way.
+__device__ __forceinline__ void kernel_accumulate(double fr, double fi, double2 v, double& ar,
+                                                  double& ai) {
+  ar = fma(fr, v.x, ar);
+  ar = fma(-fi, v.y, ar);
+  ai = fma(fr, v.y, ai);
+  ai = fma(fi, v.x, ai);
+}
+
+__device__ __forceinline__ void kernel_add(double xt, double yt, double zt, double xs,
+                                           double ys, double zs, double2 v, double kappa,
+                                           double& ar, double& ai) {
+  double fr, fi;
+  if (!kernel_value(xt, yt, zt, xs, ys, zs, kappa, fr, fi)) return;
+  kernel_accumulate(fr, fi, v, ar, ai);
 }
 
 // Near-field value of target point j (tree order); the near-field blocks of

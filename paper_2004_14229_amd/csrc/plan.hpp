@@ -247,6 +247,13 @@ struct Plan {
   // workspaces
   DevBuf<double> v_tree;  // complex128 [nS]
   DevBuf<double> y_tree;  // complex128 [nT]
+  // several right-hand sides (fdm_plan_matvec_multi): all of them in tree
+  // order, and the vector the phases of one pass read and write
+  DevBuf<double> vm_tree, ym_tree;  // complex128 [nrhs][nS], [nrhs][nT]
+  double* v_view = nullptr;
+  double* y_view = nullptr;
+  double* vtree() const { return v_view ? v_view : v_tree.get(); }
+  double* ytree() const { return y_view ? y_view : y_tree.get(); }
 
   // statistics
   int64_t n_couplings = 0, n_stored = 0, near_pairs = 0, near_entries = 0;

@@ -255,7 +255,7 @@ void launch_s2m_boxes(Plan& P, int level, const int32_t* boxes, int64_t nb, hipS
   if (nb == 0) return;
   dim3 grid(static_cast<unsigned>(std::min<int64_t>(nb, 1 << 20)), Lp.nd);
   k_s2m<<<grid, 64, 0, s>>>(P.S.x.get(), P.S.y.get(), P.S.z.get(),
-                            reinterpret_cast<const double2*>(P.v_tree.get()),
+                            reinterpret_cast<const double2*>(P.vtree()),
                             P.S.key[level].get(), P.S.start[level].get(),
                             P.S.count[level].get(), boxes, nb, level, P.lo[0], P.lo[1],
                             P.lo[2], Lp.hv(), Lp.dirvec.get(), Lp.nd, P.kappa, P.ip,

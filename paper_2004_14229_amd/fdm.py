@@ -97,6 +97,7 @@ def lib() -> ctypes.CDLL:
     L.fdm_plan_matvec.argtypes = [vp, vp, vp, vp]
     L.fdm_plan_matvec_c64.argtypes = [vp, vp, vp, vp]
     L.fdm_plan_matvec_noalloc.argtypes = [vp, vp, vp, ci, vp]
+    L.fdm_plan_matvec_multi.argtypes = [vp, vp, vp, ci, ci, vp]
     L.fdm_plan_destroy.argtypes = [vp]
     L.fdm_plan_stats.argtypes = [vp, ctypes.POINTER(Stats)]
     L.fdm_plan_export.argtypes = [vp, ctypes.c_char_p, vp, i64, ctypes.POINTER(i64)]
@@ -124,7 +125,8 @@ def lib() -> ctypes.CDLL:
     L.fdm_last_error.restype = ctypes.c_char_p
     L.fdm_version.restype = ctypes.c_char_p
     for f in ("fdm_build_tree", "fdm_build_tree_ex", "fdm_build_tree_opts", "fdm_plan_matvec",
-              "fdm_plan_matvec_c64", "fdm_plan_matvec_noalloc", "fdm_plan_destroy",
+              "fdm_plan_matvec_c64", "fdm_plan_matvec_noalloc", "fdm_plan_matvec_multi",
+              "fdm_plan_destroy",
               "fdm_plan_stats",
               "fdm_plan_export", "fdm_dense_matvec", "fdm_plan_set_timing",
               "fdm_plan_phase_ms", "fdm_plan_get_tune", "fdm_plan_set_tune",
@@ -249,6 +251,27 @@ class Plan:
             fn = lib().fdm_plan_matvec if v.dtype == torch.complex128 else lib().fdm_plan_matvec_c64
             _check(fn(self._h, _ptr(v), _ptr(out), on.handle()))
             on.keep(v, out)
+        return out
+
+    def matvec_multi(self, V, out=None, stream=None):
+        """``Y = A~ V`` for the rows of V (nrhs x n_S, complex128 or complex64,
+        one right-hand side per row); returns Y (nrhs x n_T)."""
+        import torch
+        if not isinstance(V, torch.Tensor) or not V.is_cuda or V.dim() != 2:
+            raise TypeError("V must be a 2-D CUDA tensor (nrhs x n_S)")
+        if V.dtype not in (torch.complex128, torch.complex64) or V.shape[1] != self.n_S:
+            raise TypeError("V must be complex128/complex64 with n_S columns")
+        V = V.contiguous()
+        nrhs = V.shape[0]
+        if out is None:
+            out = torch.empty(nrhs, self.n_T, dtype=V.dtype, device=V.device)
+        elif (not isinstance(out, torch.Tensor) or not out.is_cuda or out.dtype != V.dtype
+              or out.shape != (nrhs, self.n_T) or not out.is_contiguous()):
+            raise TypeError("out must be a contiguous CUDA tensor nrhs x n_T, same dtype as V")
+        with _OnStream(stream) as on:
+            _check(lib().fdm_plan_matvec_multi(self._h, _ptr(V), _ptr(out), int(nrhs),
+                                               int(V.dtype == torch.complex64), on.handle()))
+            on.keep(V, out)
         return out
 
     def matvec_noalloc(self, v, out, stream=None):
