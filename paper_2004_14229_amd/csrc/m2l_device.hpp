@@ -181,13 +181,6 @@ __device__ __forceinline__ const __attribute__((address_space(4))) T* cmem(const
   return (const __attribute__((address_space(4))) T*)p;
 }
 
-// Row tile (of 32 coupling-matrix rows) owned by this wave.  A matrix with
-// more rows than one workgroup's waves cover runs each item once per row
-// block: `first` >> 1 is the block, bit 0 the first-part flag.
-__device__ __forceinline__ int row_wave(const M2LItem& it) {
-  return threadIdx.x / 64 + (it.first >> 1) * (blockDim.x / 64);
-}
-
 __device__ __forceinline__ int4 offset_of(const M2LDesc& D, int32_t vo) {
   const int32_t b = *cmem(D.valid_off + vo);
   const int32_t* o = reinterpret_cast<const int32_t*>(D.offtab) + 4 * int64_t(b);
@@ -379,8 +372,8 @@ template <int NB, bool ADD>
 __device__ __forceinline__ void item_f64(F64Shared<NB>& sh, const M2LItem& it,
                                          const M2LDesc& D, int Kp) {
   using Tr = F64Traits;
-  const int wave = row_wave(it), lane = threadIdx.x % 64;
-  const bool rows_here = 32 * wave < Kp;  // waves past Kp only help with loads
+  const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+  const bool rows_here = 32 * wave < D.rows;  // waves past the rows only help with loads
   load_targets(sh.S, it, D);
   __syncthreads();
   double2* out = static_cast<double2*>(D.out);
@@ -549,8 +542,8 @@ __device__ __forceinline__ void item_f32(F32Shared<NB>& sh, const M2LItem& it,
                                          const M2LDesc& D, int Kp) {
   using Tr = F32Traits;
   constexpr int NT = NB / 32;
-  const int wave = ACA ? threadIdx.x / 64 : row_wave(it), lane = threadIdx.x % 64;
-  const bool rows_here = 32 * wave < Kp;
+  const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+  const bool rows_here = 32 * wave < D.rows;
   load_targets(sh.S, it, D);
   __syncthreads();
   double2* out = static_cast<double2*>(D.out);
@@ -949,8 +942,8 @@ template <int NB, bool ADD, int SPLIT>
 __device__ __forceinline__ void item_bf16(BF16SharedS<NB, SPLIT>& sh, const M2LItem& it,
                                           const M2LDesc& D, int Kp) {
   constexpr int NT = NB / 32;
-  const int wave = row_wave(it), lane = threadIdx.x % 64;
-  const bool rows_here = 32 * wave < Kp;
+  const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+  const bool rows_here = 32 * wave < D.rows;
   load_targets(sh.S, it, D);
   __syncthreads();
   double2* out = static_cast<double2*>(D.out);
@@ -1055,8 +1048,8 @@ __device__ __forceinline__ void item_compact(SH& sh, const M2LItem& it, const M2
   constexpr bool BF16 = MODE != 0;
   constexpr int KS = 16;  // k per slab in both precisions
   static_assert(F32Traits::KS == KS && kBKS == KS, "one slab size");
-  const int wave = row_wave(it), lane = threadIdx.x % 64;
-  const bool rows_here = 32 * wave < Kp;
+  const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+  const bool rows_here = 32 * wave < D.rows;
   load_targets(sh.S, it, D);
   __syncthreads();
   double2* out = static_cast<double2*>(D.out);

@@ -66,6 +66,23 @@ M2LDesc level_desc(const Plan& P, int l, const void* bank, int64_t bank_id0) {
   d.level = l;
   d.K = P.ip.K;
   d.kp = P.aca_kp;
+  d.rows = P.ip.Kp;
+  return d;
+}
+
+// Descriptor of row block rb of a level whose matrices are split into row
+// blocks of `block` rows: bank and out point at the block's first row (row
+// r of a matrix sits at offset r in every layout: k-major planes, and the
+// BF16 fragments, 512 values per 32 rows of a slab; the FP64 result has
+// stride Kp per (target, direction)).
+M2LDesc row_block_desc(const Plan& P, M2LDesc d, int rb, int block) {
+  const int64_t r0 = int64_t(rb) * block;
+  const int64_t elem = P.prec == FDM_PREC_FP64 ? 8 : P.prec == FDM_PREC_FP32 ? 4 : 2;
+  const int64_t shift = (P.prec == FDM_PREC_BF16X3 || P.prec == FDM_PREC_BF16X6) ? r0 * 16 : r0;
+  d.bank = reinterpret_cast<const void*>(reinterpret_cast<uintptr_t>(d.bank) +
+                                         static_cast<uintptr_t>(shift * elem));
+  d.out = static_cast<double2*>(d.out) + r0;
+  d.rows = static_cast<int32_t>(std::min<int64_t>(block, P.ip.Kp - r0));
   return d;
 }
 
@@ -92,13 +109,20 @@ struct LaunchBuilder {
 // at `bank` with bank id b0 at position slot0.
 void add_source(LaunchBuilder& B, const Plan& P, int64_t b0, int64_t b1, const void* bank,
                 int64_t slot0, const TuneConfig& cfg, std::vector<uint8_t>& emitted) {
+  // one descriptor per level, or per (level, row block) for matrices with
+  // more rows than a workgroup covers
+  const int row_blocks = m2l_row_blocks(P.ip.Kp);
+  const int block = m2l_threads(P.ip.Kp) / 2;  // rows per block (one wave per 32)
   std::vector<int32_t> desc_of(P.levels + 1, -1);
   for (int l = std::max(P.l_min, 0); l <= P.levels; ++l) {
     desc_of[l] = static_cast<int32_t>(B.descs.size());
-    B.descs.push_back(level_desc(P, l, bank, b0 - slot0));
+    const M2LDesc d = level_desc(P, l, bank, b0 - slot0);
+    if (row_blocks == 1)
+      B.descs.push_back(d);
+    else
+      for (int rb = 0; rb < row_blocks; ++rb) B.descs.push_back(row_block_desc(P, d, rb, block));
   }
   const auto& vo = P.valid_off_h;
-  const int row_blocks = m2l_row_blocks(P.ip.Kp);
   for (size_t i = 0; i < P.base_items.size(); ++i) {
     const M2LItem& it = P.base_items[i];
     M2LItem o = it;
@@ -120,7 +144,7 @@ void add_source(LaunchBuilder& B, const Plan& P, int64_t b0, int64_t b1, const v
     // one item per row block of the matrices (disjoint rows of the result)
     for (int rb = 0; rb < row_blocks; ++rb) {
       M2LItem r = o;
-      r.first = o.first | rb << 1;
+      r.desc = o.desc + rb;
       B.items.push_back(r);
       // plain: nb / 32 tiles per offset; compacted: the item's tiles, shared
       // over its parts in proportion to their offsets
@@ -472,7 +496,9 @@ void launch_bank(Plan& P, hipStream_t s) {
     for (size_t i = 0; i < T.adm.size(); ++i)
       P.bank_info.insert(P.bank_info.end(), {l, T.adm[i].x, T.adm[i].y, T.adm[i].z, T.dir[i]});
   }
-  P.sym = P.bank_budget == 0 && !P.full_bank && !P.aca_kp &&
+  // (row blocks shift the stored orientation's rows; the transposed reads
+  // would need another shift: matrices split into row blocks are all stored)
+  P.sym = P.bank_budget == 0 && !P.full_bank && !P.aca_kp && m2l_row_blocks(P.ip.Kp) == 1 &&
           (P.prec == FDM_PREC_FP64 || P.prec == FDM_PREC_FP32) && bank_pairs_mirror(P);
   P.n_bank_stored = 0;
   if (P.n_bank == 0 || P.bank_budget != 0) return;  // streamed: generated per matvec

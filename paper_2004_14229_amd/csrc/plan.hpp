@@ -70,6 +70,10 @@ struct M2LDesc {
   int32_t nd, level;
   int32_t K;  // interpolation nodes per box, (m+1)^3 <= Kp: rows / k beyond are padding
   int32_t kp;  // low-rank couplings: the rank cap (columns of U, rows of Vt), else 0
+  // coupling-matrix rows this descriptor's items compute (Kp; for a matrix
+  // split into row blocks, the block's rows: bank and out then point at the
+  // block's first row, the row stride stays Kp)
+  int32_t rows;
 };
 
 // Descriptor of one plan's near field in a queued launch.
