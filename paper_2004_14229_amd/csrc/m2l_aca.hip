@@ -8,18 +8,19 @@
 // into groups of 16; one launch pair covers one group of many items, so that
 // every group's T fits the plan's buffer and no two workgroups of a launch
 // add into the same result.  A group runs at its padded rank rp (its first
-// offset's rank rounded up to 16, at least 32; stored in the item's `first`
-// field as rp / 16 above the first-part bit): T rows and U columns beyond
-// the rank are zero, so the padding changes no value.  `compact` holds the
-// group's place in T, in units of 64 columns x 16 ranks.
+// offset's rank rounded up to 16; stored in the item's `first` field as
+// rp / 16 above the first-part bit): T rows and U columns beyond the rank
+// are zero, so the padding changes no value.  `compact` holds the group's
+// place in T, in units of 64 columns x 16 ranks.
 //
 // Stage 1 items (this file): a workgroup of 2 waves owns the 64 target
 // slots of a group; for each of its offsets it gathers the source moment
 // columns (as the dense items do), multiplies them by Vt of that offset
 // (wave w: slot tile w, 1 or 2 rank tiles of 32; FP32 MFMA with FP32 sums)
-// and writes the rp x 64 result to T.  Stage 2 items are the FP32 item of
-// m2l_device.hpp with the U factor as its matrix and T as its columns (FP32
-// per-offset sums, FP32 totals of the group, FP64 result).
+// and writes the rp x 64 result to T, every slot's column (zero where the
+// source box is empty).  Stage 2 items are the FP32 item of m2l_device.hpp
+// with the U factor as its matrix and T as its columns, read by address
+// (FP32 per-offset sums, FP32 totals of the group, FP64 result).
 #include "m2l_device.hpp"
 
 namespace fdm {
@@ -103,7 +104,7 @@ __device__ __forceinline__ void item_aca1(F32Shared<64>& sh, const M2LItem& it,
   const int nv = it.vo_count;
   if (nv == 0) return;
   const int kp = D.kp;
-  const int rp = 16 * (it.first >> 1);  // padded rank of the group: 32, 48 or 64
+  const int rp = 16 * (it.first >> 1);  // padded rank of the group: 16, 32, 48 or 64
   const bool two = rp > 32;              // a second rank tile
   const float* mom = static_cast<const float*>(D.mom);
   const float* bank = static_cast<const float*>(D.bank);

@@ -517,18 +517,21 @@ __device__ __forceinline__ void mfma32(f16v (&ar)[NB / 32], f16v (&ai)[NB / 32],
 // are added to the FP64 result in memory, which this workgroup alone owns.
 constexpr int kFlush = 16;
 
-// Columns of the second stage of a low-rank coupling group (ACA, NB = 64):
-// target slot j of the group's offset v reads column v * 64 + j of the
-// group's part of the first stage's output T (D.mom; the part starts
-// `base` units of 64 x 16 complex values in, rp entries per column), or
-// nothing where the source box is empty.
-__device__ __forceinline__ void aca_columns(TargetTile<64>& S, int buf, const M2LDesc& D,
-                                            int4 od, int c, int Kp, int64_t base, int v,
-                                            int rp) {
-  for (int j = threadIdx.x; j < 64; j += blockDim.x)
-    S.col[buf][j] = source_column(S, j, D, od, c, Kp) >= 0
-                        ? base * 1024 + (int64_t(v) * 64 + j) * rp
-                        : -1;
+// One k slab of the second stage's columns (ACA, NB = 64): target slot j of
+// the group's offset v reads column v * 64 + j of the group's part of the
+// first stage's output T (D.mom; the part starts `base` units of 64 x 16
+// complex values in, rp entries per column).  The first stage writes every
+// slot's column, zero where the source box is empty, so the address alone
+// decides what is read.
+__device__ __forceinline__ float4 load_cols_aca(const float* __restrict__ T, int64_t base, int v,
+                                                int rp, int k0) {
+  float4 val{};
+  const int e = threadIdx.x;
+  if (e < 64 * 8) {  // 8 float4 pieces per column of 16 complex values
+    const int64_t col = base * 1024 + (int64_t(v) * 64 + e / 8) * rp;
+    val = gload16<float4>(T + 2 * (col + k0) + (e % 8) * 4);
+  }
+  return val;
 }
 
 // ACA: the item is the second stage of a low-rank coupling group (Sect. 2.7,
@@ -536,7 +539,8 @@ __device__ __forceinline__ void aca_columns(TargetTile<64>& S, int buf, const M2
 // and the columns are the first stage's T = Vt M; rp / 16 slabs per offset
 // at the group's padded rank rp (`first` >> 1 = rp / 16, bit 0 the
 // first-part flag; `compact` = the group's place in T), every offset as
-// stored.
+// stored.  Non-ACA items need two slabs per offset at least (the next
+// offset's source columns are written one step before they are read).
 template <int NB, bool ADD, bool ACA = false>
 __device__ __forceinline__ void item_f32(F32Shared<NB>& sh, const M2LItem& it,
                                          const M2LDesc& D, int Kp) {
@@ -567,16 +571,19 @@ __device__ __forceinline__ void item_f32(F32Shared<NB>& sh, const M2LItem& it,
   const int ns = ACA ? (it.first >> 1) : Kp / Tr::KS;  // k slabs per offset (>= 2)
   const int total = nv * ns;
   auto columns = [&](int buf, int4 od, int v) {
+    if constexpr (!ACA) source_columns(sh.S, buf, D, od, it.c, Kp);
+  };
+  auto slab = [&](int buf, int v, int k0) {  // the columns of one step
     if constexpr (ACA)
-      aca_columns(sh.S, buf, D, od, it.c, Kp, it.compact, v, ns * Tr::KS);
+      return load_cols_aca(mom, it.compact, v, ns * Tr::KS, k0);
     else
-      source_columns(sh.S, buf, D, od, it.c, Kp);
+      return load_cols<Tr, NB>(sh.S, buf, mom, k0);
   };
   int4 od_cur = offset_of(D, it.vo_begin);
   int4 od_next = od_cur;
   columns(0, od_cur, 0);
   __syncthreads();
-  store_cols<Tr, NB>(sh, 0, load_cols<Tr, NB>(sh.S, 0, mom, 0));
+  store_cols<Tr, NB>(sh, 0, slab(0, 0, 0));
   __syncthreads();
   bool first = (it.first & 1) != 0;
   auto step = [&](auto transposed, int q) {
@@ -590,7 +597,7 @@ __device__ __forceinline__ void item_f32(F32Shared<NB>& sh, const M2LItem& it,
     }
     const bool more = q + 1 < total;
     float4 nxt{};
-    if (more) nxt = load_cols<Tr, NB>(sh.S, ((q + 1) / ns) & 1, mom, ((q + 1) % ns) * Tr::KS);
+    if (more) nxt = slab(((q + 1) / ns) & 1, (q + 1) / ns, ((q + 1) % ns) * Tr::KS);
     if (rows_here) {
       if (s == 0) {
         zero(acr);

@@ -354,10 +354,10 @@ std::vector<M2LLaunch> build_aca_schedule(const std::vector<Plan*>& plans,
         M2LItem it = base;
         it.vo_begin = base.vo_begin + g * G;
         it.vo_count = n;
-        int rp = 32;
+        int rp = 16;
         if (n) {
           rp = (P.aca_rank[vos[q][it.vo_begin]] + 15) / 16 * 16;
-          rp = std::min(std::max(rp, 32), kp);
+          rp = std::min(std::max(rp, 16), kp);
         }
         it.first = (g == 0 ? 1 : 0) | (rp / 16) << 1;
         const int64_t units = int64_t(n) * (rp / 16);
