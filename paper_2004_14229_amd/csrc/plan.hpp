@@ -102,11 +102,14 @@ struct AdaptNear {
 
 // Queue item.  desc >= 0: coupling item of descriptor `desc` -- targets
 // tgt_list[tgt_begin .. +ntgt), direction c, offsets valid_off[vo_begin ..
-// +vo_count); `first` = 1 for the first part of a (target block, c), whose
-// result is stored, 0 for later parts (streamed banks), which add to it.
-// `compact` = 1: the coupling item runs with compacted columns (FP32 and
-// BF16 kernels, 64 targets per item).  desc < 0: near-field item of P2P
-// descriptor -desc-1 for target points tgt_begin .. +ntgt (tree order).
+// +vo_count); bit 0 of `first` = 1 for the first part of a (target block,
+// c), whose result is stored, 0 for later parts (streamed banks, offset
+// groups), which add to it.  `compact` = 1: the coupling item runs with
+// compacted columns (FP32 and BF16 kernels, 64 targets per item).
+// Low-rank stage items (offset groups of at most 16): `first` >> 1 = the
+// group's padded rank / 16, `compact` = its place in the first stage's
+// output (units of 64 x 16 complex values).  desc < 0: near-field item of
+// P2P descriptor -desc-1 for target points tgt_begin .. +ntgt (tree order).
 struct M2LItem {
   int32_t desc, c, tgt_begin, ntgt, vo_begin, vo_count, first, compact;
 };
