@@ -58,11 +58,11 @@ def test_coupling_matrices_within_tolerance(o, c, eps):
 
 
 def test_matvec_with_compressed_couplings():
-    P = W.random_problem(51, 700, 650, 40.0, 4, 4)
+    P = W.random_problem(51, 700, 650, 40.0, 3, 4)
     plan = oracle.build(P.points_T, P.points_S, P.kappa, P.box, P.levels, P.m)
-    y = oracle.matvec(plan, P.v)
-    for eps in (1e-4, 1e-6, 1e-10):
-        # the operator error follows the tolerance (about 0.6 eps here), and
+    epss = (1e-4, 1e-6, 1e-10)
+    ys = oracle.matvec(plan, P.v, m2l=("fp64",) + tuple(f"aca:{e:g}" for e in epss))
+    for eps, ya in zip(epss, ys[1:]):
+        # the operator error follows the tolerance (about 0.4 eps here), and
         # is not zero: the compressed matrices are the ones applied
-        ya = oracle.matvec(plan, P.v, m2l=f"aca:{eps:g}")
-        assert 0.05 * eps <= _rel(ya, y) <= 2 * eps, eps
+        assert 0.05 * eps <= _rel(ya, ys[0]) <= 2 * eps, eps
