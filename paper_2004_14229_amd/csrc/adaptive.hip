@@ -17,7 +17,8 @@
 //    of a refined box from its children (M2M); the far field of a target
 //    leaf of any level is evaluated from its locals (L2T).
 // The coupling items run over existing target boxes against a source grid
-// without the pruned boxes; S2M and L2T run over per-level leaf lists.
+// without the pruned boxes; S2M and L2T run over per-level leaf lists; the
+// near-field blocks of each target box are listed at plan build.
 #include <algorithm>
 
 #include "plan.hpp"
@@ -34,42 +35,100 @@ __global__ void k_prune_grid(const uint32_t* __restrict__ key, const uint8_t* __
     if (state[b] == 0) grid[key[b]] = -1;
 }
 
-// Thread per target point (tree order): the near-field blocks of its boxes
-// on every level down to its leaf, stored into y.  On level l its box t
-// meets the existing source boxes s = t - o at the level's inadmissible
-// offsets o; the pair is a near-field block when t is a leaf or s is.
-__global__ void __launch_bounds__(256) k_p2p_adaptive(
-    const AdaptNear* __restrict__ lv, int p, const uint32_t* __restrict__ keyTp,
-    const int32_t* __restrict__ leaf_of, const double* __restrict__ xt,
-    const double* __restrict__ yt, const double* __restrict__ zt,
-    const double* __restrict__ xs, const double* __restrict__ ys,
-    const double* __restrict__ zs, const double2* __restrict__ v,
-    const int32_t* __restrict__ off, const int32_t* __restrict__ off_begin, double kappa,
-    double2* __restrict__ y, int64_t nT) {
+constexpr int kNearThreads = 256;
+
+// One workgroup per near-field item: the sums over the item's blocks for
+// each of its target points, stored into z[level * nT + point].  Sources are
+// staged through LDS in tiles of 256; an item of n <= 128 points gives each
+// point 256 / 2^ceil(log2 n) lanes, each taking every such source of a tile,
+// and their partial sums are added in lane order.
+__global__ void __launch_bounds__(kNearThreads) k_near_items(
+    const int4* __restrict__ items, const int2* __restrict__ ranges,
+    const double* __restrict__ xt, const double* __restrict__ yt,
+    const double* __restrict__ zt, const double* __restrict__ xs,
+    const double* __restrict__ ys, const double* __restrict__ zs,
+    const double2* __restrict__ v, double kappa, double2* __restrict__ z, int64_t nT) {
+  __shared__ int32_t pre[kNearThreads + 1];  // exclusive prefix of the batch's counts
+  __shared__ int32_t rst[kNearThreads];      // first source slot of each range
+  __shared__ double sx[kNearThreads], sy[kNearThreads], sz[kNearThreads];
+  __shared__ double2 sv[kNearThreads];
+  const int t = threadIdx.x;
+  const int4 it = items[blockIdx.x];
+  const int n = it.y & 0xffff, level = it.y >> 16;
+  int pw = 1;
+  while (pw < n) pw <<= 1;
+  const int sub = kNearThreads / pw;
+  const int i = t / sub, q = t % sub;
+  const bool act = i < n;
+  double px = 0.0, py = 0.0, pz = 0.0;
+  if (act) {
+    px = xt[it.x + i];
+    py = yt[it.x + i];
+    pz = zt[it.x + i];
+  }
+  double ar = 0.0, ai = 0.0;
+  for (int rb = it.z; rb < it.w; rb += kNearThreads) {
+    const int nr = min(kNearThreads, it.w - rb);
+    int c = 0;
+    if (t < nr) {
+      const int2 r = ranges[rb + t];
+      rst[t] = r.x;
+      c = r.y;
+    }
+    pre[t + 1] = c;
+    if (t == 0) pre[0] = 0;
+    __syncthreads();
+    for (int off = 1; off < kNearThreads; off <<= 1) {  // inclusive scan of pre[1..]
+      const int x = t >= off ? pre[t + 1 - off] : 0;
+      __syncthreads();
+      pre[t + 1] += x;
+      __syncthreads();
+    }
+    const int total = pre[nr];
+    for (int s0 = 0; s0 < total; s0 += kNearThreads) {
+      const int g = s0 + t;
+      if (g < total) {  // the range holding flat index g: last r with pre[r] <= g
+        int lo = 0, hi = nr - 1;
+        while (lo < hi) {
+          const int mid = (lo + hi + 1) >> 1;
+          if (pre[mid] <= g) lo = mid; else hi = mid - 1;
+        }
+        const int k = rst[lo] + (g - pre[lo]);
+        sx[t] = xs[k];
+        sy[t] = ys[k];
+        sz[t] = zs[k];
+        sv[t] = v[k];
+      }
+      __syncthreads();
+      const int tile = min(kNearThreads, total - s0);
+      if (act)
+        for (int u = q; u < tile; u += sub)
+          kernel_add(px, py, pz, sx[u], sy[u], sz[u], sv[u], kappa, ar, ai);
+      __syncthreads();
+    }
+  }
+  sv[t] = make_double2(ar, ai);
+  __syncthreads();
+  if (act && q == 0) {
+    double2 acc = sv[t];
+    for (int u = 1; u < sub; ++u) {
+      acc.x += sv[t + u].x;
+      acc.y += sv[t + u].y;
+    }
+    z[int64_t(level) * nT + it.x + i] = acc;
+  }
+}
+
+// y[j] = the sum of point j's level sums, from the root to its leaf.
+__global__ void k_near_sum(const double2* __restrict__ z, const uint8_t* __restrict__ leaf_level,
+                           int64_t nT, double2* __restrict__ y) {
   const int64_t j = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
   if (j >= nT) return;
-  const double px = xt[j], py = yt[j], pz = zt[j];
-  const uint32_t kp = keyTp[leaf_of[j]];
   double ar = 0.0, ai = 0.0;
-  for (int l = 0; l <= p; ++l) {
-    const AdaptNear L = lv[l];
-    const uint32_t kl = kp >> (3 * (p - l));
-    const int32_t tb = L.gridT[kl];
-    const bool leafT = L.stateT[tb] == 2;
-    int ix, iy, iz;
-    demorton3(kl, l, ix, iy, iz);
-    const int lim = 1 << l;
-    for (int i = off_begin[l]; i < off_begin[l + 1]; ++i) {
-      const int sx = ix - off[3 * i], sy = iy - off[3 * i + 1], sz = iz - off[3 * i + 2];
-      if (sx < 0 || sy < 0 || sz < 0 || sx >= lim || sy >= lim || sz >= lim) continue;
-      const int32_t sb = L.gridS[morton3(sx, sy, sz, l)];
-      if (sb < 0) continue;
-      if (!leafT && L.stateS[sb] != 2) continue;  // refined pair: not a leaf block
-      const int k0 = L.startS[sb], kn = L.countS[sb];
-      for (int k = k0; k < k0 + kn; ++k)
-        kernel_add(px, py, pz, xs[k], ys[k], zs[k], v[k], kappa, ar, ai);
-    }
-    if (leafT) break;
+  for (int l = 0; l <= leaf_level[j]; ++l) {
+    const double2 a = z[l * nT + j];
+    ar += a.x;
+    ai += a.y;
   }
   y[j] = make_double2(ar, ai);
 }
@@ -141,60 +200,85 @@ void build_adaptive(Plan& P, hipStream_t s) {
       FDM_LAUNCH("k_prune_grid");
     }
   }
-  // inadmissible offsets of every level, for the near field
-  std::vector<int32_t> off;
-  P.adapt_off_begin.assign(1, 0);
-  for (int l = 0; l <= p; ++l) {
-    for (const Off& o : P.tab[l].inadm) off.insert(off.end(), {o.x, o.y, o.z});
-    P.adapt_off_begin.push_back(static_cast<int32_t>(off.size() / 3));
-  }
-  to_device(P.adapt_off, off, s, &P.tally);
-  to_device(P.adapt_off_begin_d, P.adapt_off_begin, s, &P.tally);
-  std::vector<AdaptNear> lv(p + 1);
-  for (int l = 0; l <= p; ++l)
-    lv[l] = AdaptNear{P.T.grid[l].get(), P.stateT[l].get(), P.gridS_alive[l].get(),
-                      P.stateS[l].get(), P.S.start[l].get(), P.S.count[l].get()};
-  to_device(P.adapt_near, lv, s, &P.tally);
   FDM_HIP(hipStreamSynchronize(s));
 }
 
-void adaptive_near_stats(Plan& P, hipStream_t s) {
+// The near-field blocks of every existing target box, level by level (the
+// pairs (t, s) at the level's inadmissible offsets whose t or s is a leaf),
+// as source point ranges in work items of at most 256 target points, most
+// work first, and the near-field statistics.
+void adaptive_near_field(Plan& P, hipStream_t s) {
+  const int p = P.levels;
   P.near_pairs = 0;
   P.near_entries = 0;
-  if (P.nT == 0 || P.nS == 0) return;
-  for (int l = 0; l <= P.levels; ++l) {
+  std::vector<int2> ranges;
+  std::vector<std::pair<int64_t, int4>> items;  // (work, item)
+  std::vector<uint8_t> leaf_level(P.nT, 0);
+  for (int l = 0; l <= p; ++l) {
     std::vector<uint32_t> kT = to_host(P.T.key[l].get(), P.T.nb[l], s);
+    std::vector<int32_t> sT = to_host(P.T.start[l].get(), P.T.nb[l], s);
     std::vector<int32_t> cT = to_host(P.T.count[l].get(), P.T.nb[l], s);
     std::vector<int32_t> gS = to_host(P.gridS_alive[l].get(), size_t(1) << (3 * l), s);
+    std::vector<int32_t> sS = to_host(P.S.start[l].get(), P.S.nb[l], s);
     std::vector<int32_t> cS = to_host(P.S.count[l].get(), P.S.nb[l], s);
     const int lim = 1 << l;
     for (size_t b = 0; b < kT.size(); ++b) {
       const uint8_t st = P.stateT_h[l][b];
       if (st == 0) continue;
+      if (st == 2) std::fill_n(leaf_level.begin() + sT[b], cT[b], static_cast<uint8_t>(l));
+      const size_t r0 = ranges.size();
+      int64_t ns = 0;
       int ix, iy, iz;
       demorton3(kT[b], l, ix, iy, iz);
       for (const Off& o : P.tab[l].inadm) {
+        if (P.nS == 0) break;
         const int sx = ix - o.x, sy = iy - o.y, sz = iz - o.z;
         if (sx < 0 || sy < 0 || sz < 0 || sx >= lim || sy >= lim || sz >= lim) continue;
         const int32_t sb = gS[morton3(sx, sy, sz, l)];
         if (sb < 0) continue;
-        if (st != 2 && P.stateS_h[l][sb] != 2) continue;
+        if (st != 2 && P.stateS_h[l][sb] != 2) continue;  // refined pair
+        ranges.push_back(make_int2(sS[sb], cS[sb]));
+        ns += cS[sb];
         ++P.near_pairs;
         P.near_entries += int64_t(cT[b]) * cS[sb];
       }
+      if (ranges.size() > size_t(INT32_MAX)) fail(FDM_ERR_UNSUPPORTED, "near-field lists too long");
+      for (int32_t c = 0; c < cT[b]; c += kNearThreads) {
+        const int32_t n = std::min(kNearThreads, cT[b] - c);
+        items.push_back({int64_t(n) * ns + n,
+                         make_int4(sT[b] + c, n | (l << 16), static_cast<int32_t>(r0),
+                                   static_cast<int32_t>(ranges.size()))});
+      }
     }
   }
+  std::stable_sort(items.begin(), items.end(),
+                   [](const auto& a, const auto& b) { return a.first > b.first; });
+  std::vector<int4> it(items.size());
+  for (size_t k = 0; k < items.size(); ++k) it[k] = items[k].second;
+  P.n_near_items = static_cast<int64_t>(it.size());
+  to_device(P.near_items, it, s, &P.tally);
+  to_device(P.near_ranges, ranges, s, &P.tally);
+  to_device(P.near_leaf_level, leaf_level, s, &P.tally);
+  P.near_z.alloc(size_t(2) * (p + 1) * P.nT, &P.tally);
+  FDM_HIP(hipStreamSynchronize(s));
 }
 
+// Every item writes its points' sums of its level, and every point lies in
+// one item of each level from the root to its leaf, so the level sums are
+// complete without clearing.
 void launch_p2p_adaptive(Plan& P, hipStream_t s) {
-  if (P.nT == 0 || P.nS == 0) return;
-  const int B = 256;
-  k_p2p_adaptive<<<static_cast<unsigned>((P.nT + B - 1) / B), B, 0, s>>>(
-      P.adapt_near.get(), P.levels, P.T.key[P.levels].get(), P.T.leaf_of.get(), P.T.x.get(),
-      P.T.y.get(), P.T.z.get(), P.S.x.get(), P.S.y.get(), P.S.z.get(),
-      reinterpret_cast<const double2*>(P.vtree()), P.adapt_off.get(),
-      P.adapt_off_begin_d.get(), P.kappa, reinterpret_cast<double2*>(P.ytree()), P.nT);
-  FDM_LAUNCH("k_p2p_adaptive");
+  if (P.nT == 0) return;
+  double2* z = reinterpret_cast<double2*>(P.near_z.get());
+  if (P.n_near_items) {
+    k_near_items<<<static_cast<unsigned>(P.n_near_items), kNearThreads, 0, s>>>(
+        P.near_items.get(), P.near_ranges.get(), P.T.x.get(), P.T.y.get(), P.T.z.get(),
+        P.S.x.get(), P.S.y.get(), P.S.z.get(), reinterpret_cast<const double2*>(P.vtree()),
+        P.kappa, z, P.nT);
+    FDM_LAUNCH("k_near_items");
+  }
+  k_near_sum<<<grid_for(P.nT, 256), 256, 0, s>>>(z, P.near_leaf_level.get(), P.nT,
+                                                  reinterpret_cast<double2*>(P.ytree()));
+  FDM_LAUNCH("k_near_sum");
 }
 
 }  // namespace fdm

@@ -107,7 +107,7 @@ void plan_build(Plan& P, const double* pT, const double* pS, hipStream_t s) {
   }
   // near-field statistics (host, from box counts)
   if (P.adaptive()) {
-    adaptive_near_stats(P, s);
+    adaptive_near_field(P, s);
   } else {
     const int p = P.levels;
     P.near_pairs = 0;

@@ -90,16 +90,6 @@ struct P2PDesc {
   int32_t n_off, level;
 };
 
-// Per level of an adaptive plan, what its near-field kernel reads.
-struct AdaptNear {
-  const int32_t* gridT;   // full target grid: key -> box
-  const uint8_t* stateT;  // box -> 0 pruned, 1 refined, 2 leaf
-  const int32_t* gridS;   // source grid without the pruned boxes
-  const uint8_t* stateS;
-  const int32_t* startS;
-  const int32_t* countS;
-};
-
 // Queue item.  desc >= 0: coupling item of descriptor `desc` -- targets
 // tgt_list[tgt_begin .. +ntgt), direction c, offsets valid_off[vo_begin ..
 // +vo_count); bit 0 of `first` = 1 for the first part of a (target block,
@@ -245,10 +235,16 @@ struct Plan {
   std::vector<DevBuf<int32_t>> gridS_alive;  // source grid without pruned boxes
   std::vector<DevBuf<int32_t>> leafT, leafS;  // per level: leaf boxes
   std::vector<int64_t> n_leafT, n_leafS;
-  DevBuf<int32_t> adapt_off;     // per level: inadmissible offsets (x, y, z)
-  std::vector<int32_t> adapt_off_begin;  // per level: first triple, and the end
-  DevBuf<int32_t> adapt_off_begin_d;
-  DevBuf<AdaptNear> adapt_near;  // per level: what the near-field kernel reads
+  // near field: one item per (level, existing target box, chunk of at most
+  // 256 of its points), x = first point (tree order), y = count | level << 16,
+  // [z, w) = its near-field blocks in near_ranges as (first source slot,
+  // count); per point the level of its leaf; per level and point the sum of
+  // that level's blocks (near_z, complex128 [(levels + 1) * nT])
+  DevBuf<int4> near_items;
+  DevBuf<int2> near_ranges;
+  DevBuf<uint8_t> near_leaf_level;
+  DevBuf<double> near_z;
+  int64_t n_near_items = 0;
   bool adaptive() const { return n_max > 0; }
 
   // workspaces
@@ -313,7 +309,7 @@ P2PDesc p2p_desc(const Plan& P);
 // adaptive trees (adaptive.hip): box states, leaf lists and pruned grids
 // after the full-depth trees are built; near-field statistics; near field
 void build_adaptive(Plan& P, hipStream_t s);
-void adaptive_near_stats(Plan& P, hipStream_t s);
+void adaptive_near_field(Plan& P, hipStream_t s);  // near-field lists and statistics
 void launch_p2p_adaptive(Plan& P, hipStream_t s);
 
 // coupling work and schedules (m2l_work.hip)

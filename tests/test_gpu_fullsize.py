@@ -105,7 +105,7 @@ def test_bf16x6_sampled_rows(name):
     assert_close(y[rows], yo, min(1e-6, 3 * rel(ye, yo)))
 
 
-@pytest.mark.parametrize("name", ["uniform100k", "uniform1m"])
+@pytest.mark.parametrize("name", ["uniform100k", "uniform1m", "uniform4m"])
 def test_aca_sampled_rows(name):
     """Low-rank couplings (ACA to 1e-7, FP32 matrix-core stages) against the
     oracle's dense-coupling rows: the mixed-precision bound 1e-6 covers the
