@@ -15,7 +15,8 @@ Rows: 64 seeded rows at N = 1e5; 256 seeded rows plus the targets nearest
 the box corners, face centres and centre at N = 1e6 (boundary leaves and
 interior leaves), at N = 4e6 (32 + 15) and on the paper's k = 6 grid
 (256 + 15).  The 4e6-point workload runs with its bank streamed through a
-24 GB workspace, as the 188 GB FP32 bank does not fit beside its moments;
+24 GB workspace where the bank does not fit beside its moments (FP64, BF16
+splits; the symmetric FP32 bank of 99 GB is resident);
 of its runs only the BF16 three-product one is in the default suite.
 """
 import os
@@ -33,6 +34,7 @@ _cache = {}
 
 
 BUDGET = {"uniform4m": 24 << 30}
+RESIDENT = {("uniform4m", "fp32")}  # its symmetric FP32 bank (99 GB) fits
 
 # The 4e6-point runs take one to three minutes each (the bank is regenerated
 # every matvec); the BF16 three-product one always runs, the others when
@@ -51,7 +53,8 @@ def run(name, prec, aca_eps=0.0):
         pt = to_dev(P.points_T)
         ps = pt if P.same_points else to_dev(P.points_S)
         with F.Plan(pt, ps, P.kappa, P.box, P.levels, P.m, precision=prec,
-                    bank_budget=0 if aca_eps else BUDGET.get(name, 0),
+                    bank_budget=0 if aca_eps or (name, prec) in RESIDENT
+                    else BUDGET.get(name, 0),
                     aca_eps=aca_eps) as plan:  # (low-rank banks stay resident)
             y = plan.matvec(to_dev(P.v))
             torch.cuda.synchronize()
@@ -142,7 +145,8 @@ def test_structure_paper_grid_k6():
                                   pytest.param("bf16x6", marks=large)])
 def test_uniform4m_sampled_rows(prec):
     """4e6 points, kappa = 400, 8 levels, m = 6 (the large high-frequency
-    workload), streamed bank: FP32 within 1e-6 of the oracle's rows, BF16
+    workload), FP32 with its symmetric bank resident (99 GB), the BF16 splits
+    with theirs streamed: FP32 within 1e-6 of the oracle's rows, BF16
     split products within 3x the oracle's emulation of them (and the
     six-product split within 1e-6 too)."""
     rows, yo = golden("uniform4m")
@@ -150,6 +154,8 @@ def test_uniform4m_sampled_rows(prec):
     _cache.pop(("uniform4m", prec, 0.0), None)
     assert np.all(np.isfinite(y))
     assert st["n_stored_couplings"] == 200258
+    if prec == "fp32":  # resident: one matrix per offset pair
+        assert st["n_bank_matrices"] == 200258 // 2
     tol = 1e-6 if prec == "fp32" else 3 * rel(golden("uniform4m", f"y_{prec}")[1], yo)
     if prec == "bf16x6":
         tol = min(tol, 1e-6)
