@@ -1181,13 +1181,148 @@ __device__ __forceinline__ void item_compact(SH& sh, const M2LItem& it, const M2
     while (go) go = step(std::true_type{});
 }
 
+// Compacted FP32 item with two k slabs (32 k) per pipeline step.  A
+// compacted pass has one column tile, half the products per step of a plain
+// item, while the per-step costs (barrier, matrix load latency, staging)
+// stay; two slabs per step halve those per product.  The staged slab pair
+// sits in the plain item's LDS tile: k 0..15 of the step in columns 0..31,
+// k 16..31 in columns 32..63.  Products, their order, per-offset sums,
+// totals and flushes are those of the one-slab item, bit for bit.
+__device__ __forceinline__ float4 load_cols_compact2(const TargetTile<64>& S, int colbuf,
+                                                     int base, const float* __restrict__ mom,
+                                                     int k0) {
+  constexpr int PPC = F32Traits::KS * 2 / 4;  // float4 pieces per column and slab
+  float4 val{};
+  const int e = threadIdx.x;
+  if (e < 64 * PPC) {
+    const int jj = e / PPC, h = jj / 32;
+    const int i = base + jj % 32;
+    if (i < S.nval[colbuf])
+      val = gload16<float4>(mom + 2 * (S.col[colbuf][i] + k0 + 16 * h) + (e % PPC) * 4);
+  }
+  return val;
+}
+
+__device__ __forceinline__ void mfma32_tile2(f16v& ar, f16v& ai, const float (&a)[2][2][8],
+                                             const F32Shared<64>& sh, int buf, int lane) {
+  const int kl = lane / 32, cl = lane % 32;
+#pragma unroll
+  for (int h = 0; h < 2; ++h)
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+      const int kb = k_of_step32(t, kl);
+      const float b_r = sh.B[buf][0][kb][32 * h + cl];
+      const float b_i = sh.B[buf][1][kb][32 * h + cl];
+      ar = __builtin_amdgcn_mfma_f32_32x32x2f32(a[h][0][t], b_r, ar, 0, 0, 0);
+      ar = __builtin_amdgcn_mfma_f32_32x32x2f32(-a[h][1][t], b_i, ar, 0, 0, 0);
+      ai = __builtin_amdgcn_mfma_f32_32x32x2f32(a[h][0][t], b_i, ai, 0, 0, 0);
+      ai = __builtin_amdgcn_mfma_f32_32x32x2f32(a[h][1][t], b_r, ai, 0, 0, 0);
+    }
+}
+
+// Needs Kp >= 64 (two steps per pass: the next offset's columns are
+// compacted one step before they are read).
+__device__ __forceinline__ void item_compact_f32w(F32Shared<64>& sh, const M2LItem& it,
+                                                  const M2LDesc& D, int Kp) {
+  constexpr int KW = 32;  // k per step
+  const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+  const bool rows_here = 32 * wave < D.rows;
+  load_targets(sh.S, it, D);
+  __syncthreads();
+  double2* out = static_cast<double2*>(D.out);
+  f16v tor[2], toi[2];
+  zero(tor);
+  zero(toi);
+  const int nv = it.vo_count;
+  if (nv == 0) {  // no source box: the result is zero
+    if (rows_here && (it.first & 1))
+      flush_rows32<64>(tor, toi, sh.S, out, D.nd, it.c, Kp, wave, lane, true);
+    return;
+  }
+  const int64_t per = int64_t(Kp) * Kp;
+  const int ns = Kp / KW;  // steps per pass (>= 2)
+  const float* mom = static_cast<const float*>(D.mom);
+  const float* bank = static_cast<const float*>(D.bank);
+  auto passes = [&](int b) {
+    const int n = __builtin_amdgcn_readfirstlane(sh.S.nval[b]);
+    return std::max(1, (n + 31) / 32);
+  };
+  int4 od_cur = offset_of(D, it.vo_begin);
+  int4 od_next = od_cur;
+  source_columns_compact(sh.S, 0, D, od_cur, it.c, Kp);
+  __syncthreads();
+  int np = passes(0);
+  store_cols<F32Traits, 64>(sh, 0, load_cols_compact2(sh.S, 0, 0, mom, 0));
+  __syncthreads();
+  bool first = (it.first & 1) != 0;
+  f16v acr, aci;
+  int v = 0, p = 0, s = 0, cur = 0;
+  auto step = [&](auto transposed) -> bool {
+    if (s == 0 && p == 0 && v + 1 < nv) {  // compact the next offset's columns
+      od_next = offset_of(D, it.vo_begin + v + 1);
+      source_columns_compact(sh.S, (v + 1) & 1, D, od_next, it.c, Kp);
+    }
+    int v2 = v, p2 = p, s2 = s + 1;
+    if (s2 == ns) {
+      s2 = 0;
+      if (++p2 == np) {
+        p2 = 0;
+        ++v2;
+      }
+    }
+    const bool more = v2 < nv;
+    float4 nxt{};
+    if (more) nxt = load_cols_compact2(sh.S, v2 & 1, 32 * p2, mom, s2 * KW);
+    if (rows_here) {
+      if (s == 0) {
+        acr = f16v{};
+        aci = f16v{};
+      }
+      const float* A = bank + (od_cur.w >> 1) * 2 * per;
+      float a[2][2][8];
+      load_a32<decltype(transposed)::value>(a[0], A, per, s * KW, Kp, wave, lane);
+      load_a32<decltype(transposed)::value>(a[1], A, per, s * KW + 16, Kp, wave, lane);
+      __builtin_amdgcn_sched_barrier(0);
+      mfma32_tile2(acr, aci, a, sh, cur, lane);
+      if (s == ns - 1) {
+        scatter_add(tor, toi, acr, aci, sh.S, v & 1, 32 * p, lane);
+        if (v2 != v && ((v + 1) % kFlush == 0 || !more)) {
+          flush_rows32<64>(tor, toi, sh.S, out, D.nd, it.c, Kp, wave, lane, first);
+          first = false;
+          zero(tor);
+          zero(toi);
+        }
+      }
+    }
+    if (more) store_cols<F32Traits, 64>(sh, cur ^ 1, nxt);
+    __syncthreads();
+    if (!more) return false;
+    if (v2 != v) {
+      od_cur = od_next;
+      np = passes(v2 & 1);
+    }
+    v = v2;
+    p = p2;
+    s = s2;
+    cur ^= 1;
+    return true;
+  };
+  const int v_split = stored_prefix(D, it.vo_begin, nv);
+  bool go = true;
+  while (go && v < v_split) go = step(std::false_type{});
+  while (go) go = step(std::true_type{});
+}
+
 // FP32 and BF16 items: compacted where the item asks for it (NB = 64).
 template <int NB, bool ADD>
 __device__ __forceinline__ void item_f32k(F32Shared<NB>& sh, const M2LItem& it,
                                           const M2LDesc& D, int Kp) {
   if constexpr (NB == 64) {
     if (it.compact) {
-      item_compact<0>(sh, it, D, Kp);
+      if (Kp >= 64)
+        item_compact_f32w(sh, it, D, Kp);
+      else
+        item_compact<0>(sh, it, D, Kp);
       return;
     }
   }
