@@ -211,22 +211,27 @@ struct F32Traits {
   using T = float;
   using V16 = float4;  // 16-byte load unit
   static constexpr int KS = 16;
+  static constexpr int KW = 32;  // k staged per step by the two-slab items
 };
 struct F64Traits {
   using T = double;
   using V16 = double2;
   static constexpr int KS = 8;
+  static constexpr int KW = 8;
 };
 
-template <class Tr, int NB>
+template <class Tr, int NB, int KB = Tr::KS>
 struct M2LShared {
   TargetTile<NB> S;
-  typename Tr::T B[2][2][Tr::KS][NB + 1];  // [buffer][re/im][k][column]
+  typename Tr::T B[2][2][KB][NB + 1];  // [buffer][re/im][k][column]
 };
 template <int NB>
 using F64Shared = M2LShared<F64Traits, NB>;
 template <int NB>
 using F32Shared = M2LShared<F32Traits, NB>;
+// the FP32 coupling kernels' tile: room for two k slabs per step
+template <int NB>
+using F32SharedW = M2LShared<F32Traits, NB, F32Traits::KW>;
 
 // Moment columns of one k slab: NB columns x KS complex values, staged in
 // 16-byte pieces, at most one per thread (the workgroup has >= 512 threads).
@@ -247,9 +252,10 @@ __device__ __forceinline__ typename Tr::V16 load_cols(const TargetTile<NB>& S, i
   return val;
 }
 
-template <class Tr, int NB>
-__device__ __forceinline__ void store_cols(M2LShared<Tr, NB>& sh, int buf,
-                                           typename Tr::V16 val) {
+// (kb: first k of the staged slab within the step's tile)
+template <class Tr, int NB, int KB>
+__device__ __forceinline__ void store_cols(M2LShared<Tr, NB, KB>& sh, int buf,
+                                           typename Tr::V16 val, int kb = 0) {
   using T = typename Tr::T;
   using V = typename Tr::V16;
   constexpr int EPV = sizeof(V) / sizeof(T);
@@ -260,7 +266,7 @@ __device__ __forceinline__ void store_cols(M2LShared<Tr, NB>& sh, int buf,
     const T* v = reinterpret_cast<const T*>(&val);
 #pragma unroll
     for (int u = 0; u < EPV / 2; ++u) {
-      const int k = q * (EPV / 2) + u;
+      const int k = kb + q * (EPV / 2) + u;
       sh.B[buf][0][k][j] = v[2 * u];
       sh.B[buf][1][k][j] = v[2 * u + 1];
     }
@@ -368,7 +374,7 @@ __device__ __forceinline__ void flush_rows64(const d4v (&tr)[NB / 8], const d4v 
 // One FP64 accumulator chain per (row, target).  ADD: the launch holds later
 // parts of split items, whose results are added (a compile-time switch: the
 // add path costs registers).
-template <int NB, bool ADD>
+template <int NB, bool ADD, int MAXT = 768>
 __device__ __forceinline__ void item_f64(F64Shared<NB>& sh, const M2LItem& it,
                                          const M2LDesc& D, int Kp) {
   using Tr = F64Traits;
@@ -491,9 +497,9 @@ __device__ __forceinline__ void load_a32(float (&a)[2][8], const float* __restri
 // k (within the slab) of a lane's operands at MFMA step t.
 __device__ __forceinline__ int k_of_step32(int t, int kl) { return t + 8 * kl; }
 
-template <int NB>
+template <int NB, class SH>
 __device__ __forceinline__ void mfma32(f16v (&ar)[NB / 32], f16v (&ai)[NB / 32],
-                                       const float (&a)[2][8], const F32Shared<NB>& sh,
+                                       const float (&a)[2][8], const SH& sh,
                                        int buf, int lane) {
   const int kl = lane / 32, cl = lane % 32;
 #pragma unroll
@@ -541,8 +547,8 @@ __device__ __forceinline__ float4 load_cols_aca(const float* __restrict__ T, int
 // first-part flag; `compact` = the group's place in T), every offset as
 // stored.  Non-ACA items need two slabs per offset at least (the next
 // offset's source columns are written one step before they are read).
-template <int NB, bool ADD, bool ACA = false>
-__device__ __forceinline__ void item_f32(F32Shared<NB>& sh, const M2LItem& it,
+template <int NB, bool ADD, bool ACA = false, class SH>
+__device__ __forceinline__ void item_f32(SH& sh, const M2LItem& it,
                                          const M2LDesc& D, int Kp) {
   using Tr = F32Traits;
   constexpr int NT = NB / 32;
@@ -635,6 +641,129 @@ __device__ __forceinline__ void item_f32(F32Shared<NB>& sh, const M2LItem& it,
   for (; q < total; ++q) step(std::true_type{}, q);
 }
 
+// Plain FP32 item with two k slabs (32 k) per pipeline step, for the
+// 512-thread kernels (Kp <= 256, two waves per SIMD): their steps carry
+// two thirds of the products of a 768-thread step against the same
+// barrier, matrix-load latency and staging, and their register budget
+// (256 per lane) holds the second slab's matrix operands.  Products and
+// their order are those of item_f32, bit for bit.  Needs Kp >= 64 (two
+// steps per offset: the next offset's source columns are written one step
+// before they are read).
+template <int NB>
+__device__ __forceinline__ void mfma32w(f16v (&ar)[NB / 32], f16v (&ai)[NB / 32],
+                                        const float (&a)[2][2][8], const F32SharedW<NB>& sh,
+                                        int buf, int lane) {
+  const int kl = lane / 32, cl = lane % 32;
+#pragma unroll
+  for (int h = 0; h < 2; ++h)
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+      const int kb = 16 * h + k_of_step32(t, kl);
+#pragma unroll
+      for (int cs = 0; cs < NB / 32; ++cs) {
+        const float b_r = sh.B[buf][0][kb][32 * cs + cl];
+        const float b_i = sh.B[buf][1][kb][32 * cs + cl];
+        ar[cs] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[h][0][t], b_r, ar[cs], 0, 0, 0);
+        ar[cs] = __builtin_amdgcn_mfma_f32_32x32x2f32(-a[h][1][t], b_i, ar[cs], 0, 0, 0);
+        ai[cs] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[h][0][t], b_i, ai[cs], 0, 0, 0);
+        ai[cs] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[h][1][t], b_r, ai[cs], 0, 0, 0);
+      }
+    }
+}
+
+template <int NB, bool ADD>
+__device__ __forceinline__ void item_f32w(F32SharedW<NB>& sh, const M2LItem& it,
+                                          const M2LDesc& D, int Kp) {
+  using Tr = F32Traits;
+  constexpr int NT = NB / 32;
+  constexpr int KW = Tr::KW;
+  const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+  const bool rows_here = 32 * wave < D.rows;
+  load_targets(sh.S, it, D);
+  __syncthreads();
+  double2* out = static_cast<double2*>(D.out);
+  f16v acr[NT], aci[NT], tor[NT], toi[NT];
+  zero(acr);
+  zero(aci);
+  const int nv = it.vo_count;
+  if (nv == 0) {  // no source box: the result is zero
+    if (rows_here && (it.first & 1))
+      flush_rows32<NB>(acr, aci, sh.S, out, D.nd, it.c, Kp, wave, lane, true);
+    return;
+  }
+  zero(tor);
+  zero(toi);
+  const float* mom = static_cast<const float*>(D.mom);
+  const float* bank = static_cast<const float*>(D.bank);
+  const int64_t per = int64_t(Kp) * Kp;
+  const int ns = Kp / KW;  // steps per offset (>= 2)
+  const int total = nv * ns;
+  struct Pair {
+    float4 h[2];
+  };
+  auto slab = [&](int buf, int k0) {  // the columns of one step, both slabs
+    Pair p;
+    p.h[0] = load_cols<Tr, NB>(sh.S, buf, mom, k0);
+    p.h[1] = load_cols<Tr, NB>(sh.S, buf, mom, k0 + Tr::KS);
+    return p;
+  };
+  auto stage = [&](int buf, const Pair& p) {
+    store_cols<Tr, NB>(sh, buf, p.h[0], 0);
+    store_cols<Tr, NB>(sh, buf, p.h[1], Tr::KS);
+  };
+  int4 od_cur = offset_of(D, it.vo_begin);
+  int4 od_next = od_cur;
+  source_columns(sh.S, 0, D, od_cur, it.c, Kp);
+  __syncthreads();
+  stage(0, slab(0, 0));
+  __syncthreads();
+  bool first = (it.first & 1) != 0;
+  auto step = [&](auto transposed, int q) {
+    const int v = q / ns, s = q % ns, cur = q & 1;
+    if (s == 0) {
+      od_cur = od_next;
+      if (v + 1 < nv) {  // source columns of the next offset
+        od_next = offset_of(D, it.vo_begin + v + 1);
+        source_columns(sh.S, (v + 1) & 1, D, od_next, it.c, Kp);
+      }
+    }
+    const bool more = q + 1 < total;
+    Pair nxt{};
+    if (more) nxt = slab(((q + 1) / ns) & 1, ((q + 1) % ns) * KW);
+    if (rows_here) {
+      if (s == 0) {
+        zero(acr);
+        zero(aci);
+      }
+      const float* A = bank + (od_cur.w >> 1) * 2 * per;
+      float a[2][2][8];
+      load_a32<decltype(transposed)::value>(a[0], A, per, s * KW, Kp, wave, lane);
+      load_a32<decltype(transposed)::value>(a[1], A, per, s * KW + Tr::KS, Kp, wave, lane);
+      __builtin_amdgcn_sched_barrier(0);
+      mfma32w<NB>(acr, aci, a, sh, cur, lane);
+      if (s == ns - 1) {
+#pragma unroll
+        for (int c2 = 0; c2 < NT; ++c2) {
+          tor[c2] += acr[c2];
+          toi[c2] += aci[c2];
+        }
+        if ((v + 1) % kFlush == 0 || v + 1 == nv) {
+          flush_rows32<NB>(tor, toi, sh.S, out, D.nd, it.c, Kp, wave, lane, first);
+          first = false;
+          zero(tor);
+          zero(toi);
+        }
+      }
+    }
+    if (more) stage(cur ^ 1, nxt);
+    __syncthreads();
+  };
+  const int q_split = stored_prefix(D, it.vo_begin, nv) * ns;
+  int q = 0;
+  for (; q < q_split; ++q) step(std::false_type{}, q);
+  for (; q < total; ++q) step(std::true_type{}, q);
+}
+
 // ------------------------------------- compacted columns: the helpers --
 // At sparse levels most target slots of a block see an empty source box
 // for a given offset, and their zero columns cost the matrix cores as much
@@ -662,8 +791,9 @@ __device__ __forceinline__ float4 load_cols_compact(const TargetTile<64>& S, int
 }
 
 // One column tile of one k slab (columns 0 .. 31 of the staged slab).
+template <class SH>
 __device__ __forceinline__ void mfma32_tile(f16v& ar, f16v& ai, const float (&a)[2][8],
-                                            const F32Shared<64>& sh, int buf, int lane) {
+                                            const SH& sh, int buf, int lane) {
   const int kl = lane / 32, cl = lane % 32;
 #pragma unroll
   for (int t = 0; t < 8; ++t) {
@@ -1204,7 +1334,7 @@ __device__ __forceinline__ float4 load_cols_compact2(const TargetTile<64>& S, in
 }
 
 __device__ __forceinline__ void mfma32_tile2(f16v& ar, f16v& ai, const float (&a)[2][2][8],
-                                             const F32Shared<64>& sh, int buf, int lane) {
+                                             const F32SharedW<64>& sh, int buf, int lane) {
   const int kl = lane / 32, cl = lane % 32;
 #pragma unroll
   for (int h = 0; h < 2; ++h)
@@ -1222,7 +1352,7 @@ __device__ __forceinline__ void mfma32_tile2(f16v& ar, f16v& ai, const float (&a
 
 // Needs Kp >= 64 (two steps per pass: the next offset's columns are
 // compacted one step before they are read).
-__device__ __forceinline__ void item_compact_f32w(F32Shared<64>& sh, const M2LItem& it,
+__device__ __forceinline__ void item_compact_f32w(F32SharedW<64>& sh, const M2LItem& it,
                                                   const M2LDesc& D, int Kp) {
   constexpr int KW = 32;  // k per step
   const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
@@ -1314,8 +1444,10 @@ __device__ __forceinline__ void item_compact_f32w(F32Shared<64>& sh, const M2LIt
 }
 
 // FP32 and BF16 items: compacted where the item asks for it (NB = 64).
-template <int NB, bool ADD>
-__device__ __forceinline__ void item_f32k(F32Shared<NB>& sh, const M2LItem& it,
+// The 512-thread FP32 kernels (MAXT) take two k slabs per step in plain
+// items too.
+template <int NB, bool ADD, int MAXT = 768>
+__device__ __forceinline__ void item_f32k(F32SharedW<NB>& sh, const M2LItem& it,
                                           const M2LDesc& D, int Kp) {
   if constexpr (NB == 64) {
     if (it.compact) {
@@ -1326,9 +1458,15 @@ __device__ __forceinline__ void item_f32k(F32Shared<NB>& sh, const M2LItem& it,
       return;
     }
   }
+  if constexpr (MAXT == 512) {
+    if (Kp >= 64) {
+      item_f32w<NB, ADD>(sh, it, D, Kp);
+      return;
+    }
+  }
   item_f32<NB, ADD>(sh, it, D, Kp);
 }
-template <int NB, bool ADD>
+template <int NB, bool ADD, int MAXT = 768>
 __device__ __forceinline__ void item_bf16k(BF16Shared<NB>& sh, const M2LItem& it,
                                            const M2LDesc& D, int Kp) {
   if constexpr (NB == 64) {
@@ -1339,7 +1477,7 @@ __device__ __forceinline__ void item_bf16k(BF16Shared<NB>& sh, const M2LItem& it
   }
   item_bf16<NB, ADD, 3>(sh, it, D, Kp);
 }
-template <int NB, bool ADD>
+template <int NB, bool ADD, int MAXT = 768>
 __device__ __forceinline__ void item_bf16x6k(BF16x6Shared<NB>& sh, const M2LItem& it,
                                              const M2LDesc& D, int Kp) {
   if constexpr (NB == 64) {
@@ -1416,7 +1554,7 @@ __device__ __forceinline__ void run_items(const M2LItem* __restrict__ items, int
     __shared__ int32_t next;                                                                 \
     run_items<QUEUE, P2P && MAXT == 512>(items, n_items, descs, p2p, head, next,             \
                      [&](const M2LItem& it, const M2LDesc& D) {                              \
-                       ITEM<NB, ADD>(sh, it, D, Kp);                                         \
+                       ITEM<NB, ADD, MAXT>(sh, it, D, Kp);                                   \
                      });                                                                     \
   }
 

@@ -6,7 +6,7 @@ namespace fdm {
 
 namespace {
 
-FDM_M2L_KERNEL(k_m2l_f32, F32Shared, item_f32k, true)
+FDM_M2L_KERNEL(k_m2l_f32, F32SharedW, item_f32k, true)
 FDM_M2L_LAUNCHERS(k_m2l_f32, launch_items_f32, resident_f32, false)
 
 }  // namespace
