@@ -650,28 +650,29 @@ __device__ __forceinline__ void item_f32(SH& sh, const M2LItem& it,
 // steps per offset: the next offset's source columns are written one step
 // before they are read).
 template <int NB>
-__device__ __forceinline__ void mfma32w(f16v (&ar)[NB / 32], f16v (&ai)[NB / 32],
-                                        const float (&a)[2][2][8], const F32SharedW<NB>& sh,
-                                        int buf, int lane) {
+__device__ __forceinline__ void mfma32h(f16v (&ar)[NB / 32], f16v (&ai)[NB / 32],
+                                        const float (&a)[2][8], const F32SharedW<NB>& sh,
+                                        int buf, int h, int lane) {
   const int kl = lane / 32, cl = lane % 32;
 #pragma unroll
-  for (int h = 0; h < 2; ++h)
+  for (int t = 0; t < 8; ++t) {
+    const int kb = 16 * h + k_of_step32(t, kl);
 #pragma unroll
-    for (int t = 0; t < 8; ++t) {
-      const int kb = 16 * h + k_of_step32(t, kl);
-#pragma unroll
-      for (int cs = 0; cs < NB / 32; ++cs) {
-        const float b_r = sh.B[buf][0][kb][32 * cs + cl];
-        const float b_i = sh.B[buf][1][kb][32 * cs + cl];
-        ar[cs] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[h][0][t], b_r, ar[cs], 0, 0, 0);
-        ar[cs] = __builtin_amdgcn_mfma_f32_32x32x2f32(-a[h][1][t], b_i, ar[cs], 0, 0, 0);
-        ai[cs] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[h][0][t], b_i, ai[cs], 0, 0, 0);
-        ai[cs] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[h][1][t], b_r, ai[cs], 0, 0, 0);
-      }
+    for (int cs = 0; cs < NB / 32; ++cs) {
+      const float b_r = sh.B[buf][0][kb][32 * cs + cl];
+      const float b_i = sh.B[buf][1][kb][32 * cs + cl];
+      ar[cs] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[0][t], b_r, ar[cs], 0, 0, 0);
+      ar[cs] = __builtin_amdgcn_mfma_f32_32x32x2f32(-a[1][t], b_i, ar[cs], 0, 0, 0);
+      ai[cs] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[0][t], b_i, ai[cs], 0, 0, 0);
+      ai[cs] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[1][t], b_r, ai[cs], 0, 0, 0);
     }
+  }
 }
 
-template <int NB, bool ADD>
+// LATE: the second slab's matrix operands are loaded once the first slab's
+// products are issued (one slab's operands live at a time: the register
+// budget of the 768-thread kernels), else with the first slab's.
+template <int NB, bool ADD, bool LATE>
 __device__ __forceinline__ void item_f32w(F32SharedW<NB>& sh, const M2LItem& it,
                                           const M2LDesc& D, int Kp) {
   using Tr = F32Traits;
@@ -736,11 +737,24 @@ __device__ __forceinline__ void item_f32w(F32SharedW<NB>& sh, const M2LItem& it,
         zero(aci);
       }
       const float* A = bank + (od_cur.w >> 1) * 2 * per;
-      float a[2][2][8];
-      load_a32<decltype(transposed)::value>(a[0], A, per, s * KW, Kp, wave, lane);
-      load_a32<decltype(transposed)::value>(a[1], A, per, s * KW + Tr::KS, Kp, wave, lane);
-      __builtin_amdgcn_sched_barrier(0);
-      mfma32w<NB>(acr, aci, a, sh, cur, lane);
+      constexpr bool TR = decltype(transposed)::value;
+      if constexpr (LATE) {
+        float a[2][8];
+        load_a32<TR>(a, A, per, s * KW, Kp, wave, lane);
+        __builtin_amdgcn_sched_barrier(0);
+        mfma32h<NB>(acr, aci, a, sh, cur, 0, lane);
+        __builtin_amdgcn_sched_barrier(0);
+        load_a32<TR>(a, A, per, s * KW + Tr::KS, Kp, wave, lane);
+        __builtin_amdgcn_sched_barrier(0);
+        mfma32h<NB>(acr, aci, a, sh, cur, 1, lane);
+      } else {
+        float a[2][2][8];
+        load_a32<TR>(a[0], A, per, s * KW, Kp, wave, lane);
+        load_a32<TR>(a[1], A, per, s * KW + Tr::KS, Kp, wave, lane);
+        __builtin_amdgcn_sched_barrier(0);
+        mfma32h<NB>(acr, aci, a[0], sh, cur, 0, lane);
+        mfma32h<NB>(acr, aci, a[1], sh, cur, 1, lane);
+      }
       if (s == ns - 1) {
 #pragma unroll
         for (int c2 = 0; c2 < NT; ++c2) {
@@ -1458,11 +1472,9 @@ __device__ __forceinline__ void item_f32k(F32SharedW<NB>& sh, const M2LItem& it,
       return;
     }
   }
-  if constexpr (MAXT == 512) {
-    if (Kp >= 64) {
-      item_f32w<NB, ADD>(sh, it, D, Kp);
-      return;
-    }
+  if (Kp >= 64) {
+    item_f32w<NB, ADD, MAXT != 512>(sh, it, D, Kp);
+    return;
   }
   item_f32<NB, ADD>(sh, it, D, Kp);
 }
