@@ -865,11 +865,12 @@ __device__ __forceinline__ void scatter_add(f16v (&tor)[2], f16v (&toi)[2], cons
 template <int NB, int SPLIT>
 struct BF16SharedS {
   TargetTile<NB> S;
-  // [buffer][plane][column][k]: 16 k per slab, rows padded to 24 (48 bytes)
+  // [slot][plane][column][k]: 16 k per slab, rows padded to 24 (48 bytes)
   // so that 16 lanes' 16-byte reads of 16 consecutive columns fall in
   // distinct banks.  Planes: re hi, re lo, im hi, im lo (SPLIT 3); re hi,
-  // re mid, re lo, im hi, im mid, im lo (SPLIT 6).
-  alignas(16) uint16_t B[2][SPLIT == 3 ? 4 : 6][NB][24];
+  // re mid, re lo, im hi, im mid, im lo (SPLIT 6).  Slots: two buffers of
+  // up to two slabs (a pipeline step's k).
+  alignas(16) uint16_t B[4][SPLIT == 3 ? 4 : 6][NB][24];
 };
 template <int NB>
 using BF16Shared = BF16SharedS<NB, 3>;
@@ -1088,8 +1089,13 @@ __device__ __forceinline__ void mfma_bf16x6(f16v (&ar)[NTU], f16v (&ai)[NTU],
 }
 
 // BF16 split item (SPLIT = 3 or 6 products per real product): the FP32
-// item's pipeline with the moment slab staged as BF16 parts.
-template <int NB, bool ADD, int SPLIT>
+// item's pipeline with the moment slab staged as BF16 parts, W slabs per
+// step (W = 2 needs Kp >= 64).  A slab's products are short (one MFMA k
+// step), so two slabs per barrier halve the per-product cost of the
+// barrier, the matrix-load latency and the staging; each slab's matrix
+// operands are loaded once the previous slab's products are issued.  The
+// products and their order do not depend on W.
+template <int NB, bool ADD, int SPLIT, int W>
 __device__ __forceinline__ void item_bf16(BF16SharedS<NB, SPLIT>& sh, const M2LItem& it,
                                           const M2LDesc& D, int Kp) {
   constexpr int NT = NB / 32;
@@ -1112,7 +1118,7 @@ __device__ __forceinline__ void item_bf16(BF16SharedS<NB, SPLIT>& sh, const M2LI
   zero(toi);
   const uint16_t* bank = static_cast<const uint16_t*>(D.bank);
   const int64_t per = int64_t(Kp) * Kp;
-  const int ns = Kp / kBKS;  // k slabs per offset
+  const int ns = Kp / (kBKS * W);  // steps per offset
   const int total = nv * ns;
   // the moment slab (k slab s, buffer b): FP32 values split into two parts
   // while staged, or the forward transformation's three-part copy moved
@@ -1133,7 +1139,8 @@ __device__ __forceinline__ void item_bf16(BF16SharedS<NB, SPLIT>& sh, const M2LI
   int4 od_next = od_cur;
   source_columns(sh.S, 0, D, od_cur, it.c, Kp);
   __syncthreads();
-  store(0, load(0, 0));
+#pragma unroll
+  for (int h = 0; h < W; ++h) store(h, load(0, h));
   __syncthreads();
   bool first = (it.first & 1) != 0;
   for (int q = 0; q < total; ++q) {
@@ -1146,8 +1153,11 @@ __device__ __forceinline__ void item_bf16(BF16SharedS<NB, SPLIT>& sh, const M2LI
       }
     }
     const bool more = q + 1 < total;
-    decltype(load(0, 0)) nxt{};
-    if (more) nxt = load(((q + 1) / ns) & 1, (q + 1) % ns);
+    decltype(load(0, 0)) nxt[W]{};
+    if (more) {
+#pragma unroll
+      for (int h = 0; h < W; ++h) nxt[h] = load(((q + 1) / ns) & 1, ((q + 1) % ns) * W + h);
+    }
     if (rows_here) {
       if (s == 0) {
         zero(acr);
@@ -1157,12 +1167,16 @@ __device__ __forceinline__ void item_bf16(BF16SharedS<NB, SPLIT>& sh, const M2LI
           zero(bgi);
         }
       }
-      if constexpr (SPLIT == 3)
-        mfma_bf16x3<NB>(acr, aci, bank + (od_cur.w >> 1) * 4 * per, per, sh, cur, s,
-                        Kp, wave, lane);
-      else
-        mfma_bf16x6<NB>(acr, aci, bgr, bgi, bank + (od_cur.w >> 1) * 6 * per, per, sh, cur,
-                        s, Kp, wave, lane);
+#pragma unroll
+      for (int h = 0; h < W; ++h) {
+        if constexpr (SPLIT == 3)
+          mfma_bf16x3<NB>(acr, aci, bank + (od_cur.w >> 1) * 4 * per, per, sh, cur * W + h,
+                          s * W + h, Kp, wave, lane);
+        else
+          mfma_bf16x6<NB>(acr, aci, bgr, bgi, bank + (od_cur.w >> 1) * 6 * per, per, sh,
+                          cur * W + h, s * W + h, Kp, wave, lane);
+        __builtin_amdgcn_sched_barrier(0);
+      }
       if (s == ns - 1) {
 #pragma unroll
         for (int c2 = 0; c2 < NT; ++c2) {
@@ -1181,7 +1195,10 @@ __device__ __forceinline__ void item_bf16(BF16SharedS<NB, SPLIT>& sh, const M2LI
         }
       }
     }
-    if (more) store(cur ^ 1, nxt);
+    if (more) {
+#pragma unroll
+      for (int h = 0; h < W; ++h) store((cur ^ 1) * W + h, nxt[h]);
+    }
     __syncthreads();
   }
 }
@@ -1487,7 +1504,7 @@ __device__ __forceinline__ void item_bf16k(BF16Shared<NB>& sh, const M2LItem& it
       return;
     }
   }
-  item_bf16<NB, ADD, 3>(sh, it, D, Kp);
+  item_bf16<NB, ADD, 3, 1>(sh, it, D, Kp);  // (two slabs per step: more spills, 4% slower)
 }
 template <int NB, bool ADD, int MAXT = 768>
 __device__ __forceinline__ void item_bf16x6k(BF16x6Shared<NB>& sh, const M2LItem& it,
@@ -1498,7 +1515,10 @@ __device__ __forceinline__ void item_bf16x6k(BF16x6Shared<NB>& sh, const M2LItem
       return;
     }
   }
-  item_bf16<NB, ADD, 6>(sh, it, D, Kp);
+  if (Kp >= 64)
+    item_bf16<NB, ADD, 6, 2>(sh, it, D, Kp);
+  else
+    item_bf16<NB, ADD, 6, 1>(sh, it, D, Kp);
 }
 
 // ------------------------------------------------------------ launches --
