@@ -641,14 +641,14 @@ __device__ __forceinline__ void item_f32(SH& sh, const M2LItem& it,
   for (; q < total; ++q) step(std::true_type{}, q);
 }
 
-// Plain FP32 item with two k slabs (32 k) per pipeline step, for the
-// 512-thread kernels (Kp <= 256, two waves per SIMD): their steps carry
-// two thirds of the products of a 768-thread step against the same
-// barrier, matrix-load latency and staging, and their register budget
-// (256 per lane) holds the second slab's matrix operands.  Products and
-// their order are those of item_f32, bit for bit.  Needs Kp >= 64 (two
-// steps per offset: the next offset's source columns are written one step
-// before they are read).
+// Plain FP32 item with two k slabs (32 k) per pipeline step: the barrier,
+// the matrix-load latency at the start of a step and the staging are paid
+// once per 32 k.  The 512-thread kernels (Kp <= 256, two waves per SIMD,
+// 256 registers per lane) load both slabs' matrix operands up front; the
+// 768-thread kernels (168 registers) load the second slab's once the first
+// slab's products are issued (LATE).  Products and their order are those
+// of item_f32, bit for bit.  Needs Kp >= 64 (two steps per offset: the
+// next offset's source columns are written one step before they are read).
 template <int NB>
 __device__ __forceinline__ void mfma32h(f16v (&ar)[NB / 32], f16v (&ai)[NB / 32],
                                         const float (&a)[2][8], const F32SharedW<NB>& sh,
