@@ -47,6 +47,9 @@ def parse():
                     help="timed steps of the low-rank coupling plan")
     ap.add_argument("--batch-steps", type=int, default=2,
                     help="timed batched matvecs of the 64-problem workload (0 = skip)")
+    ap.add_argument("--batch-adaptive-n-max", type=int, default=0,
+                    help="> 0: also time the batched workload with its clustered half on "
+                         "adaptive trees of at most this many points per leaf")
     ap.add_argument("--bank-budget-gb", type=float, default=0.0,
                     help="> 0: generate the coupling bank during each matvec into a "
                          "workspace of this many GB (for banks that do not fit)")
@@ -243,7 +246,7 @@ def cpu_baseline(P, stats, shape, sub_div: int = 4):
             "measured_s": tm["total"], "extrapolated_s_per_matvec": total, "phases": phases}
 
 
-def batched(steps: int, compact: int = 1, aca_eps: float = 0.0) -> dict:
+def batched(steps: int, compact: int = 1, aca_eps: float = 0.0, n_max: int = 0) -> dict:
     """The batched workload: 64 independent problems (N log-uniform in
     [1e4, 2e5], kappa uniform in [10, 80], half uniform, half clustered, m=5,
     complex64 v) in one batch: mixed FP32 coupling, every problem's bank
@@ -251,17 +254,21 @@ def batched(steps: int, compact: int = 1, aca_eps: float = 0.0) -> dict:
     all problems from one device queue in one persistent launch, the whole
     batched matvec replayed as a HIP graph, launch shape picked by the
     autotuner.  aca_eps > 0: every coupling matrix compressed by ACA (low-rank
-    launch pairs over all problems' offset groups, near field apart)."""
+    launch pairs over all problems' offset groups, near field apart).
+    n_max > 0: the clustered half on adaptive trees (Alg. 1 with at most
+    n_max points per leaf above the last level; near field apart)."""
     import torch
     import paper_2004_14229_amd as F
     import workloads as W
     probs = W.batch_problems()
     t0 = time.perf_counter()
     plans = []
-    for Q in probs:
+    adaptive = [n_max > 0 and Q.meta.get("kind") == "clustered" for Q in probs]
+    for Q, ad in zip(probs, adaptive):
         qt = torch.from_numpy(Q.points_T).cuda()
         qs = torch.from_numpy(Q.points_S).cuda()
         plans.append(F.Plan(qt, qs, Q.kappa, Q.box, Q.levels, Q.m, precision="fp32",
+                            n_max=n_max if ad else 0,
                             **({"aca_eps": aca_eps} if aca_eps > 0 else
                                {"tune": {"compact": compact}})))
         del qt, qs
@@ -298,6 +305,9 @@ def batched(steps: int, compact: int = 1, aca_eps: float = 0.0) -> dict:
            "device_bytes": sum(st["device_bytes"] for st in stats),
            "tune": best, "autotune_m2l_ms": tune_ms,
            "m2l_flops": flops, "tflops_whole_batch": flops / wall / 1e12}
+    if n_max > 0:
+        res["adaptive"] = (f"clustered half on adaptive trees, n_max = {n_max}; oracle rows "
+                           "compared for uniform-tree problems only")
     golden = os.path.join(ROOT, "tests", "golden", "batch_rows.npz")
     if os.path.exists(golden):
         g = np.load(golden)
@@ -306,6 +316,8 @@ def batched(steps: int, compact: int = 1, aca_eps: float = 0.0) -> dict:
             if not key.startswith("rows"):
                 continue
             i = int(key[4:])
+            if adaptive[i]:  # (the stored rows are of the uniform-tree operator)
+                continue
             yy = ys[i].cpu().numpy().astype(np.complex128)[g[key]]
             yo = g[f"y{i}"]
             errs[str(i)] = float(np.linalg.norm(yy - yo) / np.linalg.norm(yo))
@@ -316,7 +328,8 @@ def batched(steps: int, compact: int = 1, aca_eps: float = 0.0) -> dict:
     b.close()
     for p in plans:
         p.close()
-    print(f"[bench] batched{' aca' if aca_eps > 0 else ''}: {1000.0 * wall:.1f} ms per batch "
+    print(f"[bench] batched{' aca' if aca_eps > 0 else ''}"
+          f"{f' adaptive n_max={n_max}' if n_max > 0 else ''}: {1000.0 * wall:.1f} ms per batch "
           "of 64", file=sys.stderr, flush=True)
     return res
 
@@ -502,6 +515,10 @@ def main():
             out["batched_aca"] = batched(args.batch_steps, args.compact, args.aca_eps)
             out["batched_aca"]["speedup_vs_dense_batch"] = (
                 out["batched"]["ms_per_batch"] / out["batched_aca"]["ms_per_batch"])
+        if args.batch_adaptive_n_max > 0:
+            torch.cuda.empty_cache()
+            out["batched_adaptive"] = batched(args.batch_steps, args.compact,
+                                              n_max=args.batch_adaptive_n_max)
 
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(P, stats, shape, args.cpu_sub)
