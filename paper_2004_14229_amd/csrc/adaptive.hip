@@ -106,6 +106,7 @@ __global__ void __launch_bounds__(kNearThreads) k_near_items(
           kernel_add(px, py, pz, sx[u], sy[u], sz[u], sv[u], kappa, ar, ai);
       __syncthreads();
     }
+    __syncthreads();  // the batch's prefix and starts are read up to here
   }
   sv[t] = make_double2(ar, ai);
   __syncthreads();
