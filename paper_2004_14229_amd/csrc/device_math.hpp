@@ -12,6 +12,9 @@ constexpr int kPerLane = (kMaxK + 63) / 64;      // coefficients per lane
 // and the coefficients each thread holds.
 constexpr int kXT = 256;
 constexpr int kPerXT = (kMaxK + kXT - 1) / kXT;
+// Dynamic LDS of the eight-children transfer kernels (k_m2m_oct, k_l2l_oct)
+// at most: m <= 7; m = 8 takes the child-by-child kernels.
+constexpr size_t kOctLds = 56 * 1024;
 
 __device__ __forceinline__ double2 cmul(double2 a, double2 b) {
   return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);

@@ -93,6 +93,141 @@ __global__ void __launch_bounds__(kXT) k_l2l(
   }
 }
 
+// One workgroup (kXT threads) per (parent box t, direction c' of the
+// children's level), the eight children together.  For each parent
+// direction c with dir_(l+1)(c) = c', the x pass of E_{t'} takes the
+// parent's local to its two x halves, the y pass those to the four (x, y)
+// quarters and the z pass to the eight children, each then multiplied by
+// its phase factors and added to the child's local: 14 one-dimensional
+// passes per parent and c instead of 24, and 3 barriers instead of 40.
+// The phase factors depend only on c and the child's octant bit per axis
+// and are formed once per workgroup.  The children's locals start from
+// their coupling results and stay with the thread that writes them.
+// Needs K <= 343 (m <= 6); dynamic LDS: 7 K complex values.
+constexpr int kL2lMaxC = 6;  // parent directions c per c' (6 on the level l_hf)
+constexpr int kPerXT8 = (8 * 343 + kXT - 1) / kXT;
+
+template <class GT>
+__global__ void __launch_bounds__(kXT) k_l2l_oct(
+    const double2* __restrict__ ploc, int nd, const uint32_t* __restrict__ key, int64_t nb,
+    const int32_t* __restrict__ grid1, int level, double3 h1,
+    const double* __restrict__ dirvec, const double* __restrict__ dirvec1, int nd1,
+    int l_hf, double kappa, Interp ip, const GT* g_m2l,
+    double2* loc1) {  // g_m2l may alias loc1 (read before write, same thread)
+  extern __shared__ double2 smem[];
+  __shared__ double2 ph[kL2lMaxC][3][2][kMaxM1];  // c, axis, octant bit, node
+  __shared__ double e1[2][kMaxM1][kMaxM1];         // E1[b][j][k]
+  __shared__ int32_t chs[8];
+  const int lane = threadIdx.x;
+  const int cp = blockIdx.y;  // c' on level l+1
+  const int m1 = ip.m1, m2 = m1 * m1, K = ip.K, Kp = ip.Kp;
+  double2* par = smem;          // [K]: the parent's local for c
+  double2* xh = smem + K;       // [2][K]: after the x pass
+  double2* yq = smem + 3 * K;   // [4][K]: after the y pass
+  const bool hf_child = level + 1 <= l_hf;
+  const int c_begin = hf_child ? 4 * cp : 0;
+  const int nc = hf_child ? 4 : nd;
+  for (int e = lane; e < nc * 6 * m1; e += kXT) {  // E~d_{t',c} per axis
+    const int ci = e / (6 * m1), d = (e / (2 * m1)) % 3, b = (e / m1) % 2, nu = e % m1;
+    const int c = c_begin + ci;
+    const double hd = d == 0 ? h1.x : d == 1 ? h1.y : h1.z;
+    const double r = 0.5 * hd * ip.node[nu];  // xi - m_{t'}
+    const double off = (b - 0.5) * hd;        // m_{t'} - m_t
+    double sn, cs;
+    phase_sincos(kappa * ((r + off) * dirvec[3 * c + d] - r * dirvec1[3 * cp + d]), sn, cs);
+    ph[ci][d][b][nu] = make_double2(cs, sn);
+  }
+  for (int e = lane; e < 2 * m2; e += kXT) {
+    const int b = e / m2, j = (e / m1) % m1, k = e % m1;
+    e1[b][j][k] = ip.E1[b][j][k];
+  }
+  for (int64_t t = blockIdx.x; t < nb; t += gridDim.x) {
+    __syncthreads();  // (tables; the previous box's reads of chs)
+    if (lane < 8) chs[lane] = grid1[(key[t] << 3) | lane];
+    __syncthreads();
+    double2 acc[kPerXT8];
+#pragma unroll
+    for (int i = 0; i < kPerXT8; ++i) {
+      const int e = lane + kXT * i;
+      acc[i] = make_double2(0.0, 0.0);
+      if (e < 8 * K) {
+        const int q = e / K, k = e - q * K;
+        const int32_t ch = chs[q];
+        if (ch >= 0) acc[i] = load_c(g_m2l, (int64_t(ch) * nd1 + cp) * Kp + k);
+      }
+    }
+    for (int ci = 0; ci < nc; ++ci) {
+      const double2* src = ploc + (t * nd + c_begin + ci) * int64_t(Kp);
+      for (int k = lane; k < K; k += kXT) par[k] = src[k];
+      __syncthreads();
+      for (int e = lane; e < 2 * K; e += kXT) {  // x pass (stride m1^2)
+        const int bx = e / K, ee = e - bx * K;
+        const int j = ee / m2, base = ee - j * m2;
+        double re = 0.0, im = 0.0;
+        for (int k = 0; k < m1; ++k) {
+          const double w = e1[bx][j][k];
+          re += w * par[base + k * m2].x;
+          im += w * par[base + k * m2].y;
+        }
+        xh[e] = make_double2(re, im);
+      }
+      __syncthreads();
+      for (int e = lane; e < 4 * K; e += kXT) {  // y pass (stride m1)
+        const int h = e / K, ee = e - h * K;     // h = 2 bx + by
+        const int j = (ee / m1) % m1, base = ee - j * m1;
+        const double2* x = xh + (h >> 1) * K + base;
+        double re = 0.0, im = 0.0;
+        for (int k = 0; k < m1; ++k) {
+          const double w = e1[h & 1][j][k];
+          re += w * x[k * m1].x;
+          im += w * x[k * m1].y;
+        }
+        yq[e] = make_double2(re, im);
+      }
+      __syncthreads();
+#pragma unroll
+      for (int i = 0; i < kPerXT8; ++i) {  // z pass (stride 1), phase, into the child
+        const int e = lane + kXT * i;
+        if (e < 8 * K) {
+          const int q = e / K, k = e - q * K;  // q = 4 bx + 2 by + bz
+          if (chs[q] >= 0) {
+            const int j = k % m1, base = k - j;
+            const double2* y = yq + (q >> 1) * K + base;
+            double re = 0.0, im = 0.0;
+            for (int kk = 0; kk < m1; ++kk) {
+              const double w = e1[q & 1][j][kk];
+              re += w * y[kk].x;
+              im += w * y[kk].y;
+            }
+            const int n1 = k / m2, n2 = (k / m1) % m1, n3 = k % m1;
+            const double2 f = cmul(cmul(ph[ci][0][q >> 2][n1], ph[ci][1][(q >> 1) & 1][n2]),
+                                   ph[ci][2][q & 1][n3]);
+            const double2 v = cmul(f, make_double2(re, im));
+            acc[i].x += v.x;
+            acc[i].y += v.y;
+          }
+        }
+      }
+      // (the next direction's load writes par only; xh and yq are rewritten
+      // after the barrier that follows it)
+    }
+#pragma unroll
+    for (int i = 0; i < kPerXT8; ++i) {
+      const int e = lane + kXT * i;
+      if (e < 8 * K) {
+        const int q = e / K, k = e - q * K;
+        const int32_t ch = chs[q];
+        if (ch >= 0) loc1[(int64_t(ch) * nd1 + cp) * Kp + k] = acc[i];
+      }
+    }
+    for (int e = lane; e < 8 * (Kp - K); e += kXT) {  // zero padding
+      const int q = e / (Kp - K), k = K + e % (Kp - K);
+      const int32_t ch = chs[q];
+      if (ch >= 0) loc1[(int64_t(ch) * nd1 + cp) * Kp + k] = make_double2(0.0, 0.0);
+    }
+  }
+}
+
 // One wave per leaf box: every point of the box, every direction.
 __global__ void __launch_bounds__(64) k_l2t(
     const double* __restrict__ x, const double* __restrict__ y,
@@ -175,6 +310,19 @@ void launch_l2l(Plan& P, int level, hipStream_t s) {
   LevelData& L1 = P.L[level + 1];
   const int64_t nb1 = P.T.nb[level + 1];
   if (nb1 == 0) return;
+  const int nc = level + 1 <= P.l_hf ? 4 : Lc.nd;  // parent directions per c'
+  const size_t lds = size_t(7) * P.ip.K * sizeof(double2);
+  if (P.ip.K <= 343 && lds <= kOctLds && nc <= kL2lMaxC) {  // the eight children together
+    const int64_t nb = P.T.nb[level];
+    dim3 grid(static_cast<unsigned>(std::min<int64_t>(nb, 1 << 20)), L1.nd);
+    k_l2l_oct<double2><<<grid, kXT, lds, s>>>(
+        reinterpret_cast<const double2*>(Lc.loc64.get()), Lc.nd, P.T.key[level].get(), nb,
+        P.T.grid[level + 1].get(), level, L1.hv(), Lc.dirvec.get(), L1.dirvec.get(), L1.nd,
+        P.l_hf, P.kappa, P.ip, reinterpret_cast<const double2*>(L1.loc64.get()),
+        reinterpret_cast<double2*>(L1.loc64.get()));
+    FDM_LAUNCH("k_l2l_oct");
+    return;
+  }
   dim3 grid(static_cast<unsigned>(std::min<int64_t>(nb1, 1 << 20)), L1.nd);
   k_l2l<double2><<<grid, kXT, 0, s>>>(
       reinterpret_cast<const double2*>(Lc.loc64.get()), Lc.nd, P.T.grid[level].get(),

@@ -216,6 +216,116 @@ __global__ void __launch_bounds__(kXT) k_m2m(
   }
 }
 
+// One workgroup (kXT threads) per (parent box, direction), the eight
+// children together.  E_{s'}^T is a product of three 1D passes of which
+// only the z pass depends on the child's z bit, so for each x half bx the z
+// pass takes the four children (by, bz) straight to two sums over bz, the
+// y pass those to one sum over by, and the x pass adds it to the result:
+// 14 one-dimensional passes per parent instead of 24, and 8 barriers
+// instead of 40.  The per-axis phase factors depend only on the child's
+// octant bit along that axis, so they are formed once per workgroup.
+// Dynamic LDS: 6 K complex values.
+__global__ void __launch_bounds__(kXT) k_m2m_oct(
+    const double2* __restrict__ child_mom, int nd1, const int32_t* __restrict__ grid1,
+    const uint32_t* __restrict__ key, int64_t nb, int level, double3 h1,
+    const double* __restrict__ dirvec, const double* __restrict__ dirvec1, int nd,
+    int l_hf, double kappa, Interp ip, double2* __restrict__ mom,
+    float2* __restrict__ mom32, uint16_t* __restrict__ mom16) {
+  extern __shared__ double2 smem[];
+  __shared__ double2 ph[3][2][kMaxM1];      // axis, octant bit, node
+  __shared__ double e1[2][kMaxM1][kMaxM1];  // E1[b][k][j]
+  __shared__ int32_t chs[8];
+  const int lane = threadIdx.x;
+  const int c = blockIdx.y;
+  const int m1 = ip.m1, m2 = m1 * m1, K = ip.K, Kp = ip.Kp;
+  double2* in = smem;           // [4][K]: the half's children (by, bz), phased
+  double2* mid = smem + 4 * K;  // [2][K]: z pass, summed over bz
+  double2* yx = smem;           // [K]: y pass, summed over by (in is read by then)
+  const int cp = (level + 1 <= l_hf) ? (c >> 2) : 0;  // c' = dir_(l+1)(c)
+  if (lane < 6 * m1) {  // conj(E~d) per axis: exp(-i kappa ((xi-m_s) c - (xi-m_s') c'))
+    const int d = lane / (2 * m1), b = (lane / m1) % 2, nu = lane % m1;
+    const double hd = d == 0 ? h1.x : d == 1 ? h1.y : h1.z;
+    const double r = 0.5 * hd * ip.node[nu];  // xi - m_{s'}
+    const double off = (b - 0.5) * hd;        // m_{s'} - m_s
+    double sn, cs;
+    phase_sincos(-kappa * ((r + off) * dirvec[3 * c + d] - r * dirvec1[3 * cp + d]), sn, cs);
+    ph[d][b][nu] = make_double2(cs, sn);
+  }
+  for (int e = lane; e < 2 * m2; e += kXT) {
+    const int b = e / m2, k = (e / m1) % m1, j = e % m1;
+    e1[b][k][j] = ip.E1[b][k][j];
+  }
+  for (int64_t b = blockIdx.x; b < nb; b += gridDim.x) {
+    __syncthreads();  // (tables; the previous box's reads of chs)
+    if (lane < 8) chs[lane] = grid1[(key[b] << 3) | lane];
+    __syncthreads();
+    double2 acc[kPerXT];
+    for (int i = 0; i < kPerXT; ++i) acc[i] = make_double2(0.0, 0.0);
+    for (int bx = 0; bx < 2; ++bx) {
+      if (max(max(chs[4 * bx], chs[4 * bx + 1]), max(chs[4 * bx + 2], chs[4 * bx + 3])) < 0)
+        continue;  // no child in this half (the same for the whole workgroup)
+      for (int e = lane; e < 4 * K; e += kXT) {
+        const int i = e / K, k = e - i * K;  // i = 2 by + bz
+        const int32_t ch = chs[4 * bx + i];
+        double2 v = make_double2(0.0, 0.0);
+        if (ch >= 0) {
+          const int n1 = k / m2, n2 = (k / m1) % m1, n3 = k % m1;
+          const double2 f = cmul(cmul(ph[0][bx][n1], ph[1][i >> 1][n2]), ph[2][i & 1][n3]);
+          v = cmul(f, child_mom[(int64_t(ch) * nd1 + cp) * Kp + k]);
+        }
+        in[e] = v;
+      }
+      __syncthreads();
+      for (int e = lane; e < 2 * K; e += kXT) {  // z pass (stride 1)
+        const int by = e / K, ee = e - by * K;
+        const int j = ee % m1, base = ee - j;
+        double re = 0.0, im = 0.0;
+        for (int bz = 0; bz < 2; ++bz) {
+          const double2* src = in + (2 * by + bz) * K + base;
+          for (int k = 0; k < m1; ++k) {
+            const double w = e1[bz][k][j];
+            re += w * src[k].x;
+            im += w * src[k].y;
+          }
+        }
+        mid[e] = make_double2(re, im);
+      }
+      __syncthreads();
+      for (int e = lane; e < K; e += kXT) {  // y pass (stride m1)
+        const int j = (e / m1) % m1, base = e - j * m1;
+        double re = 0.0, im = 0.0;
+        for (int by = 0; by < 2; ++by) {
+          const double2* src = mid + by * K + base;
+          for (int k = 0; k < m1; ++k) {
+            const double w = e1[by][k][j];
+            re += w * src[k * m1].x;
+            im += w * src[k * m1].y;
+          }
+        }
+        yx[e] = make_double2(re, im);
+      }
+      __syncthreads();
+#pragma unroll
+      for (int i = 0; i < kPerXT; ++i) {  // x pass (stride m1^2) into the result
+        const int e = lane + kXT * i;
+        if (e < K) {
+          const int j = e / m2, base = e - j * m2;
+          double re = 0.0, im = 0.0;
+          for (int k = 0; k < m1; ++k) {
+            const double w = e1[bx][k][j];
+            re += w * yx[base + k * m2].x;
+            im += w * yx[base + k * m2].y;
+          }
+          acc[i].x += re;
+          acc[i].y += im;
+        }
+      }
+      __syncthreads();  // (yx and in are overwritten by the next half)
+    }
+    store_coeffs<kXT>(acc, mom, mom32, mom16, (b * nd + c) * int64_t(Kp), K, Kp, lane);
+  }
+}
+
 }  // namespace
 
 void launch_permute_in(const double* v_user, const int32_t* perm, int64_t n,
@@ -274,6 +384,16 @@ void launch_m2m(Plan& P, int level, hipStream_t s) {
   const int64_t nb = P.S.nb[level];
   if (nb == 0) return;
   dim3 grid(static_cast<unsigned>(std::min<int64_t>(nb, 1 << 20)), Lc.nd);
+  const size_t lds = size_t(6) * P.ip.K * sizeof(double2);
+  if (lds <= kOctLds) {  // the eight children together (m <= 7)
+    k_m2m_oct<<<grid, kXT, lds, s>>>(
+        reinterpret_cast<const double2*>(L1.mom64.get()), L1.nd, P.S.grid[level + 1].get(),
+        P.S.key[level].get(), nb, level, L1.hv(), Lc.dirvec.get(), L1.dirvec.get(), Lc.nd,
+        P.l_hf, P.kappa, P.ip, reinterpret_cast<double2*>(Lc.mom64.get()),
+        reinterpret_cast<float2*>(Lc.mom32.get()), Lc.mom16.get());
+    FDM_LAUNCH("k_m2m_oct");
+    return;
+  }
   k_m2m<<<grid, kXT, 0, s>>>(reinterpret_cast<const double2*>(L1.mom64.get()), L1.nd,
                             P.S.grid[level + 1].get(), P.S.key[level].get(), nb, level,
                             L1.hv(), Lc.dirvec.get(), L1.dirvec.get(), Lc.nd, P.l_hf,
