@@ -229,6 +229,8 @@ __global__ void __launch_bounds__(kXT) k_l2l_oct(
 }
 
 // One wave per leaf box: every point of the box, every direction.
+// NPER: coefficients per lane, ceil(K / 64) (registers scale with it).
+template <int NPER>
 __global__ void __launch_bounds__(64) k_l2t(
     const double* __restrict__ x, const double* __restrict__ y,
     const double* __restrict__ z, const uint32_t* __restrict__ key,
@@ -248,6 +250,16 @@ __global__ void __launch_bounds__(64) k_l2t(
                  mz = lo2 + (iz + 0.5) * h.z;
     const double inv_half[3] = {2.0 / h.x, 2.0 / h.y, 2.0 / h.z};
     const int p0 = start[b], pn = count[b];
+    // one direction (every level below the high-frequency ones): the box's
+    // local is read once, before the first point's barriers
+    double2 g0[NPER];
+    if (nd == 1) {
+#pragma unroll
+      for (int i = 0; i < NPER; ++i) {
+        const int k = lane + 64 * i;
+        g0[i] = k < K ? loc[b * int64_t(Kp) + k] : make_double2(0.0, 0.0);
+      }
+    }
     for (int pi = 0; pi < pn; ++pi) {
       const int64_t j = p0 + pi;
       const double dx = x[j] - mx, dy = y[j] - my, dz = z[j] - mz;
@@ -263,12 +275,12 @@ __global__ void __launch_bounds__(64) k_l2t(
         const double2* g = loc + (b * nd + c) * int64_t(Kp);
         double sr = 0.0, si = 0.0;
 #pragma unroll
-        for (int i = 0; i < kPerLane; ++i) {
+        for (int i = 0; i < NPER; ++i) {
           const int k = lane + 64 * i;
           if (k < K) {
             const int n3 = k % m1, n2 = (k / m1) % m1, n1 = k / (m1 * m1);
             const double L = lag[0][n1] * lag[1][n2] * lag[2][n3];
-            const double2 gv = g[k];
+            const double2 gv = nd == 1 ? g0[i] : g[k];
             sr += L * gv.x;
             si += L * gv.y;
           }
@@ -336,7 +348,14 @@ void launch_l2t_boxes(Plan& P, int level, const int32_t* boxes, int64_t nb, hipS
   if (P.nT == 0 || nb == 0) return;
   if (level < P.l_min) return;  // no coupling on or above it: the far field is zero
   LevelData& Lp = P.L[level];
-  k_l2t<<<static_cast<unsigned>(std::min<int64_t>(nb, 1 << 20)), 64, 0, s>>>(
+  const int nper = (P.ip.K + 63) / 64;
+  auto kernel = nper <= 1   ? k_l2t<1>
+                : nper <= 2 ? k_l2t<2>
+                : nper <= 4 ? k_l2t<4>
+                : nper <= 6 ? k_l2t<6>
+                : nper <= 8 ? k_l2t<8>
+                            : k_l2t<kPerLane>;
+  kernel<<<static_cast<unsigned>(std::min<int64_t>(nb, 1 << 20)), 64, 0, s>>>(
       P.T.x.get(), P.T.y.get(), P.T.z.get(), P.T.key[level].get(), P.T.start[level].get(),
       P.T.count[level].get(), boxes, nb, level, P.lo[0], P.lo[1], P.lo[2], Lp.hv(),
       Lp.dirvec.get(), Lp.nd, P.kappa, P.ip, reinterpret_cast<const double2*>(Lp.loc64.get()),

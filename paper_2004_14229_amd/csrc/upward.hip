@@ -39,7 +39,7 @@ __device__ __forceinline__ void split3_bits(double x, uint16_t& h, uint16_t& m, 
 // if requested, as the FP32 operand copy or as the split BF16 operand copy
 // (per slab of 16 coefficients, six planes of 16: re hi, mid, lo, im hi,
 // mid, lo); thread `lane` of T holds coefficients lane + T i.
-template <int T, int NPER>
+template <int T, int NPER, bool X6 = true>  // X6: out16 may be set
 __device__ __forceinline__ void store_coeffs(const double2 (&acc)[NPER],
                                              double2* __restrict__ out64,
                                              float2* __restrict__ out32,
@@ -53,7 +53,7 @@ __device__ __forceinline__ void store_coeffs(const double2 (&acc)[NPER],
                                               : make_double2(0.0, 0.0);
       out64[base + k] = val;
       if (out32) out32[base + k] = make_float2(float(val.x), float(val.y));
-      if (out16) {
+      if (X6 && out16) {
         uint16_t* d = out16 + 6 * base + 96 * (k / 16) + k % 16;
         uint16_t h, m, l;
         split3_bits(val.x, h, m, l);
@@ -104,7 +104,11 @@ __global__ void k_permute_out_c64(const double2* __restrict__ y_tree,
 }
 
 // One wave per (leaf box, direction); boxes: the listed boxes of the level
-// (adaptive trees), or NULL for boxes 0 .. nb-1.
+// (adaptive trees), or NULL for boxes 0 .. nb-1.  X6: the plan keeps the
+// split BF16 moment copy (mom16), else mom16 is NULL and its code is left
+// out (fewer registers, more waves in flight for the stores).
+// NPER: coefficients per lane, ceil(K / 64) (registers scale with it).
+template <bool X6, int NPER>
 __global__ void __launch_bounds__(64) k_s2m(
     const double* __restrict__ x, const double* __restrict__ y,
     const double* __restrict__ z, const double2* __restrict__ v,
@@ -126,8 +130,8 @@ __global__ void __launch_bounds__(64) k_s2m(
     const double mx = lo0 + (ix + 0.5) * h.x, my = lo1 + (iy + 0.5) * h.y,
                  mz = lo2 + (iz + 0.5) * h.z;
     const double inv_half[3] = {2.0 / h.x, 2.0 / h.y, 2.0 / h.z};
-    double2 acc[kPerLane];
-    for (int i = 0; i < kPerLane; ++i) acc[i] = make_double2(0.0, 0.0);
+    double2 acc[NPER];
+    for (int i = 0; i < NPER; ++i) acc[i] = make_double2(0.0, 0.0);
     const int p0 = start[b], pn = count[b];
     for (int pi = 0; pi < pn; ++pi) {
       const int64_t j = p0 + pi;
@@ -144,7 +148,7 @@ __global__ void __launch_bounds__(64) k_s2m(
       const double2 vj = v[j];
       const double wr = vj.x * cs - vj.y * sn, wi = vj.x * sn + vj.y * cs;
 #pragma unroll
-      for (int i = 0; i < kPerLane; ++i) {
+      for (int i = 0; i < NPER; ++i) {
         const int mu = lane + 64 * i;
         if (mu < K) {
           const int n3 = mu % m1, n2 = (mu / m1) % m1, n1 = mu / (m1 * m1);
@@ -154,7 +158,8 @@ __global__ void __launch_bounds__(64) k_s2m(
         }
       }
     }
-    store_coeffs<64>(acc, mom, mom32, mom16, (b * nd + c) * int64_t(Kp), K, Kp, lane);
+    store_coeffs<64, NPER, X6>(acc, mom, mom32, mom16, (b * nd + c) * int64_t(Kp), K, Kp,
+                                   lane);
   }
 }
 
@@ -364,13 +369,24 @@ void launch_s2m_boxes(Plan& P, int level, const int32_t* boxes, int64_t nb, hipS
   LevelData& Lp = P.L[level];
   if (nb == 0) return;
   dim3 grid(static_cast<unsigned>(std::min<int64_t>(nb, 1 << 20)), Lp.nd);
-  k_s2m<<<grid, 64, 0, s>>>(P.S.x.get(), P.S.y.get(), P.S.z.get(),
-                            reinterpret_cast<const double2*>(P.vtree()),
-                            P.S.key[level].get(), P.S.start[level].get(),
-                            P.S.count[level].get(), boxes, nb, level, P.lo[0], P.lo[1],
-                            P.lo[2], Lp.hv(), Lp.dirvec.get(), Lp.nd, P.kappa, P.ip,
-                            reinterpret_cast<double2*>(Lp.mom64.get()),
-                            reinterpret_cast<float2*>(Lp.mom32.get()), Lp.mom16.get());
+  auto pick = [&](auto nper) {
+    constexpr int N = decltype(nper)::value;
+    return Lp.mom16.get() ? k_s2m<true, N> : k_s2m<false, N>;
+  };
+  const int nper = (P.ip.K + 63) / 64;
+  auto kernel = nper <= 1   ? pick(std::integral_constant<int, 1>{})
+                : nper <= 2 ? pick(std::integral_constant<int, 2>{})
+                : nper <= 4 ? pick(std::integral_constant<int, 4>{})
+                : nper <= 6 ? pick(std::integral_constant<int, 6>{})
+                : nper <= 8 ? pick(std::integral_constant<int, 8>{})
+                            : pick(std::integral_constant<int, kPerLane>{});
+  kernel<<<grid, 64, 0, s>>>(P.S.x.get(), P.S.y.get(), P.S.z.get(),
+                             reinterpret_cast<const double2*>(P.vtree()),
+                             P.S.key[level].get(), P.S.start[level].get(),
+                             P.S.count[level].get(), boxes, nb, level, P.lo[0], P.lo[1],
+                             P.lo[2], Lp.hv(), Lp.dirvec.get(), Lp.nd, P.kappa, P.ip,
+                             reinterpret_cast<double2*>(Lp.mom64.get()),
+                             reinterpret_cast<float2*>(Lp.mom32.get()), Lp.mom16.get());
   FDM_LAUNCH("k_s2m");
 }
 
