@@ -94,18 +94,19 @@ __global__ void __launch_bounds__(kXT) k_l2l(
 }
 
 // One workgroup (kXT threads) per (parent box t, direction c' of the
-// children's level), the eight children together.  For each parent
-// direction c with dir_(l+1)(c) = c', the x pass of E_{t'} takes the
-// parent's local to its two x halves, the y pass those to the four (x, y)
-// quarters and the z pass to the eight children, each then multiplied by
-// its phase factors and added to the child's local: 14 one-dimensional
-// passes per parent and c instead of 24, and 3 barriers instead of 40.
-// The phase factors depend only on c and the child's octant bit per axis
-// and are formed once per workgroup.  The children's locals start from
-// their coupling results and stay with the thread that writes them.
-// Needs K <= 343 (m <= 6); dynamic LDS: 7 K complex values.
+// children's level, x half bx), the four children of that half together.
+// For each parent direction c with dir_(l+1)(c) = c', the x pass of E_{t'}
+// takes the parent's local to its bx half, the y pass that to the two
+// (bx, by) quarters and the z pass to the four children, each then
+// multiplied by its phase factors and added to the child's local: 7
+// one-dimensional passes per workgroup and c (14 per parent, against 24
+// child by child) and 3 barriers.  The phase factors depend only on c and
+// the child's octant bit per axis and are formed once per workgroup.  The
+// children's locals start from their coupling results and stay with the
+// thread that writes them.  Needs K <= 512 (m <= 7); dynamic LDS: 4 K
+// complex values.
 constexpr int kL2lMaxC = 6;  // parent directions c per c' (6 on the level l_hf)
-constexpr int kPerXT8 = (8 * 343 + kXT - 1) / kXT;
+constexpr int kPerXT4 = (4 * 512 + kXT - 1) / kXT;
 
 template <class GT>
 __global__ void __launch_bounds__(kXT) k_l2l_oct(
@@ -117,13 +118,14 @@ __global__ void __launch_bounds__(kXT) k_l2l_oct(
   extern __shared__ double2 smem[];
   __shared__ double2 ph[kL2lMaxC][3][2][kMaxM1];  // c, axis, octant bit, node
   __shared__ double e1[2][kMaxM1][kMaxM1];         // E1[b][j][k]
-  __shared__ int32_t chs[8];
+  __shared__ int32_t chs[4];
   const int lane = threadIdx.x;
   const int cp = blockIdx.y;  // c' on level l+1
+  const int bx = blockIdx.z;  // the children's x bit
   const int m1 = ip.m1, m2 = m1 * m1, K = ip.K, Kp = ip.Kp;
-  double2* par = smem;          // [K]: the parent's local for c
-  double2* xh = smem + K;       // [2][K]: after the x pass
-  double2* yq = smem + 3 * K;   // [4][K]: after the y pass
+  double2* par = smem;         // [K]: the parent's local for c
+  double2* xh = smem + K;      // [K]: after the x pass (half bx)
+  double2* yq = smem + 2 * K;  // [2][K]: after the y pass (by)
   const bool hf_child = level + 1 <= l_hf;
   const int c_begin = hf_child ? 4 * cp : 0;
   const int nc = hf_child ? 4 : nd;
@@ -143,15 +145,16 @@ __global__ void __launch_bounds__(kXT) k_l2l_oct(
   }
   for (int64_t t = blockIdx.x; t < nb; t += gridDim.x) {
     __syncthreads();  // (tables; the previous box's reads of chs)
-    if (lane < 8) chs[lane] = grid1[(key[t] << 3) | lane];
+    if (lane < 4) chs[lane] = grid1[(key[t] << 3) | (4 * bx + lane)];
     __syncthreads();
-    double2 acc[kPerXT8];
+    if (max(max(chs[0], chs[1]), max(chs[2], chs[3])) < 0) continue;  // no child here
+    double2 acc[kPerXT4];
 #pragma unroll
-    for (int i = 0; i < kPerXT8; ++i) {
+    for (int i = 0; i < kPerXT4; ++i) {
       const int e = lane + kXT * i;
       acc[i] = make_double2(0.0, 0.0);
-      if (e < 8 * K) {
-        const int q = e / K, k = e - q * K;
+      if (e < 4 * K) {
+        const int q = e / K, k = e - q * K;  // q = 2 by + bz
         const int32_t ch = chs[q];
         if (ch >= 0) acc[i] = load_c(g_m2l, (int64_t(ch) * nd1 + cp) * Kp + k);
       }
@@ -160,9 +163,8 @@ __global__ void __launch_bounds__(kXT) k_l2l_oct(
       const double2* src = ploc + (t * nd + c_begin + ci) * int64_t(Kp);
       for (int k = lane; k < K; k += kXT) par[k] = src[k];
       __syncthreads();
-      for (int e = lane; e < 2 * K; e += kXT) {  // x pass (stride m1^2)
-        const int bx = e / K, ee = e - bx * K;
-        const int j = ee / m2, base = ee - j * m2;
+      for (int e = lane; e < K; e += kXT) {  // x pass (stride m1^2), half bx
+        const int j = e / m2, base = e - j * m2;
         double re = 0.0, im = 0.0;
         for (int k = 0; k < m1; ++k) {
           const double w = e1[bx][j][k];
@@ -172,24 +174,23 @@ __global__ void __launch_bounds__(kXT) k_l2l_oct(
         xh[e] = make_double2(re, im);
       }
       __syncthreads();
-      for (int e = lane; e < 4 * K; e += kXT) {  // y pass (stride m1)
-        const int h = e / K, ee = e - h * K;     // h = 2 bx + by
+      for (int e = lane; e < 2 * K; e += kXT) {  // y pass (stride m1)
+        const int by = e / K, ee = e - by * K;
         const int j = (ee / m1) % m1, base = ee - j * m1;
-        const double2* x = xh + (h >> 1) * K + base;
         double re = 0.0, im = 0.0;
         for (int k = 0; k < m1; ++k) {
-          const double w = e1[h & 1][j][k];
-          re += w * x[k * m1].x;
-          im += w * x[k * m1].y;
+          const double w = e1[by][j][k];
+          re += w * xh[base + k * m1].x;
+          im += w * xh[base + k * m1].y;
         }
         yq[e] = make_double2(re, im);
       }
       __syncthreads();
 #pragma unroll
-      for (int i = 0; i < kPerXT8; ++i) {  // z pass (stride 1), phase, into the child
+      for (int i = 0; i < kPerXT4; ++i) {  // z pass (stride 1), phase, into the child
         const int e = lane + kXT * i;
-        if (e < 8 * K) {
-          const int q = e / K, k = e - q * K;  // q = 4 bx + 2 by + bz
+        if (e < 4 * K) {
+          const int q = e / K, k = e - q * K;  // q = 2 by + bz
           if (chs[q] >= 0) {
             const int j = k % m1, base = k - j;
             const double2* y = yq + (q >> 1) * K + base;
@@ -200,7 +201,7 @@ __global__ void __launch_bounds__(kXT) k_l2l_oct(
               im += w * y[kk].y;
             }
             const int n1 = k / m2, n2 = (k / m1) % m1, n3 = k % m1;
-            const double2 f = cmul(cmul(ph[ci][0][q >> 2][n1], ph[ci][1][(q >> 1) & 1][n2]),
+            const double2 f = cmul(cmul(ph[ci][0][bx][n1], ph[ci][1][q >> 1][n2]),
                                    ph[ci][2][q & 1][n3]);
             const double2 v = cmul(f, make_double2(re, im));
             acc[i].x += v.x;
@@ -212,15 +213,15 @@ __global__ void __launch_bounds__(kXT) k_l2l_oct(
       // after the barrier that follows it)
     }
 #pragma unroll
-    for (int i = 0; i < kPerXT8; ++i) {
+    for (int i = 0; i < kPerXT4; ++i) {
       const int e = lane + kXT * i;
-      if (e < 8 * K) {
+      if (e < 4 * K) {
         const int q = e / K, k = e - q * K;
         const int32_t ch = chs[q];
         if (ch >= 0) loc1[(int64_t(ch) * nd1 + cp) * Kp + k] = acc[i];
       }
     }
-    for (int e = lane; e < 8 * (Kp - K); e += kXT) {  // zero padding
+    for (int e = lane; e < 4 * (Kp - K); e += kXT) {  // zero padding
       const int q = e / (Kp - K), k = K + e % (Kp - K);
       const int32_t ch = chs[q];
       if (ch >= 0) loc1[(int64_t(ch) * nd1 + cp) * Kp + k] = make_double2(0.0, 0.0);
@@ -323,10 +324,10 @@ void launch_l2l(Plan& P, int level, hipStream_t s) {
   const int64_t nb1 = P.T.nb[level + 1];
   if (nb1 == 0) return;
   const int nc = level + 1 <= P.l_hf ? 4 : Lc.nd;  // parent directions per c'
-  const size_t lds = size_t(7) * P.ip.K * sizeof(double2);
-  if (P.ip.K <= 343 && lds <= kOctLds && nc <= kL2lMaxC) {  // the eight children together
+  const size_t lds = size_t(4) * P.ip.K * sizeof(double2);
+  if (P.ip.K <= 512 && lds <= kOctLds && nc <= kL2lMaxC) {  // four children together
     const int64_t nb = P.T.nb[level];
-    dim3 grid(static_cast<unsigned>(std::min<int64_t>(nb, 1 << 20)), L1.nd);
+    dim3 grid(static_cast<unsigned>(std::min<int64_t>(nb, 1 << 20)), L1.nd, 2);
     k_l2l_oct<double2><<<grid, kXT, lds, s>>>(
         reinterpret_cast<const double2*>(Lc.loc64.get()), Lc.nd, P.T.key[level].get(), nb,
         P.T.grid[level + 1].get(), level, L1.hv(), Lc.dirvec.get(), L1.dirvec.get(), L1.nd,
