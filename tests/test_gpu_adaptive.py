@@ -134,3 +134,33 @@ def test_batch_of_adaptive_and_uniform_plans():
             p.close()
     assert_close(y1, oracle.matvec(oracle_plan(P1, n1), P1.v), 1e-6)
     assert_close(y2, oracle.matvec(oracle_plan(P2, None), P2.v), 1e-6)
+
+
+def test_near_field_items_span_chunks_and_range_batches():
+    """A clump of 1500 targets inside one box of level 3 against sparse
+    uniform sources, whose level-3 boxes are leaves (n_max = 8): that target
+    box meets 418 source leaves at its level's inadmissible offsets.  Its
+    near-field work is six items of at most 256 points, each with two
+    batches of at most 256 source ranges (the layout of the adaptive
+    near-field kernel).  Structure bit for bit, FP64 and FP32 against the
+    oracle."""
+    from test_gpu_parity import check_structure
+    rng = np.random.default_rng(505)
+    PT = 0.26 + 0.1 * rng.random((1500, 3))
+    PS = W.unit_cube_points(rng, 2000)
+    P = W.Problem("clump_vs_sparse", PT, PS, W.complex_normal(rng, 2000), 60.0,
+                  (0.0, 0.0, 0.0, 1.0, 1.0, 1.0), 5, 3)
+    n_max = 8
+    op = oracle_plan(P, n_max)
+    nt = op.BT.near_t[3]
+    per_box = np.bincount(nt, minlength=len(op.TT.count[3]))
+    b = int(np.argmax(per_box))
+    assert per_box[b] > 256 and op.TT.count[3][b] > 256  # several items, several batches
+    yo = oracle.matvec(op, P.v)
+    with plan(P, n_max, "fp64") as gp:
+        check_structure(P, gp, op)
+        y64 = matvec(gp, P)
+    assert_close(y64, yo, 1e-12, "fp64")
+    with plan(P, n_max, "fp32") as gp:
+        y32 = matvec(gp, P)
+    assert_close(y32, yo, 1e-6, "fp32")
