@@ -258,9 +258,11 @@ int fdm_plan_matvec_c64(fdm_plan* plan, const void* v, void* y, void* stream);
 /*
  * fdm_plan_matvec_multi -- Y = A~ V for nrhs right-hand sides (repeated
  * application of one operator, Sect. 4): the plan's trees, work lists and
- * coupling bank serve every vector, and the near field evaluates each kernel
- * value once for up to four vectors.  Each result equals fdm_plan_matvec's
- * on the same vector bit for bit.  Asynchronous on `stream`.
+ * coupling bank serve every vector.  On uniform trees whose near field runs
+ * apart from the coupling queue, the near field evaluates each kernel value
+ * once for up to four vectors; otherwise (adaptive trees, near field queued)
+ * it runs vector by vector.  Each result equals fdm_plan_matvec's on the
+ * same vector bit for bit.  Asynchronous on `stream`.
  *
  *  V     device, nrhs vectors of n_S complex values one after the other
  *        (complex64 when c64 = 1, else complex128); not modified.
