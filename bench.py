@@ -279,7 +279,9 @@ def batched(steps: int, compact: int = 1, aca_eps: float = 0.0, n_max: int = 0) 
     torch.cuda.synchronize()
     stream = torch.cuda.Stream()
     with torch.cuda.stream(stream):
-        best, tune_ms, ys = b.autotune(vs, max_candidates=4, stream=stream)
+        # launch shapes, then (dense couplings) the two other compaction modes
+        best, tune_ms, ys = b.autotune(vs, max_candidates=4 if aca_eps > 0 else 6,
+                                       stream=stream)
         b.matvec(vs, ys, stream=stream)  # graph capture + first replay
     stream.synchronize()
     t1 = time.perf_counter()

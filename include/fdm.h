@@ -226,11 +226,14 @@ int fdm_plan_set_tune(fdm_plan* plan, const fdm_tune* tune, void* stream);
 /*
  * fdm_plan_autotune -- time the coupling step under each candidate launch
  * shape (nb in {64, 32} x persistent in {1, 0} x lpt in {1, 0}, near field
- * and compaction kept as set) on the plan's own data and keep the fastest.  Runs one full
- * matvec of v into y first (same arguments as fdm_plan_matvec{,_c64}), then
- * one coupling step per candidate, and synchronises stream.
- *  max_candidates  how many of the 8 candidates to try, in the order above
- *                  (1..8).
+ * and compaction kept as set; then, for FP32 and BF16 split plans without
+ * low-rank couplings, the two other compaction modes at nb 64, persistent,
+ * heaviest first) on the plan's own data and keep the fastest.  Runs one
+ * full matvec of v into y first (same arguments as
+ * fdm_plan_matvec{,_c64}), then one coupling step per candidate, and
+ * synchronises stream.
+ *  max_candidates  how many of the candidates to try, in the order above
+ *                  (1..8, or 1..10 where the compaction modes are added).
  *  best            host, receives the chosen shape (may be NULL).
  *  ms              host array of max_candidates doubles receiving each
  *                  candidate's coupling-step time (may be NULL).
@@ -459,7 +462,8 @@ int fdm_batch_set_tune(fdm_batch* batch, const fdm_tune* tune, void* stream);
  * fdm_batch_autotune -- as fdm_plan_autotune for the batch's coupling
  * launches: one batched matvec, then one timed coupling step per candidate
  * (nb in {64, 32} x lpt in {1, 0}; persistent launches with the near field
- * queued), keeping the fastest.
+ * queued; then, as for a plan, the two other compaction modes: 1..4, or
+ * 1..6 candidates), keeping the fastest.
  */
 int fdm_batch_autotune(fdm_batch* batch, const void* const* v, void* const* y,
                        int c64, int max_candidates, void* stream,

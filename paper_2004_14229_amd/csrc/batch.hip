@@ -125,7 +125,11 @@ double time_on_stream(hipStream_t s, F&& f) {
   return ms;
 }
 
-std::vector<TuneConfig> candidates(bool persistent_only, int p2p_in_queue, int compact) {
+// Launch shapes: nb x persistent x lpt with the near field and compaction
+// as set; then, where the precision has compacted items (compactable), the
+// other two compaction modes at (64, persistent, heaviest first).
+std::vector<TuneConfig> candidates(bool persistent_only, int p2p_in_queue, int compact,
+                                   bool compactable) {
   std::vector<TuneConfig> out;
   for (int nb : {64, 32})
     for (int pers : {1, 0}) {
@@ -139,6 +143,17 @@ std::vector<TuneConfig> candidates(bool persistent_only, int p2p_in_queue, int c
         c.compact = compact;
         out.push_back(c);
       }
+    }
+  if (compactable)
+    for (int mode : {0, 1, 2}) {
+      if (mode == compact) continue;
+      TuneConfig c;
+      c.nb = 64;
+      c.persistent = 1;
+      c.lpt = 1;
+      c.p2p_in_queue = p2p_in_queue;
+      c.compact = mode;
+      out.push_back(c);
     }
   return out;
 }
@@ -157,7 +172,8 @@ int fdm_plan_autotune(fdm_plan* plan, const void* v, void* y, int c64, int max_c
     if (!plan) fail(FDM_ERR_INVALID_ARG, "plan is NULL");
     Plan& P = plan->p;
     if (P.batch_owner) fail(FDM_ERR_STATE, "the plan belongs to a batch");
-    const auto cand = candidates(false, P.tune.p2p_in_queue, P.tune.compact);
+    const auto cand = candidates(false, P.tune.p2p_in_queue, P.tune.compact,
+                                 compact_supported(P.prec, 64) && !P.aca_kp);
     if (max_candidates < 1 || max_candidates > static_cast<int>(cand.size()))
       fail(FDM_ERR_INVALID_ARG, "max_candidates out of range");
     if (P.nS) check_device_ptr(v, "v");
@@ -301,7 +317,8 @@ int fdm_batch_autotune(fdm_batch* batch, const void* const* v, void* const* y, i
   return guarded([&] {
     if (!batch) fail(FDM_ERR_INVALID_ARG, "batch is NULL");
     fdm_batch& b = *batch;
-    const auto cand = candidates(true, b.aca_kp ? 0 : 1, b.tune.compact);
+    const auto cand = candidates(true, b.aca_kp ? 0 : 1, b.tune.compact,
+                                 compact_supported(b.prec, 64) && !b.aca_kp);
     if (max_candidates < 1 || max_candidates > static_cast<int>(cand.size()))
       fail(FDM_ERR_INVALID_ARG, "max_candidates out of range");
     check_vectors(b, v, y, c64);

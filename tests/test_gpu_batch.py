@@ -291,6 +291,14 @@ def test_autotune_plan_and_batch():
     y2 = plan.matvec(to_dev(P.v))
     torch.cuda.synchronize()
     assert_close(y2.cpu().numpy(), yo, TOL_FP32)
+    # the two other compaction modes as candidates 9 and 10
+    best, ms, y = plan.autotune(to_dev(P.v), max_candidates=10)
+    torch.cuda.synchronize()
+    assert len(ms) == 10 and all(t > 0 for t in ms)
+    assert best == plan.get_tune()
+    y3 = plan.matvec(to_dev(P.v))
+    torch.cuda.synchronize()
+    assert_close(y3.cpu().numpy(), yo, TOL_FP32)
     plan.close()
 
     probs = small_batch(count=4, seed=48)
@@ -302,6 +310,13 @@ def test_autotune_plan_and_batch():
         assert len(ms) == 4 and all(t > 0 for t in ms)
         assert best == b.get_tune() and best["persistent"] == 1
         _batch_check(probs, ys, TOL_FP32, True)
+        ys = b.matvec(vs)
+        torch.cuda.synchronize()
+        _batch_check(probs, ys, TOL_FP32, True)
+        best, ms, ys = b.autotune(vs, max_candidates=6)
+        torch.cuda.synchronize()
+        assert len(ms) == 6 and all(t > 0 for t in ms)
+        assert best == b.get_tune()
         ys = b.matvec(vs)
         torch.cuda.synchronize()
         _batch_check(probs, ys, TOL_FP32, True)
